@@ -1,0 +1,27 @@
+"""CPU FP64 oracle for the IgA-SGBEM Galerkin matrix of the 2D Laplace
+single-layer operator (Aimi, Calabro, Diligenti, Sampoli, Sangalli, Sestini,
+"Efficient assembly based on B-spline tailored quadrature rules for the
+IgA-SGBEM").
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and
+``bench.py``'s ``cpu_baseline`` leg may import, call, link or execute anything
+under ``oracle/``.  It shares no code with the HIP path (no kernels, headers,
+helpers or table generators) and imports nothing from it.
+
+Parts:
+
+* ``bspline``, ``curves``: periodic B-spline bases (Cox-de Boor recurrence,
+  Section 4.2) and curve evaluation f, f', J (Section 3, eq. J).
+* ``circle`` (O1): closed forms on the exact circle (Fourier series of the log
+  kernel), used to pin the element-by-element oracle.
+* ``ebe`` + ``ebe_oracle.c`` (O2): plain element-by-element assembly, eq.
+  elbyelint (Section 5, Remark): tensor Gauss-Legendre on far element pairs,
+  regular part Gauss + analytic log part on coincident / adjacent pairs.
+* ``nearfield``: reference matrices of the analytic log part, computed in
+  50-digit arithmetic from the closed-form base integral of Section 4.2.
+* ``wq`` (O3): the weighted-quadrature rules (Alg. 1, Alg. 2, modified moments)
+  and the row assembly of eqs. IK1e2 / IK1e2_bis with dense linear algebra.
+* ``solve``: dense FP64 solve of A alpha = beta (eq. sistlin).
+
+Every function is FP64 and written for readability, not speed.
+"""

@@ -1,0 +1,144 @@
+"""Seeded synthetic inputs for the IgA-SGBEM Galerkin assembly.
+
+This module only *describes* problem instances: curve descriptions (control
+points or polar Fourier coefficients), discretisation parameters and
+Dirichlet data functions.  It holds none of the method's arithmetic (no
+B-spline evaluation, no quadrature, no kernel), so that both the HIP path and
+the CPU oracle can take their inputs from here without sharing any code.
+
+Workloads (the paper's own test curves are an open parabola and an S-shape
+whose control points only exist in a missing figure, Section 6, so these
+synthetic closed curves stand in for them):
+
+* ``circle``: x(t) = r (cos 2 pi t, sin 2 pi t), the closed-form check case.
+* ``ellipse_bspline``: semi-axes (1, 0.5) as a closed uniform cubic B-spline
+  of 32 control points interpolating the ellipse at the knots.  A closed
+  curve is a periodic B-spline whose last d control points repeat the first
+  ones (Section 3); here the periodic repetition is implicit.
+* ``star``: r(theta) = 1 + sum_{k=1..6} a_k cos(k theta + phi_k) with
+  a_k ~ U(0, 0.1/k), phi_k ~ U(0, 2 pi), drawn from numpy's PCG64 seeded
+  with ``[1703, idx]``.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import Callable, List, Tuple
+
+import numpy as np
+
+__all__ = [
+    "PolarCurve", "BSplineCurve", "circle", "ellipse_bspline", "star",
+    "g_x2_minus_y2", "g_exp_cos", "Problem", "config_circle", "config_ellipse",
+    "config_stars", "config_batch", "config_serving",
+]
+
+
+@dataclass(frozen=True)
+class PolarCurve:
+    """r(theta) = r0 * (1 + sum_k a[k-1] cos(k theta + phi[k-1])), theta = 2 pi t,
+    traversed counter-clockwise for t in [0, 1)."""
+    r0: float
+    a: np.ndarray = field(default_factory=lambda: np.zeros(0))
+    phi: np.ndarray = field(default_factory=lambda: np.zeros(0))
+    kind: str = "polar"
+
+
+@dataclass(frozen=True)
+class BSplineCurve:
+    """Closed curve f(t) = sum_j ctrl[j] B_j(t) with periodic uniform knots on
+    n_ctrl elements of [0, 1); B_j is supported on [j/n, (j+degree+1)/n) mod 1.
+    ``ctrl`` has shape (n_ctrl, 2); the first ``degree`` points are not repeated."""
+    degree: int
+    ctrl: np.ndarray
+    kind: str = "bspline"
+
+
+def circle(r: float = 0.5) -> PolarCurve:
+    return PolarCurve(r0=float(r))
+
+
+def ellipse_bspline(a: float = 1.0, b: float = 0.5, n_ctrl: int = 32) -> BSplineCurve:
+    """Closed uniform cubic B-spline interpolating the ellipse (a cos th, b sin th)
+    at its n_ctrl knots.  B_j peaks at the knot (j+2)/n; (cos th, sin th) are
+    single Fourier modes, so the control polygon is the ellipse scaled by
+    3 / (2 + cos(2 pi / n)) (the cubic's knot values are 1/6, 2/3, 1/6)."""
+    th = 2.0 * math.pi * (np.arange(n_ctrl) + 2) / n_ctrl
+    scale = 3.0 / (2.0 + math.cos(2.0 * math.pi / n_ctrl))
+    ctrl = scale * np.stack([a * np.cos(th), b * np.sin(th)], axis=1)
+    return BSplineCurve(degree=3, ctrl=np.ascontiguousarray(ctrl))
+
+
+def star(idx: int, n_modes: int = 6) -> PolarCurve:
+    rng = np.random.default_rng([1703, int(idx)])
+    k = np.arange(1, n_modes + 1)
+    a = rng.uniform(0.0, 0.1 / k)
+    phi = rng.uniform(0.0, 2.0 * math.pi, size=n_modes)
+    return PolarCurve(r0=1.0, a=a, phi=phi)
+
+
+# Dirichlet data: harmonic functions of the physical point (x1, x2).
+def g_x2_minus_y2(x1, x2):
+    return x1 * x1 - x2 * x2
+
+
+def g_exp_cos(x1, x2):
+    return np.exp(x1) * np.cos(x2)
+
+
+@dataclass(frozen=True)
+class Problem:
+    name: str
+    curve: object
+    p: int
+    N: int
+    g: Callable
+    g_name: str
+
+
+def config_circle() -> Problem:
+    """Circle r = 0.5, p = 2, N = 64, g = x1^2 - x2^2."""
+    return Problem("circle_r0.5_p2_N64", circle(0.5), 2, 64, g_x2_minus_y2, "x1^2-x2^2")
+
+
+def config_ellipse() -> Problem:
+    """Ellipse (1, 0.5) as a 32-point closed cubic B-spline, p = 3, N = 1024."""
+    return Problem("ellipse_bspline32_p3_N1024", ellipse_bspline(), 3, 1024, g_exp_cos, "exp(x1)cos(x2)")
+
+
+def config_stars(n_per: int = 8) -> List[Problem]:
+    """Stars for p in {2,3,4} x N in {4096, 16384}, n_per curves each."""
+    out = []
+    idx = 0
+    for p in (2, 3, 4):
+        for N in (4096, 16384):
+            for _ in range(n_per):
+                out.append(Problem(f"star{idx}_p{p}_N{N}", star(idx), p, N, g_exp_cos, "exp(x1)cos(x2)"))
+                idx += 1
+    return out
+
+
+def config_batch(n: int = 256) -> List[Problem]:
+    """n stars with N ~ U{128..2048}, p in {2,3}: seeds [1703, 10000 + idx]."""
+    out = []
+    for idx in range(n):
+        rng = np.random.default_rng([1703, 10000 + idx])
+        N = int(rng.integers(128, 2049))
+        p = int(rng.choice([2, 3]))
+        out.append(Problem(f"batch{idx}_p{p}_N{N}", star(10000 + idx), p, N, g_exp_cos, "exp(x1)cos(x2)"))
+    return out
+
+
+def config_serving(rate: float, n: int = 2000, n_min: int = 256, n_max: int = 8192
+                   ) -> Tuple[np.ndarray, List[Problem]]:
+    """Poisson arrivals at ``rate`` req/s: exponential inter-arrival times and
+    log-uniform N in [n_min, n_max], p in {2,3,4}; seed [1703, 20000 + rate]."""
+    rng = np.random.default_rng([1703, 20000 + int(round(rate))])
+    gaps = rng.exponential(1.0 / rate, size=n)
+    arrivals = np.cumsum(gaps)
+    probs = []
+    for idx in range(n):
+        N = int(round(math.exp(rng.uniform(math.log(n_min), math.log(n_max)))))
+        p = int(rng.choice([2, 3, 4]))
+        probs.append(Problem(f"req{idx}_p{p}_N{N}", star(30000 + idx), p, N, g_exp_cos, "exp(x1)cos(x2)"))
+    return arrivals, probs
