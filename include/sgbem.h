@@ -1,0 +1,215 @@
+/*
+ * sgbem.h -- C ABI of libsgbem: Galerkin assembly of the 2D Laplace
+ * single-layer operator with periodic B-splines on a closed curve, by
+ * B-spline weighted quadrature with row assembly and sum factorisation (the
+ * fast form) or element by element with Gauss rules (the plain form), plus
+ * the right-hand side and a mixed-precision dense solve, on one AMD Instinct
+ * MI355X (gfx950).
+ *
+ * Method: Aimi, Calabro, Diligenti, Sampoli, Sangalli, Sestini, "Efficient
+ * assembly based on B-spline tailored quadrature rules for the IgA-SGBEM".
+ *
+ * Problem (Section 2, eq. prima_BIE in indirect form on a closed curve):
+ *   find phi_h = sum_j alpha_j B_j with
+ *   A alpha = beta,  A_ij = -(1/2pi) int int B_i(s) J(s) ln|f(s)-f(t)| B_j(t) J(t) dt ds
+ *   (eqs. Gmatrix, final_1),  beta_i = int B_i(s) J(s) g(f(s)) ds (eq. final_b1),
+ * with B_i the cyclic B-splines of degree p on N uniform elements of the
+ * parameter interval [0, 1) (Section 3), f the curve and J = |f'| (eq. J).
+ *
+ * Conventions for every call:
+ *  - every function returns an sgbem_status; no C++ exception crosses the ABI;
+ *    on failure sgbem_last_error() returns a message (thread-local, never NULL);
+ *  - "device" pointers are HIP device memory owned by the caller (e.g. a
+ *    torch tensor's data_ptr); "host" pointers are ordinary host memory owned
+ *    by the caller and only read during the call;
+ *  - work is enqueued on the context's stream and is asynchronous unless
+ *    stated otherwise; a context must be used from one host thread at a time;
+ *  - matrices are row-major: entry (i, j) at ptr[i * lda + j], lda >= N;
+ *  - basis index convention: B_i is supported on [i/N, (i+p+1)/N) mod 1.
+ */
+#ifndef SGBEM_H
+#define SGBEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SGBEM_OK = 0,
+    SGBEM_E_INVAL = -1,        /* an argument is out of range or inconsistent          */
+    SGBEM_E_NOMEM = -2,        /* device or host allocation failed / budget exceeded   */
+    SGBEM_E_SINGULAR = -3,     /* zero pivot in the LU factorisation                   */
+    SGBEM_E_NOCONV = -4,       /* iterative refinement did not reach the tolerance     */
+    SGBEM_E_DEVICE = -5,       /* a HIP runtime call failed                            */
+    SGBEM_E_UNSUPPORTED = -6   /* valid request outside what this build implements     */
+} sgbem_status;
+
+typedef struct sgbem_ctx_s *sgbem_ctx;       /* one device + one HIP stream             */
+typedef struct sgbem_rules_s *sgbem_rules;   /* device-resident quadrature rules (p,N,R) */
+
+typedef enum { SGBEM_CURVE_BSPLINE = 0, SGBEM_CURVE_POLAR = 1 } sgbem_curve_kind;
+typedef enum { SGBEM_WQ = 0, SGBEM_EBE = 1 } sgbem_method;
+typedef enum { SGBEM_FP64 = 0, SGBEM_FP32 = 1 } sgbem_precision;
+
+/*
+ * Closed curve f : [0, 1) -> R^2 (Section 3).  Host memory, copied by the
+ * library at each call that takes it.
+ *  BSPLINE: f(t) = sum_j ctrl[j] M_d(n t - j mod n) with periodic uniform knots
+ *           (the closed-curve representation of Section 3, whose last d control
+ *           points repeat the first ones; here they are not repeated):
+ *           degree d in [1, 7], n_ctrl > d, ctrl_xy = [n_ctrl][2].
+ *  POLAR:   f(t) = r(theta) (cos theta, sin theta), theta = 2 pi t,
+ *           r(theta) = r0 (1 + sum_{k=1..n_modes} a[k-1] cos(k theta + phi[k-1])),
+ *           r0 > 0, 0 <= n_modes <= 64, r must stay positive.
+ * Unused fields are ignored.
+ */
+typedef struct {
+    int32_t kind;
+    int32_t degree;
+    int32_t n_ctrl;
+    const double *ctrl_xy;
+    double r0;
+    int32_t n_modes;
+    const double *a;
+    const double *phi;
+} sgbem_curve;
+
+typedef struct {
+    int32_t iters;          /* refinement steps taken                                  */
+    int32_t status;         /* same value as the call's return                          */
+    double rel_update;      /* ||dx||_inf / ||x||_inf of the last refinement step       */
+    double backward_err;    /* ||beta - A x||_inf / (||A||_inf ||x||_inf + ||beta||_inf) */
+} sgbem_solve_info;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device`; `hip_stream` is a hipStream_t (NULL:
+ * the null stream).  Allocates nothing on the device until first use.
+ * Errors: E_INVAL (bad device), E_DEVICE. */
+sgbem_status sgbem_ctx_create(int32_t device, void *hip_stream, sgbem_ctx *out);
+
+/* Synchronise the stream, free every device buffer the context owns. */
+sgbem_status sgbem_ctx_destroy(sgbem_ctx ctx);
+
+/* Switch the stream used by later calls (the previous stream is synchronised). */
+sgbem_status sgbem_ctx_set_stream(sgbem_ctx ctx, void *hip_stream);
+
+/* Message of the last failing call on this host thread. */
+const char *sgbem_last_error(void);
+
+/* Library build string (architecture, build flags). */
+const char *sgbem_version(void);
+
+/* ---------------------------------------------------------------- rules */
+
+/*
+ * Build the quadrature rules of Section 4 for degree p, N elements and
+ * refinement n_ref (the exactness space: cyclic B-splines of degree p on
+ * M = n_ref N elements), and upload them to the device.  Synchronous.
+ *  - nodes (Section 4): all breakpoints and midpoints of the refined mesh,
+ *    eta_n = n / (2M), n = 0..2M-1;
+ *  - regular rules (Alg. 1, eq. reg_exactness): minimum-norm weights on the
+ *    2 n_ref (p+1) - 1 nodes inside supp B_i, exact for every Bbar_k meeting it;
+ *  - singular rules (Alg. 2, eqs. sing_exactness, mod_mom_gen): for each source
+ *    eta_m, minimum-norm weights on all nodes exact for int Bbar_k(t) K2(eta_m,t) dt,
+ *    K2(s,t) = ln|sin(pi (s-t)) / pi| (the kernel split of Section 3.1 made
+ *    periodic), modified moments from the closed forms of Section 4.2.
+ *    With uniform periodic knots the weights depend only on (m mod 2, n - m mod 2M),
+ *    so two tables of length 2M are kept.
+ * Limits: p in [1, 6], n_ref in [1, 4], N >= 2 (p + 1), 2 n_ref N <= 2^24.
+ * Errors: E_INVAL, E_NOMEM, E_DEVICE, E_SINGULAR (rank-deficient collocation).
+ * The handle is freed with sgbem_rules_free (or with its context).
+ */
+sgbem_status sgbem_weights(sgbem_ctx ctx, int32_t p, int32_t N, int32_t n_ref, sgbem_rules *out);
+
+sgbem_status sgbem_rules_free(sgbem_ctx ctx, sgbem_rules rules);
+
+/* Host-only view of the same rules, without any device (for inspection):
+ *  w0[Q]       regular weights of B_0 on nodes n = 1..Q, Q = 2 n_ref (p+1) - 1
+ *              (B_i uses the same weights on nodes 2 n_ref i + 1 + q);
+ *  bvals[Q]    B_0(eta_n) on the same nodes;
+ *  ws[2][2M]   singular weights: w_n^(eta_m) = ws[m mod 2][(n - m) mod 2M].
+ * Any output pointer may be NULL.  Errors: E_INVAL, E_NOMEM, E_SINGULAR. */
+sgbem_status sgbem_weights_host(int32_t p, int32_t N, int32_t n_ref,
+                                double *w0, double *bvals, double *ws);
+
+/* Host-only reference matrices of the element-by-element near-pair rule
+ * (Section 5, Remark): on unit elements with the 16 Gauss-Legendre points u_a
+ * and Lagrange polynomials l_a, mco[a][b] = int_0^1 int_0^1 l_a(u) l_b(v) ln|u - v|,
+ * madj[a][b] = int int l_a(u) l_b(v) ln(1 + v - u) (u left, v right element).
+ * Outputs are [16][16] (or NULL); u16, w16 are the Gauss nodes / weights. */
+sgbem_status sgbem_nearfield_host(double *u16, double *w16, double *mco, double *madj);
+
+/* ---------------------------------------------------------------- assembly */
+
+/*
+ * Points where the Dirichlet datum g must be sampled for sgbem_rhs, written
+ * to device memory d_xy as [count][2] FP64 (x, y):
+ *   WQ:  f(eta_n), n = 0..2M-1                                   (count = 2M)
+ *   EBE: f((e + u_g) / N), e = 0..N-1, g = 0..n_gauss-1 (G-point Gauss-Legendre
+ *        nodes on [0, 1])                                         (count = N n_gauss)
+ * `cap` is the capacity of d_xy in points; *count receives the count (also
+ * when cap is too small, then E_INVAL).  Asynchronous.
+ */
+sgbem_status sgbem_rhs_points(sgbem_ctx ctx, const sgbem_curve *curve, sgbem_rules rules,
+                              int32_t method, int32_t n_gauss,
+                              double *d_xy, int64_t cap, int64_t *count);
+
+/*
+ * Assemble the N x N Galerkin matrix into device memory d_A (row-major, lda,
+ * FP64 `double` or FP32 `float` as `precision` says).  Asynchronous.
+ *  WQ (fast form): eqs. IK1e2 and IK1e2_bis by row assembly and sum
+ *      factorisation (Alg. 3), the singular rule used for every pair as the paper
+ *      does; K1 on the node grid with K1(s, s) = ln J(s) (eq. F1_lim).  The row of
+ *      eq. IK1e2_bis is not exactly symmetric: rows i <= j are computed and
+ *      mirrored, so d_A is exactly symmetric.
+ *  EBE (plain form): eq. elbyelint; far element pairs by n_gauss x n_gauss
+ *      Gauss-Legendre, coincident / adjacent pairs (the wrap pair included) by the
+ *      kernel split: regular part with 16 x 16 Gauss, ln|s - t| part integrated
+ *      exactly after interpolating B J at 16 Gauss points per element.
+ * FP32: kernel values, products and sums in FP32 (node coordinates are
+ *      differenced in FP64); the rule tables stay FP64 until rounded once.
+ * Limits: n_gauss in [1, 8] for EBE (ignored by WQ).
+ * Errors: E_INVAL, E_UNSUPPORTED (a (p, n_ref) or (p, n_gauss) pair without a
+ *      compiled kernel), E_NOMEM, E_DEVICE.
+ */
+sgbem_status sgbem_assemble(sgbem_ctx ctx, const sgbem_curve *curve, sgbem_rules rules,
+                            int32_t method, int32_t n_gauss, int32_t precision,
+                            void *d_A, int64_t lda);
+
+/*
+ * Right-hand side beta_i = int B_i J g(f) ds (eq. final_b1), FP64:
+ *  WQ:  sum_n w_n^(i) J(eta_n) g_n (Section 5);   EBE: G-point Gauss per element.
+ * d_g: device [count] FP64 samples of g at the sgbem_rhs_points of the same
+ * method / n_gauss; d_beta: device [N] FP64.  Asynchronous.  Errors: E_INVAL.
+ */
+sgbem_status sgbem_rhs(sgbem_ctx ctx, const sgbem_curve *curve, sgbem_rules rules,
+                       int32_t method, int32_t n_gauss, const double *d_g, double *d_beta);
+
+/* ---------------------------------------------------------------- solve */
+
+/*
+ * Solve A x = beta (eq. sistlin) for one N x N matrix on the device.
+ * A is LU-factorised with partial pivoting in FP32 (the matrix is symmetric
+ * but indefinite when the curve's logarithmic capacity exceeds 1, so neither
+ * Cholesky nor the paper's positive-definiteness is assumed); x is then
+ * refined in FP64: r = beta - A x with A as stored (FP64 or FP32 widened),
+ * d = LU \ r in FP32, x += d, until ||d||_inf <= tol ||x||_inf or max_iter steps.
+ *  d_A:     device, row-major, lda, FP64 or FP32 per a_prec; not modified.
+ *  d_beta:  device [N] FP64.    d_x: device [N] FP64 (output).
+ *  info:    host, may be NULL; written before return (the call synchronises).
+ * Workspace (4 N^2 + O(N) bytes) is allocated in the context and kept.
+ * Errors: E_INVAL, E_NOMEM, E_SINGULAR (zero pivot), E_NOCONV (x holds the
+ *      last iterate), E_DEVICE.
+ */
+sgbem_status sgbem_solve(sgbem_ctx ctx, int32_t N, const void *d_A, int64_t lda, int32_t a_prec,
+                         const double *d_beta, double *d_x, double tol, int32_t max_iter,
+                         sgbem_solve_info *info);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SGBEM_H */

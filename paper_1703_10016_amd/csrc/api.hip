@@ -1,0 +1,549 @@
+// C ABI of libsgbem (declared in include/sgbem.h): contexts, rule handles,
+// argument validation and the launch sequence of each entry point.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/sgbem.h"
+#include "kernels.hpp"
+#include "planner.hpp"
+#include "solve.hpp"
+
+namespace sgbem {
+hipError_t launch_wq_f64(int p, int P, const TileArgs &a, hipStream_t s);
+hipError_t launch_wq_f32(int p, int P, const TileArgs &a, hipStream_t s);
+hipError_t launch_ebe_f64(int p, int P, const TileArgs &a, hipStream_t s);
+hipError_t launch_ebe_f32(int p, int P, const TileArgs &a, hipStream_t s);
+
+hipError_t launch_assemble(int method, int prec, int p, int P, const TileArgs &a, hipStream_t s)
+{
+    if (method == 0) return prec == 0 ? launch_wq_f64(p, P, a, s) : launch_wq_f32(p, P, a, s);
+    return prec == 0 ? launch_ebe_f64(p, P, a, s) : launch_ebe_f32(p, P, a, s);
+}
+bool assemble_supported(int method, int, int p, int P)
+{
+    if (p < 1 || p > 6) return false;
+    if (method == 0) return P == 2 || P == 4 || P == 6 || P == 8;
+    return P >= 1 && P <= 8;
+}
+}  // namespace sgbem
+
+using namespace sgbem;
+
+namespace {
+thread_local std::string g_err;
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+sgbem_status set_err(sgbem_status st, const std::string &m)
+{
+    g_err = m;
+    return st;
+}
+
+#define HIPCHK(call)                                                                       \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return set_err(e_ == hipErrorOutOfMemory ? SGBEM_E_NOMEM : SGBEM_E_DEVICE,     \
+                           std::string(#call) + ": " + hipGetErrorString(e_));             \
+    } while (0)
+
+// Grow-only device buffer owned by a context.
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+}  // namespace
+
+struct sgbem_rules_s {
+    int p = 0, N = 0, R = 0, Q = 0;
+    int64_t M = 0, npts = 0;
+    std::vector<double> w0, bvals;
+    double *d_inv_s2 = nullptr, *d_ws = nullptr, *d_w0 = nullptr;
+    float *d_inv_s2f = nullptr, *d_wsf = nullptr;
+};
+
+struct sgbem_ctx_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    DevBuf geo, geo16, nearL, params, solve_ws;
+    std::vector<sgbem_rules_s *> rules;
+    // geometry-independent element-by-element tables, uploaded once per key:
+    // key p      -> u16, w16, mco, madj, M_p(a + u16)       (near pairs)
+    // key 1000 + 64p + G -> RHS coefficients w_g M_p(a + u_g) without h
+    std::map<int, double *> tables;
+};
+
+namespace {
+
+sgbem_status ensure(sgbem_ctx c, DevBuf &b, size_t bytes)
+{
+    if (b.bytes >= bytes) return SGBEM_OK;
+    if (b.ptr) {
+        HIPCHK(hipStreamSynchronize(c->stream));
+        HIPCHK(hipFree(b.ptr));
+        b.ptr = nullptr;
+        b.bytes = 0;
+    }
+    size_t nb = bytes < 4096 ? 4096 : bytes;
+    nb = (nb + 4095) & ~size_t(4095);
+    HIPCHK(hipMalloc(&b.ptr, nb));
+    b.bytes = nb;
+    return SGBEM_OK;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+void free_rules(sgbem_rules r)
+{
+    if (!r) return;
+    (void)hipFree(r->d_inv_s2);
+    (void)hipFree(r->d_ws);
+    (void)hipFree(r->d_w0);
+    (void)hipFree(r->d_inv_s2f);
+    (void)hipFree(r->d_wsf);
+    delete r;
+}
+
+sgbem_status check_curve(const sgbem_curve *c)
+{
+    if (!c) return set_err(SGBEM_E_INVAL, "curve is NULL");
+    if (c->kind == SGBEM_CURVE_BSPLINE) {
+        if (c->degree < 1 || c->degree > 7) return set_err(SGBEM_E_INVAL, "B-spline curve degree must be in [1, 7]");
+        if (c->n_ctrl <= c->degree) return set_err(SGBEM_E_INVAL, "B-spline curve needs n_ctrl > degree");
+        if (!c->ctrl_xy) return set_err(SGBEM_E_INVAL, "B-spline curve without control points");
+    } else if (c->kind == SGBEM_CURVE_POLAR) {
+        if (!(c->r0 > 0.0)) return set_err(SGBEM_E_INVAL, "polar curve needs r0 > 0");
+        if (c->n_modes < 0 || c->n_modes > 64) return set_err(SGBEM_E_INVAL, "polar curve n_modes must be in [0, 64]");
+        if (c->n_modes > 0 && (!c->a || !c->phi)) return set_err(SGBEM_E_INVAL, "polar curve modes missing");
+        double amp = 0.0;
+        for (int k = 0; k < c->n_modes; ++k) amp += std::fabs(c->a[k]);
+        if (!(amp < 1.0)) return set_err(SGBEM_E_INVAL, "polar curve: sum |a_k| must be < 1 so that r > 0");
+    } else {
+        return set_err(SGBEM_E_INVAL, "unknown curve kind");
+    }
+    return SGBEM_OK;
+}
+
+// Upload the curve's arrays and return the device description.
+sgbem_status upload_curve(sgbem_ctx c, const sgbem_curve *cv, CurveDev &d)
+{
+    sgbem_status st = check_curve(cv);
+    if (st) return st;
+    std::memset(&d, 0, sizeof d);
+    d.kind = cv->kind;
+    if (cv->kind == SGBEM_CURVE_BSPLINE) {
+        d.degree = cv->degree;
+        d.n_ctrl = cv->n_ctrl;
+        const size_t bytes = size_t(cv->n_ctrl) * 2 * sizeof(double);
+        if ((st = ensure(c, c->params, bytes))) return st;
+        HIPCHK(hipMemcpyAsync(c->params.ptr, cv->ctrl_xy, bytes, hipMemcpyHostToDevice, c->stream));
+        d.ctrl = static_cast<const double *>(c->params.ptr);
+    } else {
+        d.r0 = cv->r0;
+        d.n_modes = cv->n_modes;
+        const size_t bytes = size_t(2 * cv->n_modes + 1) * sizeof(double);
+        if ((st = ensure(c, c->params, bytes))) return st;
+        double *base = static_cast<double *>(c->params.ptr);
+        if (cv->n_modes > 0) {
+            HIPCHK(hipMemcpyAsync(base, cv->a, cv->n_modes * sizeof(double), hipMemcpyHostToDevice, c->stream));
+            HIPCHK(hipMemcpyAsync(base + cv->n_modes, cv->phi, cv->n_modes * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        }
+        d.a = base;
+        d.phi = base + cv->n_modes;
+    }
+    return SGBEM_OK;
+}
+
+sgbem_status geometry(sgbem_ctx c, const CurveDev &cd, const GridDesc &g, DevBuf &buf, double *&X, double *&Y, double *&J)
+{
+    sgbem_status st = ensure(c, buf, size_t(g.npts) * 3 * sizeof(double));
+    if (st) return st;
+    X = static_cast<double *>(buf.ptr);
+    Y = X + g.npts;
+    J = Y + g.npts;
+    HIPCHK(launch_geometry(cd, g, X, Y, J, c->stream));
+    return SGBEM_OK;
+}
+
+GridDesc wq_grid(sgbem_rules r)
+{
+    GridDesc g{};
+    g.N = r->N;
+    g.P = 0;
+    g.npts = int(r->npts);
+    return g;
+}
+
+GridDesc gauss_grid(int N, int G)
+{
+    GridDesc g{};
+    g.N = N;
+    g.P = G;
+    g.npts = N * G;
+    double w[32];
+    gauss_legendre01(G, g.off, w);
+    return g;
+}
+
+// Device copy of a host table, made once per key and kept by the context
+// (a synchronous upload the first time a key is used).
+sgbem_status cached_table(sgbem_ctx c, int key, const std::vector<double> &host, const double *&dev)
+{
+    auto it = c->tables.find(key);
+    if (it != c->tables.end()) {
+        dev = it->second;
+        return SGBEM_OK;
+    }
+    double *d = nullptr;
+    HIPCHK(hipMalloc(&d, host.size() * sizeof(double)));
+    hipError_t e = hipMemcpy(d, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(d);
+        return set_err(SGBEM_E_DEVICE, std::string("table upload: ") + hipGetErrorString(e));
+    }
+    c->tables[key] = d;
+    dev = d;
+    return SGBEM_OK;
+}
+
+std::vector<double> near_table(int p)
+{
+    const std::vector<double> pcs = cardinal_pieces(p);
+    const NearField &nf = nearfield16();
+    std::vector<double> tab(544 + size_t(p + 1) * 16);
+    std::memcpy(&tab[0], nf.u, 16 * sizeof(double));
+    std::memcpy(&tab[16], nf.w, 16 * sizeof(double));
+    std::memcpy(&tab[32], nf.mco, 256 * sizeof(double));
+    std::memcpy(&tab[288], nf.madj, 256 * sizeof(double));
+    for (int a = 0; a <= p; ++a)
+        for (int q = 0; q < 16; ++q) tab[544 + a * 16 + q] = cardinal_eval(p, pcs, a + nf.u[q]);
+    return tab;
+}
+
+// w_g M_p(a + u_g) for a = 0..p, g = 0..G-1 (index a G + g).
+std::vector<double> gauss_basis_coef(int p, int G)
+{
+    const std::vector<double> pcs = cardinal_pieces(p);
+    double gx[32], gw[32];
+    gauss_legendre01(G, gx, gw);
+    std::vector<double> coef(size_t(G) * (p + 1));
+    for (int a = 0; a <= p; ++a)
+        for (int q = 0; q < G; ++q) coef[a * G + q] = gw[q] * cardinal_eval(p, pcs, a + gx[q]);
+    return coef;
+}
+
+bool valid_rules(sgbem_ctx c, sgbem_rules r)
+{
+    for (auto *x : c->rules)
+        if (x == r) return true;
+    return false;
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+extern "C" {
+
+const char *sgbem_last_error(void) { return g_err.c_str(); }
+
+const char *sgbem_version(void)
+{
+    return "libsgbem 1.0 (gfx950)";
+}
+
+sgbem_status sgbem_ctx_create(int32_t device, void *hip_stream, sgbem_ctx *out)
+{
+    if (!out) return set_err(SGBEM_E_INVAL, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    HIPCHK(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) return set_err(SGBEM_E_INVAL, "no such HIP device");
+    auto *c = new (std::nothrow) sgbem_ctx_s;
+    if (!c) return set_err(SGBEM_E_NOMEM, "host allocation failed");
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    *out = c;
+    return SGBEM_OK;
+}
+
+sgbem_status sgbem_ctx_set_stream(sgbem_ctx c, void *hip_stream)
+{
+    if (!c) return set_err(SGBEM_E_INVAL, "ctx is NULL");
+    DeviceGuard g(c->device);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    return SGBEM_OK;
+}
+
+sgbem_status sgbem_ctx_destroy(sgbem_ctx c)
+{
+    if (!c) return SGBEM_OK;
+    DeviceGuard g(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    for (DevBuf *b : {&c->geo, &c->geo16, &c->nearL, &c->params, &c->solve_ws})
+        if (b->ptr) (void)hipFree(b->ptr);
+    for (auto &kv : c->tables) (void)hipFree(kv.second);
+    for (auto *r : c->rules) free_rules(r);
+    delete c;
+    return SGBEM_OK;
+}
+
+sgbem_status sgbem_weights_host(int32_t p, int32_t N, int32_t n_ref, double *w0, double *bvals, double *ws)
+{
+    try {
+        WQRules W = build_wq_rules(p, N, n_ref);
+        if (w0) std::memcpy(w0, W.w0.data(), W.w0.size() * sizeof(double));
+        if (bvals) std::memcpy(bvals, W.bvals.data(), W.bvals.size() * sizeof(double));
+        if (ws) std::memcpy(ws, W.ws.data(), W.ws.size() * sizeof(double));
+    } catch (const PlanError &e) {
+        return set_err(sgbem_status(e.status), e.msg);
+    } catch (const std::bad_alloc &) {
+        return set_err(SGBEM_E_NOMEM, "host allocation failed");
+    }
+    return SGBEM_OK;
+}
+
+sgbem_status sgbem_nearfield_host(double *u16, double *w16, double *mco, double *madj)
+{
+    const NearField &nf = nearfield16();
+    if (u16) std::memcpy(u16, nf.u, sizeof nf.u);
+    if (w16) std::memcpy(w16, nf.w, sizeof nf.w);
+    if (mco) std::memcpy(mco, nf.mco, sizeof nf.mco);
+    if (madj) std::memcpy(madj, nf.madj, sizeof nf.madj);
+    return SGBEM_OK;
+}
+
+sgbem_status sgbem_weights(sgbem_ctx c, int32_t p, int32_t N, int32_t n_ref, sgbem_rules *out)
+{
+    if (!c || !out) return set_err(SGBEM_E_INVAL, "ctx or out is NULL");
+    *out = nullptr;
+    DeviceGuard g(c->device);
+    WQRules W;
+    try {
+        W = build_wq_rules(p, N, n_ref);
+    } catch (const PlanError &e) {
+        return set_err(sgbem_status(e.status), e.msg);
+    } catch (const std::bad_alloc &) {
+        return set_err(SGBEM_E_NOMEM, "host allocation failed");
+    }
+    auto *r = new (std::nothrow) sgbem_rules_s;
+    if (!r) return set_err(SGBEM_E_NOMEM, "host allocation failed");
+    r->p = p;
+    r->N = N;
+    r->R = n_ref;
+    r->Q = W.Q;
+    r->M = W.M;
+    r->npts = W.n_nodes;
+    r->w0 = W.w0;
+    r->bvals = W.bvals;
+    const size_t n = size_t(W.n_nodes);
+    std::vector<float> f_inv(n), f_ws(2 * n);
+    for (size_t i = 0; i < n; ++i) f_inv[i] = float(W.inv_s2[i]);
+    for (size_t i = 0; i < 2 * n; ++i) f_ws[i] = float(W.ws[i]);
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = hipMalloc(&r->d_inv_s2, n * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&r->d_ws, 2 * n * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&r->d_w0, 64 * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&r->d_inv_s2f, n * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&r->d_wsf, 2 * n * sizeof(float));
+    if (e == hipSuccess) e = hipMemcpy(r->d_inv_s2, W.inv_s2.data(), n * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(r->d_ws, W.ws.data(), 2 * n * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(r->d_w0, W.w0.data(), W.w0.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(r->d_inv_s2f, f_inv.data(), n * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(r->d_wsf, f_ws.data(), 2 * n * sizeof(float), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        free_rules(r);
+        return set_err(e == hipErrorOutOfMemory ? SGBEM_E_NOMEM : SGBEM_E_DEVICE,
+                       std::string("uploading rules: ") + hipGetErrorString(e));
+    }
+    c->rules.push_back(r);
+    *out = r;
+    return SGBEM_OK;
+}
+
+sgbem_status sgbem_rules_free(sgbem_ctx c, sgbem_rules r)
+{
+    if (!c) return set_err(SGBEM_E_INVAL, "ctx is NULL");
+    if (!r) return SGBEM_OK;
+    if (!valid_rules(c, r)) return set_err(SGBEM_E_INVAL, "rules handle does not belong to this context");
+    DeviceGuard g(c->device);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (size_t i = 0; i < c->rules.size(); ++i)
+        if (c->rules[i] == r) {
+            c->rules.erase(c->rules.begin() + i);
+            break;
+        }
+    free_rules(r);
+    return SGBEM_OK;
+}
+
+sgbem_status sgbem_rhs_points(sgbem_ctx c, const sgbem_curve *curve, sgbem_rules r, int32_t method, int32_t n_gauss,
+                              double *d_xy, int64_t cap, int64_t *count)
+{
+    if (!c || !r || !count) return set_err(SGBEM_E_INVAL, "NULL argument");
+    if (!valid_rules(c, r)) return set_err(SGBEM_E_INVAL, "rules handle does not belong to this context");
+    if (method != SGBEM_WQ && method != SGBEM_EBE) return set_err(SGBEM_E_INVAL, "unknown method");
+    if (method == SGBEM_EBE && (n_gauss < 1 || n_gauss > 8)) return set_err(SGBEM_E_INVAL, "n_gauss must be in [1, 8]");
+    DeviceGuard g(c->device);
+    const GridDesc grid = method == SGBEM_WQ ? wq_grid(r) : gauss_grid(r->N, n_gauss);
+    *count = grid.npts;
+    if (cap < grid.npts || !d_xy) return set_err(SGBEM_E_INVAL, "output capacity too small");
+    CurveDev cd;
+    sgbem_status st = upload_curve(c, curve, cd);
+    if (st) return st;
+    double *X, *Y, *J;
+    if ((st = geometry(c, cd, grid, c->geo, X, Y, J))) return st;
+    HIPCHK(launch_points_xy(X, Y, grid.npts, d_xy, c->stream));
+    return SGBEM_OK;
+}
+
+sgbem_status sgbem_assemble(sgbem_ctx c, const sgbem_curve *curve, sgbem_rules r, int32_t method, int32_t n_gauss,
+                            int32_t precision, void *d_A, int64_t lda)
+{
+    if (!c || !r || !d_A) return set_err(SGBEM_E_INVAL, "NULL argument");
+    if (!valid_rules(c, r)) return set_err(SGBEM_E_INVAL, "rules handle does not belong to this context");
+    if (method != SGBEM_WQ && method != SGBEM_EBE) return set_err(SGBEM_E_INVAL, "unknown method");
+    if (precision != SGBEM_FP64 && precision != SGBEM_FP32) return set_err(SGBEM_E_INVAL, "unknown precision");
+    if (lda < r->N) return set_err(SGBEM_E_INVAL, "lda < N");
+    if (method == SGBEM_EBE && (n_gauss < 1 || n_gauss > 8)) return set_err(SGBEM_E_INVAL, "n_gauss must be in [1, 8]");
+    const int p = r->p, N = r->N;
+    const int P = method == SGBEM_WQ ? 2 * r->R : n_gauss;
+    if (!assemble_supported(method, precision, p, P)) return set_err(SGBEM_E_UNSUPPORTED, "no kernel compiled for this (p, P)");
+    DeviceGuard g(c->device);
+    CurveDev cd;
+    sgbem_status st = upload_curve(c, curve, cd);
+    if (st) return st;
+
+    TileArgs ta;
+    std::memset(&ta, 0, sizeof ta);
+    ta.N = N;
+    ta.scale = -1.0 / (2.0 * kPi);
+    ta.out = d_A;
+    ta.lda = lda;
+    if (method == SGBEM_WQ) {
+        const GridDesc grid = wq_grid(r);
+        double *X, *Y, *J;
+        if ((st = geometry(c, cd, grid, c->geo, X, Y, J))) return st;
+        ta.npts = grid.npts;
+        ta.X = X;
+        ta.Y = Y;
+        ta.J = J;
+        ta.inv_s2 = r->d_inv_s2;
+        ta.ws = r->d_ws;
+        ta.inv_s2f = r->d_inv_s2f;
+        ta.wsf = r->d_wsf;
+        for (int q = 0; q < r->Q; ++q) {
+            ta.coefA[q] = r->w0[q];
+            ta.coefB[q] = r->bvals[q];
+        }
+        HIPCHK(launch_assemble(0, precision, p, P, ta, c->stream));
+        return SGBEM_OK;
+    }
+    // ---- element by element: far part by the tile kernel, near pairs by their own rule
+    const int G = n_gauss;
+    const GridDesc grid = gauss_grid(N, G);
+    double *X, *Y, *J;
+    if ((st = geometry(c, cd, grid, c->geo, X, Y, J))) return st;
+    const GridDesc g16 = gauss_grid(N, 16);
+    double *X16, *Y16, *J16;
+    if ((st = geometry(c, cd, g16, c->geo16, X16, Y16, J16))) return st;
+    const double *dt = nullptr;
+    if ((st = cached_table(c, p, near_table(p), dt))) return st;
+    if ((st = ensure(c, c->nearL, size_t(N) * 2 * (p + 1) * (p + 1) * sizeof(double)))) return st;
+    NearArgs na;
+    na.N = N;
+    na.p = p;
+    na.X16 = X16;
+    na.Y16 = Y16;
+    na.J16 = J16;
+    na.u16 = dt;
+    na.w16 = dt + 16;
+    na.mco = dt + 32;
+    na.madj = dt + 288;
+    na.bv16 = dt + 544;
+    na.L = static_cast<double *>(c->nearL.ptr);
+    HIPCHK(launch_near(na, c->stream));
+
+    ta.npts = grid.npts;
+    ta.X = X;
+    ta.Y = Y;
+    ta.J = J;
+    const std::vector<double> gc = gauss_basis_coef(p, G);
+    for (size_t q = 0; q < gc.size(); ++q) ta.coefA[q] = gc[q] / N;      // h w_g M_p(a + u_g)
+    HIPCHK(launch_assemble(1, precision, p, P, ta, c->stream));
+    HIPCHK(launch_band(precision, N, p, na.L, ta.scale, d_A, lda, c->stream));
+    return SGBEM_OK;
+}
+
+sgbem_status sgbem_rhs(sgbem_ctx c, const sgbem_curve *curve, sgbem_rules r, int32_t method, int32_t n_gauss,
+                       const double *d_g, double *d_beta)
+{
+    if (!c || !r || !d_g || !d_beta) return set_err(SGBEM_E_INVAL, "NULL argument");
+    if (!valid_rules(c, r)) return set_err(SGBEM_E_INVAL, "rules handle does not belong to this context");
+    if (method != SGBEM_WQ && method != SGBEM_EBE) return set_err(SGBEM_E_INVAL, "unknown method");
+    if (method == SGBEM_EBE && (n_gauss < 1 || n_gauss > 8)) return set_err(SGBEM_E_INVAL, "n_gauss must be in [1, 8]");
+    DeviceGuard g(c->device);
+    CurveDev cd;
+    sgbem_status st = upload_curve(c, curve, cd);
+    if (st) return st;
+    const int p = r->p, N = r->N;
+    if (method == SGBEM_WQ) {
+        const GridDesc grid = wq_grid(r);
+        double *X, *Y, *J;
+        if ((st = geometry(c, cd, grid, c->geo, X, Y, J))) return st;
+        HIPCHK(launch_rhs(N, grid.npts, 2 * r->R, 1, r->Q, r->d_w0, 1.0, J, d_g, d_beta, c->stream));
+        return SGBEM_OK;
+    }
+    const int G = n_gauss;
+    const GridDesc grid = gauss_grid(N, G);
+    double *X, *Y, *J;
+    if ((st = geometry(c, cd, grid, c->geo, X, Y, J))) return st;
+    const double *dcoef = nullptr;
+    if ((st = cached_table(c, 1000 + 64 * p + G, gauss_basis_coef(p, G), dcoef))) return st;
+    HIPCHK(launch_rhs(N, grid.npts, G, 0, G * (p + 1), dcoef, 1.0 / N, J, d_g, d_beta, c->stream));
+    return SGBEM_OK;
+}
+
+sgbem_status sgbem_solve(sgbem_ctx c, int32_t N, const void *d_A, int64_t lda, int32_t a_prec, const double *d_beta,
+                         double *d_x, double tol, int32_t max_iter, sgbem_solve_info *info)
+{
+    if (!c || !d_A || !d_beta || !d_x) return set_err(SGBEM_E_INVAL, "NULL argument");
+    if (N < 1 || lda < N) return set_err(SGBEM_E_INVAL, "bad N or lda");
+    if (a_prec != SGBEM_FP64 && a_prec != SGBEM_FP32) return set_err(SGBEM_E_INVAL, "unknown precision");
+    if (max_iter < 0 || !(tol >= 0.0)) return set_err(SGBEM_E_INVAL, "bad tol or max_iter");
+    DeviceGuard g(c->device);
+    const size_t bytes = solve_workspace_bytes(N);
+    sgbem_status st = ensure(c, c->solve_ws, bytes);
+    if (st) return st;
+    SolveResult res;
+    std::string msg;
+    const int rc = mixed_solve(N, d_A, lda, a_prec, d_beta, d_x, tol, max_iter, c->solve_ws.ptr, c->stream, res, msg);
+    if (info) {
+        info->iters = res.iters;
+        info->status = rc;
+        info->rel_update = res.rel_update;
+        info->backward_err = res.backward_err;
+    }
+    if (rc != SGBEM_OK) return set_err(sgbem_status(rc), msg);
+    return SGBEM_OK;
+}
+
+}  // extern "C"

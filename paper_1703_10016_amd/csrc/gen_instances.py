@@ -1,0 +1,53 @@
+"""Write the tile-kernel instantiation units asm_{wq,ebe}_{f64,f32}.hip.
+
+Each unit holds one switch from (degree p, points per element P) to the
+kernel compiled for those compile-time sizes: WQ for p in 1..6 and
+n_ref in 1..4 (P = 2 n_ref, Q = P (p+1) - 1 support nodes, first support node
+1), EBE for p in 1..6 and G in 1..8 Gauss points (P = G, Q = G (p+1), first
+support point 0).  Tiles are 32 x 32 for P <= 4 and 16 x 16 above, 8-column
+strips.  Run from this directory: python gen_instances.py
+"""
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+HDR = '''// Instantiations of the tile kernel for {what} in {prec}: one kernel per
+// (degree p, points per element P); written by gen_instances.py.
+#include "tile_kernel.hpp"
+
+namespace sgbem {{
+
+hipError_t {fname}(int p, int P, const TileArgs &a, hipStream_t s)
+{{
+    switch (p * 16 + P) {{
+'''
+
+
+def wq_cases():
+    for p in range(1, 7):
+        for R in range(1, 5):
+            P = 2 * R
+            yield p, P, P * (p + 1) - 1, 1, "true", 32 if P <= 4 else 16
+
+
+def ebe_cases():
+    for p in range(1, 7):
+        for G in range(1, 9):
+            yield p, G, G * (p + 1), 0, "false", 32 if G <= 4 else 16
+
+
+def main():
+    for what, cases, tag in (("weighted-quadrature row assembly", wq_cases, "wq"),
+                             ("the element-by-element far part", ebe_cases, "ebe")):
+        for prec, real, suf in (("FP64", "double", "f64"), ("FP32", "float", "f32")):
+            fname = f"launch_{tag}_{suf}"
+            s = HDR.format(what=what, prec=prec, fname=fname)
+            for (p, P, Q, S0, wq, T) in cases():
+                s += f"    case {p * 16 + P}: return launch_tile<{P}, {Q}, {S0}, {wq}, {real}, {T}, 8>(a, s);\n"
+            s += "    default: return hipErrorInvalidValue;\n    }\n}\n\n}  // namespace sgbem\n"
+            with open(os.path.join(HERE, f"asm_{tag}_{suf}.hip"), "w") as f:
+                f.write(s)
+
+
+if __name__ == "__main__":
+    main()

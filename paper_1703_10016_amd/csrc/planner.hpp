@@ -1,0 +1,47 @@
+// Host FP64 construction of the quadrature rules (geometry independent).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace sgbem {
+
+struct PlanError {
+    int status;
+    std::string msg;
+};
+
+// Gauss-Legendre nodes / weights on [0, 1].
+void gauss_legendre01(int n, double *x, double *w);
+// Gauss rule for the weight -ln(x) on [0, 1] (exact for polynomials of degree <= 2n-1).
+void gauss_log01(int n, double *x, double *w);
+
+// Cardinal B-spline M_p on [0, p+1]: monomial coefficients of its pieces,
+// coef[c*(p+1) + a] with M_p(c + u) = sum_a coef[c][a] u^a, u in [0, 1].
+std::vector<double> cardinal_pieces(int p);
+double cardinal_eval(int p, const std::vector<double> &pieces, double x);
+
+// int_0^1 P(u) ln|u - sigma| du, P(u) = sum_a c[a] u^a of degree deg.
+double int_poly_log(const double *c, int deg, double sigma);
+
+struct WQRules {
+    int p = 0, N = 0, R = 0;
+    int64_t M = 0, n_nodes = 0;      // M = R N refined elements, 2M nodes
+    int Q = 0;                       // nodes per support: 2R(p+1) - 1
+    std::vector<double> w0;          // [Q]   regular weights of B_0 on nodes 1..Q
+    std::vector<double> bvals;       // [Q]   B_0 at those nodes
+    std::vector<double> ws;          // [2][2M] singular-weight tables
+    std::vector<double> inv_s2;      // [2M]  (pi / sin(pi d / 2M))^2, entry 0 unused
+};
+
+// Build the rules; throws PlanError.
+WQRules build_wq_rules(int p, int N, int R);
+
+struct NearField {
+    double u[16], w[16];
+    double mco[256], madj[256];
+};
+const NearField &nearfield16();
+
+}  // namespace sgbem

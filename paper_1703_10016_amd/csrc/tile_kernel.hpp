@@ -1,0 +1,223 @@
+// Sum-factorised Galerkin tile kernel (fused kernel sweep + banded contraction).
+//
+// Both assembly forms share one structure.  A point grid carries P points per
+// element (WQ: the 2 n_ref nodes of Section 4 per element; EBE: the G Gauss
+// points), basis function j owns the Q points n = P j + S0 + q of its
+// support, and
+//
+//   stage 1   C1[n1][j] = sum_q J(n2) (coefA[q] U(n1,n2) + coefB[q] V(n1,n2)),  n2 = P j + S0 + q
+//   stage 2   A[i][j]   = scale sum_q coefA[q] J(n1) C1[n1][j],                 n1 = P i + S0 + q
+//
+// WQ (eqs. IK1e2, IK1e2_bis, Alg. 3):  U = K1(n1,n2) = 1/2 ln(|f1-f2|^2 (pi/sin(pi d/npts))^2)
+//     (diagonal: ln J, eq. F1_lim), V = singular weight w_{n2}^{(eta_n1)}, coefA = regular
+//     weights, coefB = B_j at the nodes;
+// EBE far part (eq. elbyelint):  U = ln|f1-f2| for element pairs that are neither
+//     coincident nor adjacent (0 otherwise), V = 0, coefA = h w_g M_p(a + u_g).
+//
+// One workgroup owns a T x T tile of A in the upper triangle.  The node
+// coordinates of its two point windows and the slices of the translation-
+// invariant tables sit in LDS; every thread of stage 1 sweeps one n1 row
+// against a strip of S columns, evaluating each kernel value once and
+// accumulating it into the S column sums in registers; stage 2 contracts
+// C1 from LDS.  The tile is written row-major (coalesced) and mirrored through
+// LDS, so the matrix is exactly symmetric (rows i <= j are the computed ones).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace sgbem {
+
+template <typename Real>
+__device__ __forceinline__ Real k_log(Real x);
+template <>
+__device__ __forceinline__ double k_log<double>(double x) { return log(x); }
+template <>
+__device__ __forceinline__ float k_log<float>(float x) { return __logf(x); }
+
+struct TileArgsF {          // FP32 copies of the per-support coefficients
+    float coefA[64];
+    float coefB[64];
+};
+
+template <typename Real>
+__device__ __forceinline__ Real coef_a(const TileArgs &a, const TileArgsF &f, int q);
+template <>
+__device__ __forceinline__ double coef_a<double>(const TileArgs &a, const TileArgsF &, int q) { return a.coefA[q]; }
+template <>
+__device__ __forceinline__ float coef_a<float>(const TileArgs &, const TileArgsF &f, int q) { return f.coefA[q]; }
+template <typename Real>
+__device__ __forceinline__ Real coef_b(const TileArgs &a, const TileArgsF &f, int q);
+template <>
+__device__ __forceinline__ double coef_b<double>(const TileArgs &a, const TileArgsF &, int q) { return a.coefB[q]; }
+template <>
+__device__ __forceinline__ float coef_b<float>(const TileArgs &, const TileArgsF &f, int q) { return f.coefB[q]; }
+
+__device__ __forceinline__ void tile_coords(int nb, int b, int &bi, int &bj)
+{
+    // linear index b over the upper-triangle tiles, row by row
+    const double tn = 2.0 * nb + 1.0;
+    int r = int((tn - sqrt(tn * tn - 8.0 * b)) * 0.5);
+    if (r < 0) r = 0;
+    while (r > 0 && r * nb - (r * (r - 1)) / 2 > b) --r;
+    while ((r + 1) * nb - ((r + 1) * r) / 2 <= b) ++r;
+    bi = r;
+    bj = r + (b - (r * nb - (r * (r - 1)) / 2));
+}
+
+template <int P, int Q, int S0, bool WQ, typename Real, typename OutT, int T, int S>
+__global__ __launch_bounds__(256) void tile_kernel(TileArgs a, TileArgsF af)
+{
+    constexpr int L = P * (T - 1) + Q;     // points in each window
+    constexpr int LT = 2 * L - 1;          // table slice for n2 - n1
+    constexpr int NSTRIP = T / S;
+    constexpr int W2 = P * (S - 1) + Q;    // n2 points swept by one strip
+    static_assert(T % S == 0, "strip must divide tile");
+
+    __shared__ double sx1[L], sy1[L], sx2[L], sy2[L];
+    __shared__ Real sJ1[L], sJ2[L];
+    __shared__ int se1[WQ ? 1 : L], se2[WQ ? 1 : L];
+    __shared__ Real sinv[WQ ? LT : 1], sw0[WQ ? LT : 1], sw1[WQ ? LT : 1];
+    __shared__ Real C1[L][T + 1];
+    __shared__ Real tileo[T][T + 1];
+
+    const int N = a.N, npts = a.npts;
+    const int nb = (N + T - 1) / T;
+    int bi, bj;
+    tile_coords(nb, blockIdx.x, bi, bj);
+    const int I0 = bi * T, J0 = bj * T;
+    const int start1 = (P * I0 + S0) % npts;
+    const int start2 = (P * J0 + S0) % npts;
+
+    for (int r = threadIdx.x; r < L; r += blockDim.x) {
+        const int g1 = (start1 + r) % npts;
+        const int g2 = (start2 + r) % npts;
+        sx1[r] = a.X[g1];
+        sy1[r] = a.Y[g1];
+        sJ1[r] = Real(a.J[g1]);
+        sx2[r] = a.X[g2];
+        sy2[r] = a.Y[g2];
+        sJ2[r] = Real(a.J[g2]);
+        if constexpr (!WQ) {
+            se1[r] = g1 / P;
+            se2[r] = g2 / P;
+        }
+    }
+    if constexpr (WQ) {
+        // slice index dl <-> d = (start2 - start1 + dl - (L - 1)) mod npts
+        int dbase = (start2 - start1 - (L - 1)) % npts;
+        if (dbase < 0) dbase += npts;
+        for (int dl = threadIdx.x; dl < LT; dl += blockDim.x) {
+            const int d = (dbase + dl) % npts;
+            if constexpr (sizeof(Real) == 8) {
+                sinv[dl] = Real(a.inv_s2[d]);
+                sw0[dl] = Real(a.ws[d]);
+                sw1[dl] = Real(a.ws[npts + d]);
+            } else {
+                sinv[dl] = Real(a.inv_s2f[d]);
+                sw0[dl] = Real(a.wsf[d]);
+                sw1[dl] = Real(a.wsf[npts + d]);
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---------------- stage 1: kernel sweep and contraction over the n2 supports
+    for (int item = threadIdx.x; item < L * NSTRIP; item += blockDim.x) {
+        const int r = item % L;
+        const int st = item / L;
+        const double x1 = sx1[r], y1 = sy1[r];
+        const Real J1 = sJ1[r];
+        const int par = (start1 + r) % npts & 1;
+        const int e1 = WQ ? 0 : se1[r];
+        Real acc[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) acc[s] = Real(0);
+#pragma unroll
+        for (int k2 = 0; k2 < W2; ++k2) {
+            const int c2 = st * S * P + k2;
+            const double dx = x1 - sx2[c2], dy = y1 - sy2[c2];
+            Real r2;
+            if constexpr (sizeof(Real) == 8) {
+                r2 = dx * dx + dy * dy;
+            } else {
+                const float fx = float(dx), fy = float(dy);
+                r2 = fx * fx + fy * fy;
+            }
+            Real U, V = Real(0);
+            if constexpr (WQ) {
+                const int dl = c2 - r + (L - 1);
+                const Real inv = sinv[dl];
+                const Real ratio = (inv == Real(0)) ? J1 * J1 : r2 * inv;
+                U = Real(0.5) * k_log<Real>(ratio);
+                V = par ? sw1[dl] : sw0[dl];
+            } else {
+                int de = se2[c2] - e1;
+                if (de < 0) de += N;
+                const bool near = (de == 0) | (de == 1) | (de == N - 1);
+                U = near ? Real(0) : Real(0.5) * k_log<Real>(r2);
+            }
+            const Real J2 = sJ2[c2];
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const int q = k2 - s * P;
+                if (q >= 0 && q < Q) {
+                    if constexpr (WQ)
+                        acc[s] += J2 * (coef_a<Real>(a, af, q) * U + coef_b<Real>(a, af, q) * V);
+                    else
+                        acc[s] += J2 * coef_a<Real>(a, af, q) * U;
+                }
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < S; ++s) C1[r][st * S + s] = J1 * acc[s];
+    }
+    __syncthreads();
+
+    // ---------------- stage 2: contraction over the n1 supports
+    const Real scale = Real(a.scale);
+    for (int e = threadIdx.x; e < T * T; e += blockDim.x) {
+        const int il = e / T, jl = e % T;
+        Real v = Real(0);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) v += coef_a<Real>(a, af, q) * C1[P * il + q][jl];
+        tileo[il][jl] = v * scale;
+    }
+    __syncthreads();
+
+    OutT *out = reinterpret_cast<OutT *>(a.out);
+    const int64_t lda = a.lda;
+    for (int e = threadIdx.x; e < T * T; e += blockDim.x) {
+        const int il = e / T, jl = e % T;
+        const int i = I0 + il, j = J0 + jl;
+        if (i < N && j < N) {
+            const Real v = (bi == bj && il > jl) ? tileo[jl][il] : tileo[il][jl];
+            out[int64_t(i) * lda + j] = OutT(v);
+        }
+    }
+    if (bi != bj) {
+        for (int e = threadIdx.x; e < T * T; e += blockDim.x) {
+            const int rl = e / T, cl = e % T;          // output row J0 + rl, column I0 + cl
+            const int i = J0 + rl, j = I0 + cl;
+            if (i < N && j < N) out[int64_t(i) * lda + j] = OutT(tileo[cl][rl]);
+        }
+    }
+}
+
+template <int P, int Q, int S0, bool WQ, typename Real, int T, int S>
+hipError_t launch_tile(const TileArgs &a, hipStream_t s)
+{
+    TileArgsF af;
+    for (int q = 0; q < 64; ++q) {
+        af.coefA[q] = float(a.coefA[q]);
+        af.coefB[q] = float(a.coefB[q]);
+    }
+    const int nb = (a.N + T - 1) / T;
+    const int blocks = nb * (nb + 1) / 2;
+    using OutT = Real;
+    hipLaunchKernelGGL((tile_kernel<P, Q, S0, WQ, Real, OutT, T, S>), dim3(blocks), dim3(256), 0, s, a, af);
+    return hipGetLastError();
+}
+
+}  // namespace sgbem

@@ -1,0 +1,74 @@
+"""Torch-side convenience wrapper over the C ABI: device buffers come from
+torch, every computation is a libsgbem call on the context's stream."""
+from __future__ import annotations
+
+import numpy as np
+
+from . import sgbem as S
+
+_METHODS = {"wq": S.SGBEM_WQ, "ebe": S.SGBEM_EBE}
+_PREC = {"fp64": S.SGBEM_FP64, "fp32": S.SGBEM_FP32}
+
+
+class Context:
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.ctx = S.sgbem_ctx_create(device, self.stream.cuda_stream)
+        self._rules = {}
+
+    def close(self):
+        if self.ctx is not None:
+            S.sgbem_ctx_destroy(self.ctx)
+            self.ctx = None
+            self._rules = {}
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def rules(self, p: int, N: int, n_ref: int = 1):
+        key = (p, N, n_ref)
+        if key not in self._rules:
+            self._rules[key] = S.sgbem_weights(self.ctx, p, N, n_ref)
+        return self._rules[key]
+
+    def assemble(self, curve, p, N, method="wq", n_ref=1, n_gauss=6, precision="fp64", out=None):
+        dt = self.torch.float64 if precision == "fp64" else self.torch.float32
+        if out is None:
+            out = self.torch.empty((N, N), dtype=dt, device=self.device)
+        assert out.dtype == dt and out.is_cuda and out.stride(1) == 1 and out.shape[0] >= N
+        S.sgbem_assemble(self.ctx, curve, self.rules(p, N, n_ref), _METHODS[method], n_gauss, _PREC[precision],
+                         out.data_ptr(), out.stride(0))
+        return out
+
+    def rhs_points(self, curve, p, N, method="wq", n_ref=1, n_gauss=6):
+        count = 2 * n_ref * N if method == "wq" else N * n_gauss
+        xy = self.torch.empty((count, 2), dtype=self.torch.float64, device=self.device)
+        S.sgbem_rhs_points(self.ctx, curve, self.rules(p, N, n_ref), _METHODS[method], n_gauss, xy.data_ptr(), count)
+        return xy
+
+    def sample(self, g, xy):
+        """The Dirichlet datum at the library's points (evaluated by the caller)."""
+        self.stream.synchronize()
+        h = xy.cpu().numpy()
+        return self.torch.from_numpy(np.ascontiguousarray(g(h[:, 0], h[:, 1]), dtype=np.float64)).to(self.device)
+
+    def rhs(self, curve, p, N, g, method="wq", n_ref=1, n_gauss=6):
+        gv = self.sample(g, self.rhs_points(curve, p, N, method, n_ref, n_gauss))
+        beta = self.torch.empty(N, dtype=self.torch.float64, device=self.device)
+        S.sgbem_rhs(self.ctx, curve, self.rules(p, N, n_ref), _METHODS[method], n_gauss, gv.data_ptr(),
+                    beta.data_ptr())
+        return beta
+
+    def solve(self, A, beta, tol=1e-12, max_iter=30, check=True):
+        N = A.shape[0]
+        prec = S.SGBEM_FP64 if A.dtype == self.torch.float64 else S.SGBEM_FP32
+        x = self.torch.empty(N, dtype=self.torch.float64, device=self.device)
+        st, info = S.sgbem_solve(self.ctx, N, A.data_ptr(), A.stride(0), prec, beta.data_ptr(), x.data_ptr(),
+                                 tol, max_iter, check=check)
+        return x, info

@@ -1,0 +1,200 @@
+"""ctypes binding of libsgbem (include/sgbem.h): argument marshalling only.
+
+Every numerical step runs inside the library's HIP kernels; PyTorch only
+provides device memory and the stream.  The library must have been built
+(``python -m paper_1703_10016_amd.build`` or ``__graft_entry__.build()``);
+there is no fallback of any kind.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsgbem.so")
+
+SGBEM_OK, SGBEM_E_INVAL, SGBEM_E_NOMEM, SGBEM_E_SINGULAR = 0, -1, -2, -3
+SGBEM_E_NOCONV, SGBEM_E_DEVICE, SGBEM_E_UNSUPPORTED = -4, -5, -6
+SGBEM_CURVE_BSPLINE, SGBEM_CURVE_POLAR = 0, 1
+SGBEM_WQ, SGBEM_EBE = 0, 1
+SGBEM_FP64, SGBEM_FP32 = 0, 1
+
+_NAMES = {0: "OK", -1: "E_INVAL", -2: "E_NOMEM", -3: "E_SINGULAR", -4: "E_NOCONV", -5: "E_DEVICE",
+          -6: "E_UNSUPPORTED"}
+
+
+class SgbemError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class sgbem_curve(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("degree", ctypes.c_int32), ("n_ctrl", ctypes.c_int32),
+                ("ctrl_xy", ctypes.POINTER(ctypes.c_double)), ("r0", ctypes.c_double),
+                ("n_modes", ctypes.c_int32), ("a", ctypes.POINTER(ctypes.c_double)),
+                ("phi", ctypes.POINTER(ctypes.c_double))]
+
+
+class sgbem_solve_info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32), ("rel_update", ctypes.c_double),
+                ("backward_err", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libsgbem.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_1703_10016_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        dp = ctypes.POINTER(ctypes.c_double)
+        cp = ctypes.POINTER(sgbem_curve)
+        sig = {
+            "sgbem_ctx_create": [i32, vp, ctypes.POINTER(vp)],
+            "sgbem_ctx_destroy": [vp],
+            "sgbem_ctx_set_stream": [vp, vp],
+            "sgbem_weights": [vp, i32, i32, i32, ctypes.POINTER(vp)],
+            "sgbem_rules_free": [vp, vp],
+            "sgbem_weights_host": [i32, i32, i32, dp, dp, dp],
+            "sgbem_nearfield_host": [dp, dp, dp, dp],
+            "sgbem_rhs_points": [vp, cp, vp, i32, i32, vp, i64, ctypes.POINTER(i64)],
+            "sgbem_assemble": [vp, cp, vp, i32, i32, i32, vp, i64],
+            "sgbem_rhs": [vp, cp, vp, i32, i32, vp, vp],
+            "sgbem_solve": [vp, i32, vp, i64, i32, vp, vp, dbl, i32, ctypes.POINTER(sgbem_solve_info)],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int
+        L.sgbem_last_error.restype = ctypes.c_char_p
+        L.sgbem_last_error.argtypes = []
+        L.sgbem_version.restype = ctypes.c_char_p
+        L.sgbem_version.argtypes = []
+        _lib = L
+    return _lib
+
+
+def _check(st):
+    if st != SGBEM_OK:
+        raise SgbemError(st, lib().sgbem_last_error().decode())
+
+
+def exported_symbols():
+    """Names of the ABI functions (for the load / export check)."""
+    return ["sgbem_ctx_create", "sgbem_ctx_destroy", "sgbem_ctx_set_stream", "sgbem_last_error", "sgbem_version",
+            "sgbem_weights", "sgbem_rules_free", "sgbem_weights_host", "sgbem_nearfield_host", "sgbem_rhs_points",
+            "sgbem_assemble", "sgbem_rhs", "sgbem_solve"]
+
+
+# ------------------------------------------------------------------ curve marshalling
+class Curve:
+    """A curve description kept alive next to its C struct."""
+
+    def __init__(self, curve):
+        self._keep = []
+        c = sgbem_curve()
+        kind = getattr(curve, "kind", None)
+        if kind == "polar":
+            c.kind = SGBEM_CURVE_POLAR
+            c.r0 = float(curve.r0)
+            a = np.ascontiguousarray(curve.a, dtype=np.float64)
+            ph = np.ascontiguousarray(curve.phi, dtype=np.float64)
+            c.n_modes = a.size
+            self._keep += [a, ph]
+            c.a = a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            c.phi = ph.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        elif kind == "bspline":
+            c.kind = SGBEM_CURVE_BSPLINE
+            c.degree = int(curve.degree)
+            q = np.ascontiguousarray(curve.ctrl, dtype=np.float64)
+            c.n_ctrl = q.shape[0]
+            self._keep.append(q)
+            c.ctrl_xy = q.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        else:
+            raise ValueError("curve must have kind 'polar' or 'bspline'")
+        self.c = c
+
+    def ref(self):
+        return ctypes.byref(self.c)
+
+
+def _as_curve(curve):
+    return curve if isinstance(curve, Curve) else Curve(curve)
+
+
+# ------------------------------------------------------------------ ABI functions
+def sgbem_ctx_create(device=0, stream=None):
+    h = ctypes.c_void_p()
+    _check(lib().sgbem_ctx_create(int(device), ctypes.c_void_p(stream or 0), ctypes.byref(h)))
+    return h
+
+
+def sgbem_ctx_destroy(ctx):
+    _check(lib().sgbem_ctx_destroy(ctx))
+
+
+def sgbem_ctx_set_stream(ctx, stream):
+    _check(lib().sgbem_ctx_set_stream(ctx, ctypes.c_void_p(stream or 0)))
+
+
+def sgbem_weights(ctx, p, N, n_ref=1):
+    h = ctypes.c_void_p()
+    _check(lib().sgbem_weights(ctx, int(p), int(N), int(n_ref), ctypes.byref(h)))
+    return h
+
+
+def sgbem_rules_free(ctx, rules):
+    _check(lib().sgbem_rules_free(ctx, rules))
+
+
+def sgbem_weights_host(p, N, n_ref=1):
+    """(w0[Q], bvals[Q], ws[2, 2M]) from the library's host planner."""
+    Q = max(1, 2 * n_ref * (p + 1) - 1)
+    M = max(1, n_ref * N)
+    w0, bv, ws = np.zeros(Q), np.zeros(Q), np.zeros(4 * M)
+    P = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    _check(lib().sgbem_weights_host(int(p), int(N), int(n_ref), P(w0), P(bv), P(ws)))
+    return w0, bv, ws.reshape(2, 2 * M)
+
+
+def sgbem_nearfield_host():
+    u, w, mco, madj = np.zeros(16), np.zeros(16), np.zeros(256), np.zeros(256)
+    P = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    _check(lib().sgbem_nearfield_host(P(u), P(w), P(mco), P(madj)))
+    return u, w, mco.reshape(16, 16), madj.reshape(16, 16)
+
+
+def sgbem_rhs_points(ctx, curve, rules, method, n_gauss, d_xy_ptr, cap):
+    cnt = ctypes.c_int64()
+    c = _as_curve(curve)
+    _check(lib().sgbem_rhs_points(ctx, c.ref(), rules, int(method), int(n_gauss), ctypes.c_void_p(d_xy_ptr),
+                                  int(cap), ctypes.byref(cnt)))
+    return cnt.value
+
+
+def sgbem_assemble(ctx, curve, rules, method, n_gauss, precision, d_A_ptr, lda):
+    c = _as_curve(curve)
+    _check(lib().sgbem_assemble(ctx, c.ref(), rules, int(method), int(n_gauss), int(precision),
+                                ctypes.c_void_p(d_A_ptr), int(lda)))
+
+
+def sgbem_rhs(ctx, curve, rules, method, n_gauss, d_g_ptr, d_beta_ptr):
+    c = _as_curve(curve)
+    _check(lib().sgbem_rhs(ctx, c.ref(), rules, int(method), int(n_gauss), ctypes.c_void_p(d_g_ptr),
+                           ctypes.c_void_p(d_beta_ptr)))
+
+
+def sgbem_solve(ctx, N, d_A_ptr, lda, a_prec, d_beta_ptr, d_x_ptr, tol=1e-12, max_iter=30, check=True):
+    info = sgbem_solve_info()
+    st = lib().sgbem_solve(ctx, int(N), ctypes.c_void_p(d_A_ptr), int(lda), int(a_prec), ctypes.c_void_p(d_beta_ptr),
+                           ctypes.c_void_p(d_x_ptr), float(tol), int(max_iter), ctypes.byref(info))
+    if check:
+        _check(st)
+    return st, info
