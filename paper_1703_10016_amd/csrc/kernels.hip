@@ -187,9 +187,11 @@ __global__ void band_kernel(int N, int p, const double *L, double scale, OutT *o
                 s += L[(int64_t(e2) * 2 + 1) * np * np + b * np + ia];
         }
     }
-    const double c = scale * s;
-    out[int64_t(i) * lda + j] = OutT(double(out[int64_t(i) * lda + j]) + c);
-    if (i != j) out[int64_t(j) * lda + i] = OutT(double(out[int64_t(j) * lda + i]) + c);
+    // (i, j) and (j, i) hold the same value before the update; compute the
+    // new value once so that the matrix stays exactly symmetric.
+    const OutT v = OutT(double(out[int64_t(i) * lda + j]) + scale * s);
+    out[int64_t(i) * lda + j] = v;
+    if (i != j) out[int64_t(j) * lda + i] = v;
 }
 
 hipError_t launch_band(int prec, int N, int p, const double *L, double scale, void *out, int64_t lda, hipStream_t s)

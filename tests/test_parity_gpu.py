@@ -158,11 +158,12 @@ def test_mixed_solve_matches_fp64_solve(ctx, N, prec):
     curve, p = synth.star(13), 3
     A = ctx.assemble(curve, p, N, "wq", precision=prec)
     beta = ctx.rhs(curve, p, N, synth.g_exp_cos)
-    x, info = ctx.solve(A, beta, tol=1e-14, max_iter=30)
+    x, info = ctx.solve(A, beta, tol=1e-12, max_iter=30)
     Ah = A.cpu().numpy().astype(np.float64)
     ref = np.linalg.solve(Ah, beta.cpu().numpy())
     xh = x.cpu().numpy()
-    assert np.linalg.norm(xh - ref) / np.linalg.norm(ref) < 1e-10
+    err = np.linalg.norm(xh - ref) / np.linalg.norm(ref)
+    assert err < 1e-10, (err, info.iters, info.rel_update, info.backward_err)
     assert info.backward_err < 1e-14 and info.iters >= 1
 
 
