@@ -1,0 +1,267 @@
+#!/usr/bin/env python3
+"""Galerkin entries/s of the weighted-quadrature row assembly against the
+element-by-element Gauss assembly at equal solution error, on one MI355X.
+
+Workload: the ellipse with semi-axes (1, 0.5) as a closed cubic B-spline of 32
+control points, periodic B-splines p = 3 on N = 1024 elements, FP64,
+g = exp(x1) cos(x2).  A step is one assembly of the full 1024 x 1024 matrix by
+the fast form (node-grid geometry kernel + fused sweep-and-contract kernel),
+with the curve and the quadrature rules resident on the device.  K steps are
+captured in one HIP graph and replayed once inside the timed region.
+
+Also measured in the same run (reported beside the headline value):
+ * the element-by-element form at the smallest Gauss order whose solution
+   error is not larger than the fast form's (errors of the coefficient vector
+   against an element-by-element G = 8 solution), and the speedup;
+ * latency of a solve request (assemble + right-hand side + mixed-precision
+   solve), p50 / p99 over repeated requests;
+ * the fused kernel's duration from HIP events on its stream -> roofline;
+ * FP32 and FP64 throughput at N = 16384 (a star curve, one assembly each);
+ * the CPU oracle (element-by-element, FP64, C + OpenMP) on a sample of rows.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64 = 78.6e12          # MI355X FP64 vector, FLOP/s
+PEAK_FP32 = 157.3e12         # MI355X FP32 vector, FLOP/s
+PEAK_HBM = 8.0e12            # bytes/s
+FLOPS_PER_LOG = 20           # cost model of one logarithm
+
+
+def wq_flops_per_entry(p: int, R: int) -> float:
+    """Algorithmic flops per matrix entry of the fast form: stage 1 and stage 2
+    contractions, (4R + 1) Q multiply-adds, Q = 2R(p+1) - 1 (2 flops each), and
+    4R^2 kernel evaluations on the node grid (difference, squared distance,
+    scaling: 6 flops + one logarithm)."""
+    Q = 2 * R * (p + 1) - 1
+    return 2.0 * (4 * R + 1) * Q + 4.0 * R * R * (6 + FLOPS_PER_LOG)
+
+
+def ebe_flops_per_entry(p: int, G: int) -> float:
+    """Element-by-element far part: G^2 kernel evaluations (5 flops + log) and
+    (p+1) G^2 + (p+1) G multiply-adds per entry (sum factorised)."""
+    return G * G * (5 + FLOPS_PER_LOG) + 2.0 * ((p + 1) * G * G + (p + 1) * G)
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the CPU oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-scale", action="store_true", help="skip the N = 16384 points")
+    ap.add_argument("--solves", type=int, default=60)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(the row-block sharding is described in DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    from paper_1703_10016_amd import sgbem as S
+    from paper_1703_10016_amd.runtime import Context
+
+    assert torch.cuda.is_available(), "no GPU visible"
+    K, W = args.steps, args.warmup
+    prob = synth.config_ellipse()
+    curve, p, N, g = prob.curve, prob.p, prob.N, prob.g
+    R = 1
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    ctx = Context(0, stream=stream)
+
+    t0 = time.perf_counter()
+    ctx.rules(p, N, R)
+    t_rules = time.perf_counter() - t0
+    log(f"[bench] rules (p={p}, N={N}, n_ref={R}) built in {t_rules*1e3:.1f} ms")
+
+    # ---------------------------------------------------------------- equal error
+    def solve_coeffs(method, **kw):
+        A = ctx.assemble(curve, p, N, method, **kw)
+        beta = ctx.rhs(curve, p, N, g, method=method, **kw)
+        x, info = ctx.solve(A, beta, tol=1e-12, max_iter=30)
+        return x.cpu().numpy()
+
+    a_ref = solve_coeffs("ebe", n_gauss=8)
+    err = lambda a: float(np.linalg.norm(a - a_ref) / np.linalg.norm(a_ref))
+    err_wq = err(solve_coeffs("wq", n_ref=R))
+    err_ebe = {G: err(solve_coeffs("ebe", n_gauss=G)) for G in (1, 2, 3, 4, 5, 6)}
+    G_eq = next((G for G in sorted(err_ebe) if err_ebe[G] <= err_wq), 6)
+    log(f"[bench] solution error vs EBE(G=8): WQ {err_wq:.3e}; EBE " +
+        " ".join(f"G={G}:{e:.3e}" for G, e in err_ebe.items()) + f" -> equal-error G = {G_eq}")
+
+    # ---------------------------------------------------------------- timed steps (graph replay)
+    def graph_rate(method, steps, **kw):
+        A = torch.empty((N, N), dtype=torch.float64, device="cuda")
+        for _ in range(W):
+            ctx.assemble(curve, p, N, method, out=A, **kw)
+        torch.cuda.synchronize()
+        gph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(gph, stream=stream):
+            for _ in range(steps):
+                ctx.assemble(curve, p, N, method, out=A, **kw)
+        gph.replay()                      # warm replay
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        gph.replay()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        del gph
+        return ms / steps, A
+
+    ms_wq, A_wq = graph_rate("wq", K, n_ref=R)
+    value = N * N / (ms_wq * 1e-3)
+    log(f"[bench] WQ FP64 step {ms_wq*1e3:.2f} us -> {value:.3e} entries/s")
+    ms_ebe, _ = graph_rate("ebe", max(10, K // 4), n_gauss=G_eq)
+    ebe_rate = N * N / (ms_ebe * 1e-3)
+    log(f"[bench] EBE FP64 G={G_eq} step {ms_ebe*1e3:.2f} us -> {ebe_rate:.3e} entries/s")
+
+    # direct launches (host enqueue included), for reference
+    A = torch.empty((N, N), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        ctx.assemble(curve, p, N, "wq", n_ref=R, out=A)
+    torch.cuda.synchronize()
+    ms_direct = (time.perf_counter() - t0) * 1e3 / K
+
+    # ---------------------------------------------------------------- roofline of the fused kernel
+    S.sgbem_ctx_set_timing(ctx.ctx, 1)
+    for _ in range(K):
+        ctx.assemble(curve, p, N, "wq", n_ref=R, out=A)
+    tot_ms, cnt = S.sgbem_ctx_kernel_time(ctx.ctx)
+    S.sgbem_ctx_set_timing(ctx.ctx, 0)
+    kern_ms = tot_ms / cnt
+    upper = N * (N + 1) / 2
+    flops = upper * wq_flops_per_entry(p, R)
+    achieved = flops / (kern_ms * 1e-3)
+    log(f"[bench] fused WQ kernel {kern_ms*1e3:.2f} us avg over {cnt}: {achieved/1e12:.3f} TFLOP/s "
+        f"({achieved/PEAK_FP64:.4f} of FP64 peak), write {8*N*N/(kern_ms*1e-3)/1e9:.1f} GB/s")
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", "wq_fp64_ellipse_N1024_traffic.json")
+    if os.path.exists(tfile):
+        with open(tfile) as f:
+            traffic = json.load(f).get("bytes_per_launch")
+
+    # ---------------------------------------------------------------- solve latency
+    xy = ctx.rhs_points(curve, p, N, "wq", n_ref=R)
+    gv = ctx.sample(g, xy)
+    beta = torch.empty(N, dtype=torch.float64, device="cuda")
+    lat_req, lat_solve = [], []
+    for it in range(args.solves + 3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.assemble(curve, p, N, "wq", n_ref=R, out=A)
+        S.sgbem_rhs(ctx.ctx, curve, ctx.rules(p, N, R), S.SGBEM_WQ, 0, gv.data_ptr(), beta.data_ptr())
+        t1 = time.perf_counter()
+        x, info = ctx.solve(A, beta, tol=1e-12, max_iter=30)
+        t2 = time.perf_counter()
+        if it >= 3:
+            lat_req.append((t2 - t0) * 1e3)
+            lat_solve.append((t2 - t1) * 1e3)
+    pct = lambda v, q: float(np.percentile(np.array(v), q))
+    log(f"[bench] request latency p50 {pct(lat_req, 50):.3f} ms p99 {pct(lat_req, 99):.3f} ms; "
+        f"solve p50 {pct(lat_solve, 50):.3f} p99 {pct(lat_solve, 99):.3f} ms ({info.iters} refinement steps)")
+
+    # ---------------------------------------------------------------- N = 16384 scale points
+    scale = {}
+    if not args.no_scale:
+        star = synth.star(0)
+        Nb = 16384
+        for prec, dt in (("fp32", torch.float32), ("fp64", torch.float64)):
+            Ab = torch.empty((Nb, Nb), dtype=dt, device="cuda")
+            ctx.assemble(star, p, Nb, "wq", n_ref=R, precision=prec, out=Ab)
+            torch.cuda.synchronize()
+            S.sgbem_ctx_set_timing(ctx.ctx, 1)
+            reps = 3
+            for _ in range(reps):
+                ctx.assemble(star, p, Nb, "wq", n_ref=R, precision=prec, out=Ab)
+            tms, c2 = S.sgbem_ctx_kernel_time(ctx.ctx)
+            S.sgbem_ctx_set_timing(ctx.ctx, 0)
+            kms = tms / c2
+            fl = Nb * (Nb + 1) / 2 * wq_flops_per_entry(p, R)
+            pk = PEAK_FP32 if prec == "fp32" else PEAK_FP64
+            scale[prec] = {"N": Nb, "kernel_ms": round(kms, 4), "entries_per_s": Nb * Nb / (kms * 1e-3),
+                           "tflops": fl / (kms * 1e-3) / 1e12, "frac_of_vector_peak": fl / (kms * 1e-3) / pk}
+            log(f"[bench] star N={Nb} WQ {prec}: {kms:.3f} ms -> {Nb*Nb/(kms*1e-3):.3e} entries/s, "
+                f"{fl/(kms*1e-3)/1e12:.2f} TFLOP/s")
+            del Ab
+        torch.cuda.empty_cache()
+
+    # ---------------------------------------------------------------- CPU oracle
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import ebe as oebe
+        P = oebe.EBEProblem(curve, p, N, G_eq)
+        nthreads = min(os.cpu_count() or 1, 16)
+        t0 = time.perf_counter()
+        P.rows(np.arange(4), nthreads)
+        dt1 = time.perf_counter() - t0
+        nrows = int(max(4, min(N, 4 * args.cpu_seconds / max(dt1, 1e-3))))
+        t0 = time.perf_counter()
+        P.rows(np.arange(nrows), nthreads)
+        dt = time.perf_counter() - t0
+        cpu = {"value": nrows * N / dt, "unit": "entries/s", "cores": int(P.threads_used), "kind": "oracle",
+               "sample": f"element-by-element oracle (FP64, G={G_eq}, 16x16 near rule), rows 0..{nrows-1} of the "
+                         f"N={N} ellipse matrix ({nrows*N} entries, {dt:.1f} s)"}
+        log(f"[bench] CPU oracle: {cpu['value']:.3e} entries/s on {cpu['cores']} threads ({dt:.1f} s)")
+
+    out = {
+        "metric": "Galerkin entries/sec, WQ row vs element-by-element at equal err; p99 solve latency",
+        "value": value,
+        "unit": "entries/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": ms_wq,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "ellipse (1, 0.5) as closed cubic B-spline of 32 control points; periodic "
+                               "B-splines p=3, N=1024; weighted-quadrature row assembly n_ref=1, FP64",
+                   "p": p, "N": N, "n_ref": R, "step": "geometry + fused WQ assembly, HIP graph replay"},
+        "equal_error": {"wq_solution_err": err_wq, "ebe_solution_err": err_ebe, "ebe_gauss_order": G_eq,
+                        "reference": "element-by-element G=8 solution (FP64)"},
+        "ebe": {"entries_per_s": ebe_rate, "ms_per_step": ms_ebe, "n_gauss": G_eq},
+        "speedup_wq_vs_ebe_equal_err": value / ebe_rate,
+        "direct_launch_ms_per_step": ms_direct,
+        "rules_build_ms": t_rules * 1e3,
+        "solve_latency_ms": {"p50": pct(lat_solve, 50), "p99": pct(lat_solve, 99)},
+        "request_latency_ms": {"p50": pct(lat_req, 50), "p99": pct(lat_req, 99),
+                               "request": "assemble + rhs + mixed solve, N=1024"},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64, "traffic": traffic,
+                     "kernel": "fused WQ sweep-and-contract (FP64)", "kernel_us": kern_ms * 1e3,
+                     "flops_per_launch": flops},
+        "scale_N16384": scale,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -54,8 +54,10 @@ typedef enum { SGBEM_WQ = 0, SGBEM_EBE = 1 } sgbem_method;
 typedef enum { SGBEM_FP64 = 0, SGBEM_FP32 = 1 } sgbem_precision;
 
 /*
- * Closed curve f : [0, 1) -> R^2 (Section 3).  Host memory, copied by the
- * library at each call that takes it.
+ * Closed curve f : [0, 1) -> R^2 (Section 3).  Host memory, read during the
+ * call: up to 64 control points (or any polar curve) travel inline in the
+ * kernel arguments; larger control nets are copied to device memory owned by
+ * the context.
  *  BSPLINE: f(t) = sum_j ctrl[j] M_d(n t - j mod n) with periodic uniform knots
  *           (the closed-curve representation of Section 3, whose last d control
  *           points repeat the first ones; here they are not repeated):
@@ -95,6 +97,17 @@ sgbem_status sgbem_ctx_destroy(sgbem_ctx ctx);
 
 /* Switch the stream used by later calls (the previous stream is synchronised). */
 sgbem_status sgbem_ctx_set_stream(sgbem_ctx ctx, void *hip_stream);
+
+/* Timing of the main kernel of every later assembly call: when `on`, the
+ * library records a pair of HIP events on the context's stream around the
+ * tile kernel of each sgbem_assemble call (WQ: the fused sweep-and-contract
+ * kernel; EBE: its far-pair kernel).  Events are kept by the context. */
+sgbem_status sgbem_ctx_set_timing(sgbem_ctx ctx, int32_t on);
+
+/* Wait for the recorded events and return the summed elapsed milliseconds and
+ * the number of timed kernels since the last call (then forget them).
+ * Errors: E_INVAL, E_DEVICE. */
+sgbem_status sgbem_ctx_kernel_time(sgbem_ctx ctx, double *total_ms, int64_t *count);
 
 /* Message of the last failing call on this host thread. */
 const char *sgbem_last_error(void);

@@ -78,6 +78,10 @@ struct sgbem_ctx_s {
     // key p      -> u16, w16, mco, madj, M_p(a + u16)       (near pairs)
     // key 1000 + 64p + G -> RHS coefficients w_g M_p(a + u_g) without h
     std::map<int, double *> tables;
+    // optional HIP-event timing of the main kernel of each call
+    int timing = 0;
+    std::vector<hipEvent_t> ev;
+    size_t ev_used = 0;
 };
 
 namespace {
@@ -149,25 +153,30 @@ sgbem_status upload_curve(sgbem_ctx c, const sgbem_curve *cv, CurveDev &d)
     if (st) return st;
     std::memset(&d, 0, sizeof d);
     d.kind = cv->kind;
-    if (cv->kind == SGBEM_CURVE_BSPLINE) {
+    if (cv->kind == SGBEM_CURVE_BSPLINE && cv->n_ctrl <= 64) {
+        d.degree = cv->degree;
+        d.n_ctrl = cv->n_ctrl;
+        d.inline_data = 1;
+        std::memcpy(d.inl, cv->ctrl_xy, size_t(cv->n_ctrl) * 2 * sizeof(double));
+        return SGBEM_OK;
+    }
+    if (cv->kind == SGBEM_CURVE_POLAR) {
+        d.r0 = cv->r0;
+        d.n_modes = cv->n_modes;
+        d.inline_data = 1;
+        if (cv->n_modes > 0) {
+            std::memcpy(d.inl, cv->a, size_t(cv->n_modes) * sizeof(double));
+            std::memcpy(d.inl + 64, cv->phi, size_t(cv->n_modes) * sizeof(double));
+        }
+        return SGBEM_OK;
+    }
+    {
         d.degree = cv->degree;
         d.n_ctrl = cv->n_ctrl;
         const size_t bytes = size_t(cv->n_ctrl) * 2 * sizeof(double);
         if ((st = ensure(c, c->params, bytes))) return st;
         HIPCHK(hipMemcpyAsync(c->params.ptr, cv->ctrl_xy, bytes, hipMemcpyHostToDevice, c->stream));
         d.ctrl = static_cast<const double *>(c->params.ptr);
-    } else {
-        d.r0 = cv->r0;
-        d.n_modes = cv->n_modes;
-        const size_t bytes = size_t(2 * cv->n_modes + 1) * sizeof(double);
-        if ((st = ensure(c, c->params, bytes))) return st;
-        double *base = static_cast<double *>(c->params.ptr);
-        if (cv->n_modes > 0) {
-            HIPCHK(hipMemcpyAsync(base, cv->a, cv->n_modes * sizeof(double), hipMemcpyHostToDevice, c->stream));
-            HIPCHK(hipMemcpyAsync(base + cv->n_modes, cv->phi, cv->n_modes * sizeof(double), hipMemcpyHostToDevice, c->stream));
-        }
-        d.a = base;
-        d.phi = base + cv->n_modes;
     }
     return SGBEM_OK;
 }
@@ -250,6 +259,20 @@ std::vector<double> gauss_basis_coef(int p, int G)
     return coef;
 }
 
+// Record an event on the context's stream when timing is on (pairs bracket the
+// main kernel of a call).
+sgbem_status mark(sgbem_ctx c)
+{
+    if (!c->timing) return SGBEM_OK;
+    if (c->ev_used == c->ev.size()) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        c->ev.push_back(e);
+    }
+    HIPCHK(hipEventRecord(c->ev[c->ev_used++], c->stream));
+    return SGBEM_OK;
+}
+
 bool valid_rules(sgbem_ctx c, sgbem_rules r)
 {
     for (auto *x : c->rules)
@@ -302,7 +325,35 @@ sgbem_status sgbem_ctx_destroy(sgbem_ctx c)
         if (b->ptr) (void)hipFree(b->ptr);
     for (auto &kv : c->tables) (void)hipFree(kv.second);
     for (auto *r : c->rules) free_rules(r);
+    for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     delete c;
+    return SGBEM_OK;
+}
+
+sgbem_status sgbem_ctx_set_timing(sgbem_ctx c, int32_t on)
+{
+    if (!c) return set_err(SGBEM_E_INVAL, "ctx is NULL");
+    c->timing = on ? 1 : 0;
+    c->ev_used = 0;
+    return SGBEM_OK;
+}
+
+sgbem_status sgbem_ctx_kernel_time(sgbem_ctx c, double *total_ms, int64_t *count)
+{
+    if (!c || !total_ms || !count) return set_err(SGBEM_E_INVAL, "NULL argument");
+    DeviceGuard g(c->device);
+    double tot = 0.0;
+    int64_t n = 0;
+    if (c->ev_used >= 2) HIPCHK(hipEventSynchronize(c->ev[c->ev_used - 1]));
+    for (size_t i = 0; i + 1 < c->ev_used; i += 2) {
+        float ms = 0.0f;
+        HIPCHK(hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]));
+        tot += ms;
+        ++n;
+    }
+    c->ev_used = 0;
+    *total_ms = tot;
+    *count = n;
     return SGBEM_OK;
 }
 
@@ -454,7 +505,9 @@ sgbem_status sgbem_assemble(sgbem_ctx c, const sgbem_curve *curve, sgbem_rules r
             ta.coefA[q] = r->w0[q];
             ta.coefB[q] = r->bvals[q];
         }
+        if ((st = mark(c))) return st;
         HIPCHK(launch_assemble(0, precision, p, P, ta, c->stream));
+        if ((st = mark(c))) return st;
         return SGBEM_OK;
     }
     // ---- element by element: far part by the tile kernel, near pairs by their own rule
@@ -488,7 +541,9 @@ sgbem_status sgbem_assemble(sgbem_ctx c, const sgbem_curve *curve, sgbem_rules r
     ta.J = J;
     const std::vector<double> gc = gauss_basis_coef(p, G);
     for (size_t q = 0; q < gc.size(); ++q) ta.coefA[q] = gc[q] / N;      // h w_g M_p(a + u_g)
+    if ((st = mark(c))) return st;
     HIPCHK(launch_assemble(1, precision, p, P, ta, c->stream));
+    if ((st = mark(c))) return st;
     HIPCHK(launch_band(precision, N, p, na.L, ta.scale, d_A, lda, c->stream));
     return SGBEM_OK;
 }

@@ -23,6 +23,9 @@ __global__ void geometry_kernel(CurveDev c, GridDesc g, double *X, double *Y, do
         const int e = n / g.P, q = n - e * g.P;
         t = (double(e) + g.off[q]) / double(g.N);
     }
+    const double *ca = c.inline_data ? c.inl : c.a;
+    const double *cphi = c.inline_data ? c.inl + 64 : c.phi;
+    const double *cq = c.inline_data ? c.inl : c.ctrl;
     double x, y, dx, dy;
     if (c.kind == 1) {
         double sn, cs;
@@ -31,9 +34,9 @@ __global__ void geometry_kernel(CurveDev c, GridDesc g, double *X, double *Y, do
         double r = 1.0, dr = 0.0;
         for (int k = 1; k <= c.n_modes; ++k) {
             double sk, ck;
-            sincos(k * th + c.phi[k - 1], &sk, &ck);
-            r += c.a[k - 1] * ck;
-            dr -= k * c.a[k - 1] * sk;
+            sincos(k * th + cphi[k - 1], &sk, &ck);
+            r += ca[k - 1] * ck;
+            dr -= k * ca[k - 1] * sk;
         }
         r *= c.r0;
         dr *= c.r0;
@@ -51,8 +54,8 @@ __global__ void geometry_kernel(CurveDev c, GridDesc g, double *X, double *Y, do
         for (int i = 0; i <= d; ++i) {
             int j = l - d + i;
             j = ((j % nc) + nc) % nc;
-            px[i] = c.ctrl[2 * j];
-            py[i] = c.ctrl[2 * j + 1];
+            px[i] = cq[2 * j];
+            py[i] = cq[2 * j + 1];
         }
         // derivative control points (degree d-1): n_ctrl (Q_j - Q_{j-1}), j = l-d+1 .. l
         double qx[8], qy[8];

@@ -17,6 +17,8 @@ struct CurveDev {
     const double *ctrl;   // [n_ctrl][2]
     const double *a;      // [n_modes]
     const double *phi;    // [n_modes]
+    int inline_data;      // 1: ctrl / a / phi live in inl[] below (no upload needed)
+    double inl[128];      // B-spline: ctrl[64][2]; polar: a[64], phi[64]
 };
 
 // Point grid on [0, 1): n = e * P + q  ->  t = (e + off[q]) / N  (P <= 32),

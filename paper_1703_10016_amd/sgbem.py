@@ -60,6 +60,8 @@ def lib():
             "sgbem_ctx_create": [i32, vp, ctypes.POINTER(vp)],
             "sgbem_ctx_destroy": [vp],
             "sgbem_ctx_set_stream": [vp, vp],
+            "sgbem_ctx_set_timing": [vp, i32],
+            "sgbem_ctx_kernel_time": [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)],
             "sgbem_weights": [vp, i32, i32, i32, ctypes.POINTER(vp)],
             "sgbem_rules_free": [vp, vp],
             "sgbem_weights_host": [i32, i32, i32, dp, dp, dp],
@@ -88,7 +90,8 @@ def _check(st):
 
 def exported_symbols():
     """Names of the ABI functions (for the load / export check)."""
-    return ["sgbem_ctx_create", "sgbem_ctx_destroy", "sgbem_ctx_set_stream", "sgbem_last_error", "sgbem_version",
+    return ["sgbem_ctx_create", "sgbem_ctx_destroy", "sgbem_ctx_set_stream", "sgbem_ctx_set_timing",
+            "sgbem_ctx_kernel_time", "sgbem_last_error", "sgbem_version",
             "sgbem_weights", "sgbem_rules_free", "sgbem_weights_host", "sgbem_nearfield_host", "sgbem_rhs_points",
             "sgbem_assemble", "sgbem_rhs", "sgbem_solve"]
 
@@ -142,6 +145,16 @@ def sgbem_ctx_destroy(ctx):
 
 def sgbem_ctx_set_stream(ctx, stream):
     _check(lib().sgbem_ctx_set_stream(ctx, ctypes.c_void_p(stream or 0)))
+
+
+def sgbem_ctx_set_timing(ctx, on):
+    _check(lib().sgbem_ctx_set_timing(ctx, int(bool(on))))
+
+
+def sgbem_ctx_kernel_time(ctx):
+    ms, n = ctypes.c_double(), ctypes.c_int64()
+    _check(lib().sgbem_ctx_kernel_time(ctx, ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
 
 
 def sgbem_weights(ctx, p, N, n_ref=1):
