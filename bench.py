@@ -54,6 +54,15 @@ def ebe_flops_per_entry(p: int, G: int) -> float:
     return G * G * (5 + FLOPS_PER_LOG) + 2.0 * ((p + 1) * G * G + (p + 1) * G)
 
 
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("tile_kernel.hpp", "kernels.hpp"):
+        with open(os.path.join(ROOT, "paper_1703_10016_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -67,6 +76,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-scale", action="store_true", help="skip the N = 16384 points")
     ap.add_argument("--solves", type=int, default=60)
+    ap.add_argument("--profile-run", action="store_true",
+                    help="only K direct WQ assemblies of the workload and one 256 MiB device copy "
+                         "(the copy calibrates the byte counters of a profiler run)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -90,6 +102,18 @@ def main():
     t0 = time.perf_counter()
     ctx.rules(p, N, R)
     t_rules = time.perf_counter() - t0
+    if args.profile_run:
+        A = torch.empty((N, N), dtype=torch.float64, device="cuda")
+        for _ in range(W + K):
+            ctx.assemble(curve, p, N, "wq", n_ref=R, out=A)
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)                      # 256 MiB read + 256 MiB written
+        torch.cuda.synchronize()
+        log(f"[bench] profile run: {W + K} WQ assemblies, one copy of {src.numel() * 8} bytes")
+        ctx.close()
+        return
     log(f"[bench] rules (p={p}, N={N}, n_ref={R}) built in {t_rules*1e3:.1f} ms")
 
     # ---------------------------------------------------------------- equal error
@@ -162,7 +186,9 @@ def main():
     tfile = os.path.join(ROOT, "profiles", "wq_fp64_ellipse_N1024_traffic.json")
     if os.path.exists(tfile):
         with open(tfile) as f:
-            traffic = json.load(f).get("bytes_per_launch")
+            tj = json.load(f)
+        if tj.get("source_hash") == kernel_source_hash():   # counters only count for the kernel they measured
+            traffic = tj.get("bytes_per_launch")
 
     # ---------------------------------------------------------------- solve latency
     xy = ctx.rhs_points(curve, p, N, "wq", n_ref=R)
@@ -216,15 +242,21 @@ def main():
         P = oebe.EBEProblem(curve, p, N, G_eq)
         nthreads = min(os.cpu_count() or 1, 16)
         t0 = time.perf_counter()
-        P.rows(np.arange(4), nthreads)
+        P.rows(np.arange(16), nthreads)
         dt1 = time.perf_counter() - t0
-        nrows = int(max(4, min(N, 4 * args.cpu_seconds / max(dt1, 1e-3))))
+        # rows of the matrix, cycled, for about --cpu-seconds of oracle work
+        nrows = int(max(16, 16 * args.cpu_seconds / max(dt1, 1e-4)))
+        rows = np.arange(nrows) % N
         t0 = time.perf_counter()
-        P.rows(np.arange(nrows), nthreads)
+        done = 0
+        while done < nrows:
+            chunk = rows[done:done + N]
+            P.rows(chunk, nthreads)
+            done += chunk.size
         dt = time.perf_counter() - t0
         cpu = {"value": nrows * N / dt, "unit": "entries/s", "cores": int(P.threads_used), "kind": "oracle",
-               "sample": f"element-by-element oracle (FP64, G={G_eq}, 16x16 near rule), rows 0..{nrows-1} of the "
-                         f"N={N} ellipse matrix ({nrows*N} entries, {dt:.1f} s)"}
+               "sample": f"element-by-element oracle (FP64, G={G_eq}, 16x16 near rule) on {nrows} rows of the "
+                         f"N={N} ellipse matrix taken cyclically ({nrows*N} entries, {dt:.1f} s)"}
         log(f"[bench] CPU oracle: {cpu['value']:.3e} entries/s on {cpu['cores']} threads ({dt:.1f} s)")
 
     out = {
