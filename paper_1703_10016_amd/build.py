@@ -20,6 +20,8 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 HIP_UNITS = ["api.hip", "kernels.hip", "solve.hip",
              "asm_wq_f64.hip", "asm_wq_f32.hip", "asm_ebe_f64.hip", "asm_ebe_f32.hip"]
 CXX_UNITS = ["planner.cpp"]
+# the register-resident LU panel needs its 64 x 64 column loop fully unrolled
+UNIT_FLAGS = {"solve.hip": ["-mllvm", "-pragma-unroll-threshold=1000000"]}
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall", "-Wno-unused-result"]
 
@@ -41,7 +43,7 @@ def build(jobs: int = 8, verbose: bool = False) -> str:
     for u in HIP_UNITS:
         o = os.path.join(BUILD, u + ".o")
         objs.append(o)
-        cmds.append([HIPCC] + HIP_FLAGS + ["-c", os.path.join(CSRC, u), "-o", o])
+        cmds.append([HIPCC] + HIP_FLAGS + UNIT_FLAGS.get(u, []) + ["-c", os.path.join(CSRC, u), "-o", o])
     for u in CXX_UNITS:
         o = os.path.join(BUILD, u + ".o")
         objs.append(o)

@@ -14,15 +14,16 @@ namespace sgbem {
 
 namespace {
 
-constexpr int NB = 64;            // panel width
+constexpr int NB = 64;            // widest panel (register panels); longer panels use 32 columns
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 struct WS {
     float *LU;
     int *piv, *perm, *info;
     double *r;
-    float *v;
+    float *v, *v2;
     double *red;     // reduction outputs
+    float *DI;       // inverted diagonal blocks
 };
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
@@ -43,8 +44,17 @@ WS carve(void *base, int N)
     p += align_up(size_t(N) * sizeof(double));
     w.v = reinterpret_cast<float *>(p);
     p += align_up(size_t(N) * sizeof(float));
+    w.v2 = reinterpret_cast<float *>(p);
+    p += align_up(size_t(N) * sizeof(float));
     w.red = reinterpret_cast<double *>(p);
+    p += align_up(64 * sizeof(double)) + align_up(size_t(N) * sizeof(double));
+    w.DI = reinterpret_cast<float *>(p);
     return w;
+}
+
+__global__ void zero_int_kernel(int *p)
+{
+    if (threadIdx.x == 0) *p = 0;
 }
 
 // ---------------------------------------------------------------- copy / transpose
@@ -142,6 +152,115 @@ __global__ __launch_bounds__(1024) void panel_kernel(int N, float *LU, int k0, i
     }
 }
 
+// Register-resident panel factorisation (one workgroup of 1024 threads, RT rows
+// per thread, W <= 32 columns): thread t owns the panel rows k0 + r*1024 + t
+// with all W columns in registers.  The column loop is unrolled, so every
+// register index is a compile-time constant.  Per column: pivot = largest
+// magnitude at or below the diagonal (lowest row on ties); the pivot row and
+// the diagonal row exchange their register rows through LDS (earlier L
+// multipliers included: a row interchange of the panel) -- only the two
+// owning wavefronts execute that copy; the rows below are scaled and updated.
+// Global memory is touched only to load the panel and to store it, the
+// pivots and info at the end; two barriers per column.
+template <int RT, int W>
+__global__ __launch_bounds__(1024) void panel_reg_kernel(int N, float *LU, int k0, int w, int *piv, int *info)
+{
+    __shared__ unsigned long long skey[16];
+    __shared__ float prow[W], jrow[W];
+    __shared__ int pivs[W];
+    __shared__ int sinfo;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    if (tid == 0) sinfo = 0;
+    float a[RT][W];
+#pragma unroll
+    for (int r = 0; r < RT; ++r) {
+        const int i = k0 + r * 1024 + tid;
+#pragma unroll
+        for (int c = 0; c < W; ++c) a[r][c] = (i < N && c < w) ? LU[int64_t(k0 + c) * N + i] : 0.0f;
+    }
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        if (j < w) {
+            const int gj = k0 + j;
+            // pivot key: |value| bits (monotone for non-negative floats) high, inverted row low,
+            // so the largest key is the largest magnitude with the lowest row on ties
+            unsigned long long key = 0ull;
+#pragma unroll
+            for (int r = 0; r < RT; ++r) {
+                const int i = k0 + r * 1024 + tid;
+                if (i >= gj && i < N) {
+                    const unsigned long long k = (static_cast<unsigned long long>(__float_as_uint(fabsf(a[r][j]))) << 32) |
+                                                 static_cast<unsigned int>(0x7fffffff - i);
+                    key = k > key ? k : key;
+                }
+            }
+            for (int off = 32; off > 0; off >>= 1) {
+                const unsigned long long o = __shfl_xor(key, off);
+                key = o > key ? o : key;
+            }
+            if (lane == 0) skey[wid] = key;
+            __syncthreads();
+            key = skey[lane & 15];
+            for (int off = 8; off > 0; off >>= 1) {
+                const unsigned long long o = __shfl_xor(key, off);
+                key = o > key ? o : key;
+            }
+            const float b = __uint_as_float(static_cast<unsigned int>(key >> 32));
+            int pr = 0x7fffffff - static_cast<int>(key & 0xffffffffull);
+            if (!(b > 0.0f)) pr = gj;
+            if (tid == 0) {
+                if (!(b > 0.0f) && sinfo == 0) sinfo = gj + 1;
+                pivs[j] = pr;
+            }
+#pragma unroll
+            for (int r = 0; r < RT; ++r) {
+                const int i = k0 + r * 1024 + tid;
+                if (i == pr) {
+#pragma unroll
+                    for (int c = 0; c < W; ++c) prow[c] = a[r][c];
+                }
+                if (i == gj) {
+#pragma unroll
+                    for (int c = 0; c < W; ++c) jrow[c] = a[r][c];
+                }
+            }
+            __syncthreads();
+            const float d = prow[j];
+            const float inv = d != 0.0f ? 1.0f / d : 0.0f;
+#pragma unroll
+            for (int r = 0; r < RT; ++r) {
+                const int i = k0 + r * 1024 + tid;
+                if (i == gj) {
+#pragma unroll
+                    for (int c = 0; c < W; ++c) a[r][c] = prow[c];
+                } else if (i == pr) {
+#pragma unroll
+                    for (int c = 0; c < W; ++c) a[r][c] = jrow[c];
+                }
+                if (i > gj && i < N && d != 0.0f) {
+                    const float l = a[r][j] * inv;
+                    a[r][j] = l;
+#pragma unroll
+                    for (int c = j + 1; c < W; ++c) a[r][c] -= l * prow[c];
+                }
+            }
+            // No third barrier: skey/prow/jrow of the next column are written only
+            // after the next column's first barrier, which every wavefront reaches
+            // after its last read of this column's values.
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RT; ++r) {
+        const int i = k0 + r * 1024 + tid;
+#pragma unroll
+        for (int c = 0; c < W; ++c)
+            if (i < N && c < w) LU[int64_t(k0 + c) * N + i] = a[r][c];
+    }
+    __syncthreads();
+    if (tid < w) piv[k0 + tid] = pivs[tid];
+    if (tid == 0 && sinfo != 0 && *info == 0) *info = sinfo;
+}
+
 // Apply the panel's interchanges to the columns outside it.
 __global__ void laswp_kernel(int N, float *LU, int k0, int w, const int *piv)
 {
@@ -229,49 +348,79 @@ __global__ __launch_bounds__(256) void gemm_update_kernel(int N, float *LU, int 
 // ---------------------------------------------------------------- triangular solves
 // One launch per 64-row block; every workgroup solves the diagonal block
 // (the same arithmetic in each) and then updates its own rows.
-__global__ __launch_bounds__(256) void trsv_lower_kernel(int N, const float *LU, float *y, int b0)
+// Inverses of the 64 x 64 diagonal blocks of L (unit lower) and U, kept so
+// that every block step of the triangular solves is a plain matrix-vector
+// product.  DI[b][0] = inv(L_bb), DI[b][1] = inv(U_bb), row-major 64 x 64;
+// a partial last block is padded with the identity.
+__global__ __launch_bounds__(64) void invert_diag_kernel(int N, const float *LU, float *DI)
 {
-    __shared__ float yb[64];
+    __shared__ float T[64][65];
+    __shared__ float X[64][65];
+    const int b0 = blockIdx.x * 64, bw = min(64, N - b0);
+    const int c = threadIdx.x;
+    for (int r = 0; r < 64; ++r) T[r][c] = (r < bw && c < bw) ? LU[int64_t(b0 + c) * N + b0 + r] : (r == c ? 1.0f : 0.0f);
+    __syncthreads();
+    // L X = I, column c: X[r][c] = delta_rc - sum_{k<r} L[r][k] X[k][c]
+    for (int r = 0; r < 64; ++r) {
+        float s = (r == c) ? 1.0f : 0.0f;
+        for (int k = 0; k < r; ++k) s -= T[r][k] * X[k][c];
+        X[r][c] = s;
+    }
+    for (int r = 0; r < 64; ++r) DI[(int64_t(blockIdx.x) * 2 + 0) * 4096 + r * 64 + c] = X[r][c];
+    __syncthreads();
+    // U X = I, column c: X[r][c] = (delta_rc - sum_{k>r} U[r][k] X[k][c]) / U[r][r]
+    for (int r = 63; r >= 0; --r) {
+        float s = (r == c) ? 1.0f : 0.0f;
+        for (int k = r + 1; k < 64; ++k) s -= T[r][k] * X[k][c];
+        X[r][c] = s / T[r][r];
+    }
+    for (int r = 0; r < 64; ++r) DI[(int64_t(blockIdx.x) * 2 + 1) * 4096 + r * 64 + c] = X[r][c];
+}
+
+// Forward step for the 64-row block at b0: x_b = inv(L_bb) y_b (computed by
+// every workgroup), written to yout by workgroup 0; rows below are updated in
+// y (rows of the block itself are only read in this launch).
+__global__ __launch_bounds__(256) void trsv_lower_kernel(int N, const float *LU, const float *DI, float *y, float *yout, int b0)
+{
+    __shared__ float yb[64], xb[64];
     const int bw = min(64, N - b0);
     const int tid = threadIdx.x;
+    if (tid < 64) yb[tid] = tid < bw ? y[b0 + tid] : 0.0f;
+    __syncthreads();
     if (tid < 64) {
-        float x = tid < bw ? y[b0 + tid] : 0.0f;
-        for (int s = 0; s < bw; ++s) {
-            const float xs = __shfl(x, s);
-            if (tid > s && tid < bw) x -= LU[int64_t(b0 + s) * N + b0 + tid] * xs;
-        }
-        yb[tid] = x;
-        if (blockIdx.x == 0 && tid < bw) y[b0 + tid] = x;
+        const float *row = DI + (int64_t(b0 / 64) * 2 + 0) * 4096 + tid * 64;
+        float s = 0.0f;
+        for (int k = 0; k < 64; ++k) s += row[k] * yb[k];
+        xb[tid] = s;
+        if (blockIdx.x == 0 && tid < bw) yout[b0 + tid] = s;
     }
     __syncthreads();
     const int r = b0 + bw + blockIdx.x * blockDim.x + tid;
     if (r < N) {
         float s = 0.0f;
-        for (int k = 0; k < bw; ++k) s += LU[int64_t(b0 + k) * N + r] * yb[k];
+        for (int k = 0; k < bw; ++k) s += LU[int64_t(b0 + k) * N + r] * xb[k];
         y[r] -= s;
     }
 }
 
-__global__ __launch_bounds__(256) void trsv_upper_kernel(int N, const float *LU, float *y, int b0, int bw)
+__global__ __launch_bounds__(256) void trsv_upper_kernel(int N, const float *LU, const float *DI, float *y, float *yout, int b0, int bw)
 {
-    __shared__ float yb[64];
+    __shared__ float yb[64], xb[64];
     const int tid = threadIdx.x;
+    if (tid < 64) yb[tid] = tid < bw ? y[b0 + tid] : 0.0f;
+    __syncthreads();
     if (tid < 64) {
-        float x = tid < bw ? y[b0 + tid] : 0.0f;
-        for (int s = bw - 1; s >= 0; --s) {
-            const float d = LU[int64_t(b0 + s) * N + b0 + s];
-            const float xs = __shfl(x, s) / d;
-            if (tid == s) x = xs;
-            if (tid < s) x -= LU[int64_t(b0 + s) * N + b0 + tid] * xs;
-        }
-        yb[tid] = x;
-        if (blockIdx.x == 0 && tid < bw) y[b0 + tid] = x;
+        const float *row = DI + (int64_t(b0 / 64) * 2 + 1) * 4096 + tid * 64;
+        float s = 0.0f;
+        for (int k = 0; k < 64; ++k) s += row[k] * yb[k];
+        xb[tid] = s;
+        if (blockIdx.x == 0 && tid < bw) yout[b0 + tid] = s;
     }
     __syncthreads();
     const int r = blockIdx.x * blockDim.x + tid;
     if (r < b0) {
         float s = 0.0f;
-        for (int k = 0; k < bw; ++k) s += LU[int64_t(b0 + k) * N + r] * yb[k];
+        for (int k = 0; k < bw; ++k) s += LU[int64_t(b0 + k) * N + r] * xb[k];
         y[r] -= s;
     }
 }
@@ -363,18 +512,35 @@ void launch_residual(int N, const void *A, int64_t lda, const double *x, const d
 
 size_t solve_workspace_bytes(int N)
 {
+    const size_t nblk = size_t(N + 63) / 64;
     return align_up(size_t(N) * N * sizeof(float)) + 2 * align_up(size_t(N) * sizeof(int)) + align_up(16) +
-           align_up(size_t(N) * sizeof(double)) + align_up(size_t(N) * sizeof(float)) + align_up(64 * sizeof(double)) +
-           align_up(size_t(N) * sizeof(double));
+           align_up(size_t(N) * sizeof(double)) + 2 * align_up(size_t(N) * sizeof(float)) + align_up(64 * sizeof(double)) +
+           align_up(size_t(N) * sizeof(double)) + align_up(nblk * 2 * 4096 * sizeof(float));
 }
 
-hipError_t lu_factor_f32(int N, float *LU, int *piv, int *info, void *, hipStream_t s)
+hipError_t lu_factor_f32(int N, float *LU, int *piv, int *info, void *diag_inv, hipStream_t s)
 {
-    hipError_t e = hipMemsetAsync(info, 0, sizeof(int), s);
-    if (e != hipSuccess) return e;
-    for (int k0 = 0; k0 < N; k0 += NB) {
-        const int w = std::min(NB, N - k0);
-        hipLaunchKernelGGL(panel_kernel, dim3(1), dim3(1024), 0, s, N, LU, k0, w, piv, info);
+    hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(64), 0, s, info);
+    for (int k0 = 0; k0 < N;) {
+        const int m = N - k0;
+        int w;
+        // register panels while the rows fit (1, 2, 4, 8 rows per thread), narrower as they grow
+        if (m <= 1024) {
+            w = std::min(32, m);
+            hipLaunchKernelGGL((panel_reg_kernel<1, 32>), dim3(1), dim3(1024), 0, s, N, LU, k0, w, piv, info);
+        } else if (m <= 2048) {
+            w = 16;
+            hipLaunchKernelGGL((panel_reg_kernel<2, 16>), dim3(1), dim3(1024), 0, s, N, LU, k0, w, piv, info);
+        } else if (m <= 4096) {
+            w = 8;
+            hipLaunchKernelGGL((panel_reg_kernel<4, 8>), dim3(1), dim3(1024), 0, s, N, LU, k0, w, piv, info);
+        } else if (m <= 8192) {
+            w = 8;
+            hipLaunchKernelGGL((panel_reg_kernel<8, 8>), dim3(1), dim3(1024), 0, s, N, LU, k0, w, piv, info);
+        } else {
+            w = 32;
+            hipLaunchKernelGGL(panel_kernel, dim3(1), dim3(1024), 0, s, N, LU, k0, w, piv, info);
+        }
         if (N - w > 0) hipLaunchKernelGGL(laswp_kernel, dim3((N - w + 255) / 256), dim3(256), 0, s, N, LU, k0, w, piv);
         const int rest = N - k0 - w;
         if (rest > 0) {
@@ -382,23 +548,29 @@ hipError_t lu_factor_f32(int N, float *LU, int *piv, int *info, void *, hipStrea
             const int nbk = (rest + 63) / 64;
             hipLaunchKernelGGL(gemm_update_kernel, dim3(nbk, nbk), dim3(256), 0, s, N, LU, k0, w);
         }
-        e = hipGetLastError();
+        hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
+        k0 += w;
     }
-    return hipSuccess;
+    if (diag_inv) hipLaunchKernelGGL(invert_diag_kernel, dim3((N + 63) / 64), dim3(64), 0, s, N, LU, static_cast<float *>(diag_inv));
+    return hipGetLastError();
 }
 
-hipError_t lu_solve_f32(int N, const float *LU, const int *, float *b, hipStream_t s)
+hipError_t lu_solve_f32(int N, const float *LU, const float *diag_inv, float *b, float *tmp, hipStream_t s)
 {
-    // b is already permuted (b := P b)
+    // b is already permuted (b := P b).
+    // forward: b is updated below each block, solved blocks go to tmp;
+    // backward: tmp is updated above each block, solved blocks go to b.
     for (int b0 = 0; b0 < N; b0 += 64) {
         const int rest = std::max(0, N - b0 - 64);
-        hipLaunchKernelGGL(trsv_lower_kernel, dim3(std::max(1, (rest + 255) / 256)), dim3(256), 0, s, N, LU, b, b0);
+        hipLaunchKernelGGL(trsv_lower_kernel, dim3(std::max(1, (rest + 255) / 256)), dim3(256), 0, s, N, LU, diag_inv,
+                           b, tmp, b0);
     }
     const int nblk = (N + 63) / 64;
     for (int bk = nblk - 1; bk >= 0; --bk) {
         const int b0 = bk * 64, bw = std::min(64, N - b0);
-        hipLaunchKernelGGL(trsv_upper_kernel, dim3(std::max(1, (b0 + 255) / 256)), dim3(256), 0, s, N, LU, b, b0, bw);
+        hipLaunchKernelGGL(trsv_upper_kernel, dim3(std::max(1, (b0 + 255) / 256)), dim3(256), 0, s, N, LU, diag_inv,
+                           tmp, b, b0, bw);
     }
     return hipGetLastError();
 }
@@ -416,13 +588,21 @@ int mixed_solve(int N, const void *d_A, int64_t lda, int a_prec, const double *d
         hipLaunchKernelGGL(to_colmajor_kernel<double>, tg, dim3(256), 0, s, N, static_cast<const double *>(d_A), lda, w.LU);
     else
         hipLaunchKernelGGL(to_colmajor_kernel<float>, tg, dim3(256), 0, s, N, static_cast<const float *>(d_A), lda, w.LU);
-    hipError_t e = lu_factor_f32(N, w.LU, w.piv, w.info, nullptr, s);
+    hipError_t e = lu_factor_f32(N, w.LU, w.piv, w.info, w.DI, s);
     if (e != hipSuccess) return fail(-5, "LU factorisation launch", e);
+    // ||A||_inf for the backward error (one read of A)
+    if (a_prec == 0)
+        hipLaunchKernelGGL(rowabs_kernel<double>, dim3((N + 3) / 4), dim3(256), 0, s, N, static_cast<const double *>(d_A), lda, w.red + 8);
+    else
+        hipLaunchKernelGGL(rowabs_kernel<float>, dim3((N + 3) / 4), dim3(256), 0, s, N, static_cast<const float *>(d_A), lda, w.red + 8);
+    hipLaunchKernelGGL(max_kernel, dim3(1), dim3(1024), 0, s, N, w.red + 8, w.red + 4);
     // permutation from the interchange sequence (host, O(N))
     std::vector<int> piv(N), perm(N);
     int info = 0;
+    double normA = 0.0;
     if ((e = hipMemcpyAsync(piv.data(), w.piv, N * sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess ||
         (e = hipMemcpyAsync(&info, w.info, sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(&normA, w.red + 4, sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess ||
         (e = hipStreamSynchronize(s)) != hipSuccess)
         return fail(-5, "LU factorisation", e);
     if (info != 0) return fail(-3, "zero pivot in the FP32 LU factorisation", hipSuccess);
@@ -438,34 +618,39 @@ int mixed_solve(int N, const void *d_A, int64_t lda, int a_prec, const double *d
     double red[4];
     // x0 = LU \ beta
     hipLaunchKernelGGL(permute_kernel, dim3((N + 255) / 256), dim3(256), 0, s, N, w.perm, d_beta, w.v);
-    (void)lu_solve_f32(N, w.LU, w.piv, w.v, s);
+    (void)lu_solve_f32(N, w.LU, w.DI, w.v, w.v2, s);
     hipLaunchKernelGGL(update_norms_kernel, dim3(1), dim3(1024), 0, s, N, d_x, w.v, d_beta, d_beta, 0, w.red);
     res.iters = 0;
     res.rel_update = 1.0;
+    res.backward_err = 1.0;
     int status = -4;
+    double prev = 1e300;
+    // Refinement: stop when ||d|| <= tol ||x||, or when the corrections stop
+    // shrinking (||d_k|| > ||d_{k-1}|| / 2: the FP64 residual has reached the
+    // cond(A) eps floor) with a backward error at the FP64 level.
     for (int it = 0; it < max_iter; ++it) {
         residual();
         hipLaunchKernelGGL(permute_kernel, dim3((N + 255) / 256), dim3(256), 0, s, N, w.perm, w.r, w.v);
-        (void)lu_solve_f32(N, w.LU, w.piv, w.v, s);
+        (void)lu_solve_f32(N, w.LU, w.DI, w.v, w.v2, s);
         hipLaunchKernelGGL(update_norms_kernel, dim3(1), dim3(1024), 0, s, N, d_x, w.v, w.r, d_beta, 1, w.red);
         if ((e = hipMemcpyAsync(red, w.red, sizeof red, hipMemcpyDeviceToHost, s)) != hipSuccess ||
             (e = hipStreamSynchronize(s)) != hipSuccess)
             return fail(-5, "refinement step", e);
         res.iters = it + 1;
         res.rel_update = red[1] > 0 ? red[0] / red[1] : 0.0;
+        res.backward_err = red[2] / (normA * red[1] + red[3]);   // of the iterate before this step
         if (res.rel_update <= tol) {
             status = 0;
             break;
         }
+        if (res.rel_update > 0.5 * prev && res.backward_err <= 64 * 1.1102230246251565e-16) {
+            status = 0;
+            break;
+        }
+        prev = res.rel_update;
     }
-    // backward error ||beta - A x||_inf / (||A||_inf ||x||_inf + ||beta||_inf)
+    // backward error of the returned x: ||beta - A x||_inf / (||A||_inf ||x||_inf + ||beta||_inf)
     residual();
-    if (a_prec == 0)
-        hipLaunchKernelGGL(rowabs_kernel<double>, dim3((N + 3) / 4), dim3(256), 0, s, N, static_cast<const double *>(d_A), lda, w.red + 8);
-    else
-        hipLaunchKernelGGL(rowabs_kernel<float>, dim3((N + 3) / 4), dim3(256), 0, s, N, static_cast<const float *>(d_A), lda, w.red + 8);
-    double *rowabs = w.red + 8;
-    hipLaunchKernelGGL(max_kernel, dim3(1), dim3(1024), 0, s, N, rowabs, w.red + 4);
     hipLaunchKernelGGL(max_kernel, dim3(1), dim3(1024), 0, s, N, w.r, w.red + 5);
     hipLaunchKernelGGL(max_kernel, dim3(1), dim3(1024), 0, s, N, d_x, w.red + 6);
     hipLaunchKernelGGL(max_kernel, dim3(1), dim3(1024), 0, s, N, d_beta, w.red + 7);
@@ -474,7 +659,6 @@ int mixed_solve(int N, const void *d_A, int64_t lda, int a_prec, const double *d
         (e = hipStreamSynchronize(s)) != hipSuccess)
         return fail(-5, "backward error", e);
     res.backward_err = nr[1] / (nr[0] * nr[2] + nr[3]);
-    if (max_iter == 0) status = -4;
     if (status != 0) return fail(-4, "iterative refinement did not reach the tolerance", hipSuccess);
     return 0;
 }
