@@ -17,6 +17,9 @@ Also measured in the same run (reported beside the headline value):
    solve), p50 / p99 over repeated requests;
  * the fused kernel's duration from HIP events on its stream -> roofline;
  * FP32 and FP64 throughput at N = 16384 (a star curve, one assembly each);
+ * a batch of 256 star curves (N in [128, 2048], p in {2, 3}, FP32) in one
+   autotuned persistent launch replayed from a HIP graph, against 256
+   sequential single-curve launches;
  * the CPU oracle (element-by-element, FP64, C + OpenMP) on a sample of rows.
 """
 from __future__ import annotations
@@ -75,6 +78,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-scale", action="store_true", help="skip the N = 16384 points")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 256-curve batch")
     ap.add_argument("--solves", type=int, default=60)
     ap.add_argument("--profile-run", action="store_true",
                     help="only K direct WQ assemblies of the workload and one 256 MiB device copy "
@@ -235,6 +239,58 @@ def main():
             del Ab
         torch.cuda.empty_cache()
 
+    # ---------------------------------------------------------------- batched persistent launch (256 stars)
+    batch = None
+    if not args.no_batch:
+        probs = synth.config_batch(256)
+        t0 = time.perf_counter()
+        brules = [ctx.rules(pb.p, pb.N, 1) for pb in probs]
+        t_brules = time.perf_counter() - t0
+        bouts = [torch.empty((pb.N, pb.N), dtype=torch.float32, device="cuda") for pb in probs]
+        hb = S.sgbem_batch_create(ctx.ctx, [pb.curve for pb in probs], brules, S.SGBEM_FP32,
+                                  [o.data_ptr() for o in bouts], [o.stride(0) for o in bouts])
+        cfg, tune_ms = S.sgbem_batch_tune(ctx.ctx, hb, 2)
+        entries = float(sum(pb.N * pb.N for pb in probs))
+        gb = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(gb, stream=stream):
+            S.sgbem_batch_assemble(ctx.ctx, hb)
+        gb.replay()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        reps = 5
+        e0.record(stream)
+        for _ in range(reps):
+            gb.replay()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_batch = e0.elapsed_time(e1) / reps
+        del gb
+        # 256 sequential single-curve launches: with a synchronisation after each, and back to back
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for pb, o in zip(probs, bouts):
+            ctx.assemble(pb.curve, pb.p, pb.N, "wq", precision="fp32", out=o)
+            torch.cuda.synchronize()
+        ms_seq_sync = (time.perf_counter() - t0) * 1e3
+        t0 = time.perf_counter()
+        for pb, o in zip(probs, bouts):
+            ctx.assemble(pb.curve, pb.p, pb.N, "wq", precision="fp32", out=o)
+        torch.cuda.synchronize()
+        ms_seq = (time.perf_counter() - t0) * 1e3
+        S.sgbem_batch_free(ctx.ctx, hb)
+        del bouts
+        torch.cuda.empty_cache()
+        cfgs = [(32, 8), (32, 16), (16, 8), (16, 4)]
+        batch = {"curves": len(probs), "entries": entries, "precision": "fp32",
+                 "batched_graph_ms": ms_batch, "entries_per_s": entries / (ms_batch * 1e-3),
+                 "sequential_sync_ms": ms_seq_sync, "sequential_ms": ms_seq,
+                 "speedup_vs_sequential_sync": ms_seq_sync / ms_batch, "speedup_vs_sequential": ms_seq / ms_batch,
+                 "tuned_tile": {"T": cfgs[cfg][0], "S": cfgs[cfg][1]}, "rules_build_s": t_brules}
+        log(f"[bench] batch of {len(probs)} stars ({entries:.3e} entries, FP32): one graph-replayed persistent launch "
+            f"{ms_batch:.3f} ms ({entries/(ms_batch*1e-3):.3e} entries/s), tuned T={cfgs[cfg][0]} S={cfgs[cfg][1]}; "
+            f"256 sequential launches {ms_seq:.3f} ms, with a sync each {ms_seq_sync:.3f} ms")
+
     # ---------------------------------------------------------------- CPU oracle
     cpu = None
     if not args.no_cpu_baseline:
@@ -289,6 +345,7 @@ def main():
                      "kernel": "fused WQ sweep-and-contract (FP64)", "kernel_us": kern_ms * 1e3,
                      "flops_per_launch": flops},
         "scale_N16384": scale,
+        "batch_256_stars": batch,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

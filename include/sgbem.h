@@ -48,6 +48,7 @@ typedef enum {
 
 typedef struct sgbem_ctx_s *sgbem_ctx;       /* one device + one HIP stream             */
 typedef struct sgbem_rules_s *sgbem_rules;   /* device-resident quadrature rules (p,N,R) */
+typedef struct sgbem_batch_s *sgbem_batch;   /* device-resident description of many curves */
 
 typedef enum { SGBEM_CURVE_BSPLINE = 0, SGBEM_CURVE_POLAR = 1 } sgbem_curve_kind;
 typedef enum { SGBEM_WQ = 0, SGBEM_EBE = 1 } sgbem_method;
@@ -200,6 +201,38 @@ sgbem_status sgbem_assemble(sgbem_ctx ctx, const sgbem_curve *curve, sgbem_rules
  */
 sgbem_status sgbem_rhs(sgbem_ctx ctx, const sgbem_curve *curve, sgbem_rules rules,
                        int32_t method, int32_t n_gauss, const double *d_g, double *d_beta);
+
+/* ---------------------------------------------------------------- batches */
+
+/*
+ * Describe a batch of n curves for the fast form (eqs. IK1e2, IK1e2_bis,
+ * Alg. 3), each with its own rules (n_ref = 1, p in {2, 3, 4}, any N) and its
+ * own output matrix d_A[b] (device, row-major, lda[b], FP64 or FP32 as
+ * `precision`).  Everything the launch needs (curve descriptions, rule
+ * pointers, support coefficients, the tile index space) is uploaded once to
+ * device memory owned by the batch, so sgbem_batch_assemble enqueues kernel
+ * launches only and can be captured in a HIP graph.  The rules handles and the
+ * output buffers must outlive the batch.  Curves: polar, or B-spline with at
+ * most 64 control points.  Synchronous.
+ * Errors: E_INVAL, E_UNSUPPORTED, E_NOMEM, E_DEVICE.
+ */
+sgbem_status sgbem_batch_create(sgbem_ctx ctx, int32_t n, const sgbem_curve *curves, const sgbem_rules *rules,
+                                int32_t precision, void *const *d_A, const int64_t *lda, sgbem_batch *out);
+
+/* Assemble every matrix of the batch: one geometry launch for all curves and
+ * one persistent launch that strides over the upper-triangle tiles of all
+ * matrices (curves of different degree and size in the same launch), with the
+ * tile shape chosen by sgbem_batch_tune (default: 32 x 32 tiles, 8-column
+ * strips).  Asynchronous; same results as sgbem_assemble per curve. */
+sgbem_status sgbem_batch_assemble(sgbem_ctx ctx, sgbem_batch batch);
+
+/* Autotuner: time every compiled tile shape (32x32 / 16x16 tiles, strips of
+ * 4 to 16 columns, grid sized from the kernel's occupancy) on this batch, reps
+ * launches each, keep the fastest for the batch and as the context's default
+ * for later batches of the same precision.  Synchronous; writes the outputs. */
+sgbem_status sgbem_batch_tune(sgbem_ctx ctx, sgbem_batch batch, int32_t reps, int32_t *best_cfg, double *best_ms);
+
+sgbem_status sgbem_batch_free(sgbem_ctx ctx, sgbem_batch batch);
 
 /* ---------------------------------------------------------------- solve */
 

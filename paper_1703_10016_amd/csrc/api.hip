@@ -14,6 +14,7 @@
 #include "kernels.hpp"
 #include "planner.hpp"
 #include "solve.hpp"
+#include "batch.hpp"
 
 namespace sgbem {
 hipError_t launch_wq_f64(int p, int P, const TileArgs &a, hipStream_t s);
@@ -69,15 +70,26 @@ struct sgbem_rules_s {
     float *d_inv_s2f = nullptr, *d_wsf = nullptr;
 };
 
+struct sgbem_batch_s {
+    int n = 0, prec = 0, max_npts = 0;
+    int total32 = 0, total16 = 0;
+    int cfg = 0, grid = 0;
+    BatchDev d{};
+    void *mem = nullptr;     // one device allocation holding the whole description
+};
+
 struct sgbem_ctx_s {
     int device = 0;
     hipStream_t stream = nullptr;
     DevBuf geo, geo16, nearL, params, solve_ws;
     std::vector<sgbem_rules_s *> rules;
+    std::vector<sgbem_batch_s *> batches;
     // geometry-independent element-by-element tables, uploaded once per key:
     // key p      -> u16, w16, mco, madj, M_p(a + u16)       (near pairs)
     // key 1000 + 64p + G -> RHS coefficients w_g M_p(a + u_g) without h
     std::map<int, double *> tables;
+    // autotuned batched tile configuration per precision (-1: not tuned yet)
+    int batch_cfg[2] = {-1, -1};
     // optional HIP-event timing of the main kernel of each call
     int timing = 0;
     std::vector<hipEvent_t> ev;
@@ -144,6 +156,45 @@ sgbem_status check_curve(const sgbem_curve *c)
         return set_err(SGBEM_E_INVAL, "unknown curve kind");
     }
     return SGBEM_OK;
+}
+
+// Device description of a curve whose arrays fit the inline storage.
+sgbem_status inline_curve(const sgbem_curve *cv, CurveDev &d)
+{
+    sgbem_status st = check_curve(cv);
+    if (st) return st;
+    std::memset(&d, 0, sizeof d);
+    d.kind = cv->kind;
+    d.inline_data = 1;
+    if (cv->kind == SGBEM_CURVE_BSPLINE) {
+        if (cv->n_ctrl > 64) return set_err(SGBEM_E_UNSUPPORTED, "batched curves need at most 64 control points");
+        d.degree = cv->degree;
+        d.n_ctrl = cv->n_ctrl;
+        std::memcpy(d.inl, cv->ctrl_xy, size_t(cv->n_ctrl) * 2 * sizeof(double));
+    } else {
+        d.r0 = cv->r0;
+        d.n_modes = cv->n_modes;
+        if (cv->n_modes > 0) {
+            std::memcpy(d.inl, cv->a, size_t(cv->n_modes) * sizeof(double));
+            std::memcpy(d.inl + 64, cv->phi, size_t(cv->n_modes) * sizeof(double));
+        }
+    }
+    return SGBEM_OK;
+}
+
+int batch_grid(sgbem_ctx c, int cfg, int prec, int total)
+{
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess || cus < 1) cus = 256;
+    const int g = batch_blocks_per_cu(cfg, prec) * cus;
+    return total < g ? (total > 0 ? total : 1) : g;
+}
+
+bool valid_batch(sgbem_ctx c, sgbem_batch b)
+{
+    for (auto *x : c->batches)
+        if (x == b) return true;
+    return false;
 }
 
 // Upload the curve's arrays and return the device description.
@@ -325,6 +376,10 @@ sgbem_status sgbem_ctx_destroy(sgbem_ctx c)
         if (b->ptr) (void)hipFree(b->ptr);
     for (auto &kv : c->tables) (void)hipFree(kv.second);
     for (auto *r : c->rules) free_rules(r);
+    for (auto *b : c->batches) {
+        (void)hipFree(b->mem);
+        delete b;
+    }
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     delete c;
     return SGBEM_OK;
@@ -574,6 +629,184 @@ sgbem_status sgbem_rhs(sgbem_ctx c, const sgbem_curve *curve, sgbem_rules r, int
     const double *dcoef = nullptr;
     if ((st = cached_table(c, 1000 + 64 * p + G, gauss_basis_coef(p, G), dcoef))) return st;
     HIPCHK(launch_rhs(N, grid.npts, G, 0, G * (p + 1), dcoef, 1.0 / N, J, d_g, d_beta, c->stream));
+    return SGBEM_OK;
+}
+
+sgbem_status sgbem_batch_create(sgbem_ctx c, int32_t n, const sgbem_curve *curves, const sgbem_rules *rules,
+                                int32_t precision, void *const *d_A, const int64_t *lda, sgbem_batch *out)
+{
+    if (!c || !curves || !rules || !d_A || !lda || !out || n < 1) return set_err(SGBEM_E_INVAL, "NULL argument or n < 1");
+    if (precision != SGBEM_FP64 && precision != SGBEM_FP32) return set_err(SGBEM_E_INVAL, "unknown precision");
+    *out = nullptr;
+    DeviceGuard g(c->device);
+    std::vector<CurveDev> cd(n);
+    std::vector<int> npts(n), deg(n), pre32(n + 1, 0), pre16(n + 1, 0);
+    std::vector<int64_t> goff(n);
+    std::vector<TileArgs> args(n);
+    std::vector<TileArgsF> argsf(n);
+    int64_t gsum = 0;
+    int max_npts = 0;
+    for (int b = 0; b < n; ++b) {
+        sgbem_rules r = rules[b];
+        if (!r || !valid_rules(c, r)) return set_err(SGBEM_E_INVAL, "batch: rules handle does not belong to this context");
+        if (r->R != 1 || r->p < 2 || r->p > 4)
+            return set_err(SGBEM_E_UNSUPPORTED, "batch: n_ref = 1 and p in {2, 3, 4} only");
+        if (!d_A[b] || lda[b] < r->N) return set_err(SGBEM_E_INVAL, "batch: NULL matrix or lda < N");
+        sgbem_status st = inline_curve(&curves[b], cd[b]);
+        if (st) return st;
+        npts[b] = int(r->npts);
+        deg[b] = r->p;
+        goff[b] = gsum;
+        gsum += r->npts;
+        if (npts[b] > max_npts) max_npts = npts[b];
+        const int64_t t32 = int64_t((r->N + 31) / 32) * ((r->N + 31) / 32 + 1) / 2;
+        const int64_t t16 = int64_t((r->N + 15) / 16) * ((r->N + 15) / 16 + 1) / 2;
+        if (int64_t(pre16[b]) + t16 > (int64_t(1) << 31) - 1) return set_err(SGBEM_E_INVAL, "batch: too many tiles");
+        pre32[b + 1] = pre32[b] + int(t32);
+        pre16[b + 1] = pre16[b] + int(t16);
+        TileArgs &ta = args[b];
+        std::memset(&ta, 0, sizeof ta);
+        ta.N = r->N;
+        ta.npts = int(r->npts);
+        ta.inv_s2 = r->d_inv_s2;
+        ta.ws = r->d_ws;
+        ta.inv_s2f = r->d_inv_s2f;
+        ta.wsf = r->d_wsf;
+        for (int q = 0; q < r->Q; ++q) {
+            ta.coefA[q] = r->w0[q];
+            ta.coefB[q] = r->bvals[q];
+            argsf[b].coefA[q] = float(r->w0[q]);
+            argsf[b].coefB[q] = float(r->bvals[q]);
+        }
+        ta.scale = -1.0 / (2.0 * kPi);
+        ta.out = d_A[b];
+        ta.lda = lda[b];
+    }
+    // one allocation: curves | npts | goff | args | argsf | deg | prefix32 | prefix16 | geometry
+    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+    const size_t o_curves = 0;
+    const size_t o_npts = o_curves + al(sizeof(CurveDev) * n);
+    const size_t o_goff = o_npts + al(sizeof(int) * n);
+    const size_t o_args = o_goff + al(sizeof(int64_t) * n);
+    const size_t o_argsf = o_args + al(sizeof(TileArgs) * n);
+    const size_t o_deg = o_argsf + al(sizeof(TileArgsF) * n);
+    const size_t o_p32 = o_deg + al(sizeof(int) * n);
+    const size_t o_p16 = o_p32 + al(sizeof(int) * (n + 1));
+    const size_t o_geo = o_p16 + al(sizeof(int) * (n + 1));
+    const size_t total_bytes = o_geo + al(sizeof(double) * 3 * size_t(gsum));
+    auto *bt = new (std::nothrow) sgbem_batch_s;
+    if (!bt) return set_err(SGBEM_E_NOMEM, "host allocation failed");
+    hipError_t e = hipMalloc(&bt->mem, total_bytes);
+    if (e != hipSuccess) {
+        delete bt;
+        return set_err(e == hipErrorOutOfMemory ? SGBEM_E_NOMEM : SGBEM_E_DEVICE, "batch allocation failed");
+    }
+    char *base = static_cast<char *>(bt->mem);
+    bt->d.curves = reinterpret_cast<CurveDev *>(base + o_curves);
+    bt->d.npts = reinterpret_cast<int *>(base + o_npts);
+    bt->d.goff = reinterpret_cast<int64_t *>(base + o_goff);
+    bt->d.args = reinterpret_cast<TileArgs *>(base + o_args);
+    bt->d.argsf = reinterpret_cast<TileArgsF *>(base + o_argsf);
+    bt->d.deg = reinterpret_cast<int *>(base + o_deg);
+    bt->d.prefix32 = reinterpret_cast<int *>(base + o_p32);
+    bt->d.prefix16 = reinterpret_cast<int *>(base + o_p16);
+    bt->d.geo = reinterpret_cast<double *>(base + o_geo);
+    for (int b = 0; b < n; ++b) {
+        args[b].X = bt->d.geo + 3 * goff[b];
+        args[b].Y = args[b].X + npts[b];
+        args[b].J = args[b].Y + npts[b];
+    }
+    struct Up {
+        void *dst;
+        const void *src;
+        size_t bytes;
+    } ups[] = {{bt->d.curves, cd.data(), sizeof(CurveDev) * n}, {bt->d.npts, npts.data(), sizeof(int) * n},
+               {bt->d.goff, goff.data(), sizeof(int64_t) * n}, {bt->d.args, args.data(), sizeof(TileArgs) * n},
+               {bt->d.argsf, argsf.data(), sizeof(TileArgsF) * n}, {bt->d.deg, deg.data(), sizeof(int) * n},
+               {bt->d.prefix32, pre32.data(), sizeof(int) * (n + 1)}, {bt->d.prefix16, pre16.data(), sizeof(int) * (n + 1)}};
+    for (const Up &u : ups) {
+        if ((e = hipMemcpy(u.dst, u.src, u.bytes, hipMemcpyHostToDevice)) != hipSuccess) {
+            (void)hipFree(bt->mem);
+            delete bt;
+            return set_err(SGBEM_E_DEVICE, std::string("batch upload: ") + hipGetErrorString(e));
+        }
+    }
+    bt->n = n;
+    bt->prec = precision;
+    bt->max_npts = max_npts;
+    bt->total32 = pre32[n];
+    bt->total16 = pre16[n];
+    bt->cfg = c->batch_cfg[precision] >= 0 ? c->batch_cfg[precision] : 0;
+    const int tot = kBatchConfigs[bt->cfg].T == 32 ? bt->total32 : bt->total16;
+    bt->grid = batch_grid(c, bt->cfg, precision, tot);
+    c->batches.push_back(bt);
+    *out = bt;
+    return SGBEM_OK;
+}
+
+sgbem_status sgbem_batch_assemble(sgbem_ctx c, sgbem_batch b)
+{
+    if (!c || !b || !valid_batch(c, b)) return set_err(SGBEM_E_INVAL, "batch handle does not belong to this context");
+    DeviceGuard g(c->device);
+    HIPCHK(launch_batch_geometry(b->d, b->n, b->max_npts, c->stream));
+    const int tot = kBatchConfigs[b->cfg].T == 32 ? b->total32 : b->total16;
+    sgbem_status st;
+    if ((st = mark(c))) return st;
+    HIPCHK(launch_batch_tiles(b->cfg, b->prec, b->d, b->n, tot, b->grid, c->stream));
+    if ((st = mark(c))) return st;
+    return SGBEM_OK;
+}
+
+sgbem_status sgbem_batch_tune(sgbem_ctx c, sgbem_batch b, int32_t reps, int32_t *best_cfg, double *best_ms)
+{
+    if (!c || !b || !valid_batch(c, b)) return set_err(SGBEM_E_INVAL, "batch handle does not belong to this context");
+    if (reps < 1) reps = 3;
+    DeviceGuard g(c->device);
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    double best = 1e300;
+    int bestc = 0;
+    HIPCHK(launch_batch_geometry(b->d, b->n, b->max_npts, c->stream));
+    for (int cfg = 0; cfg < kNumBatchConfigs; ++cfg) {
+        const int tot = kBatchConfigs[cfg].T == 32 ? b->total32 : b->total16;
+        const int grid = batch_grid(c, cfg, b->prec, tot);
+        HIPCHK(launch_batch_tiles(cfg, b->prec, b->d, b->n, tot, grid, c->stream));   // warm
+        HIPCHK(hipEventRecord(e0, c->stream));
+        for (int r = 0; r < reps; ++r) HIPCHK(launch_batch_tiles(cfg, b->prec, b->d, b->n, tot, grid, c->stream));
+        HIPCHK(hipEventRecord(e1, c->stream));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (ms / reps < best) {
+            best = ms / reps;
+            bestc = cfg;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    b->cfg = bestc;
+    b->grid = batch_grid(c, bestc, b->prec, kBatchConfigs[bestc].T == 32 ? b->total32 : b->total16);
+    c->batch_cfg[b->prec] = bestc;
+    if (best_cfg) *best_cfg = bestc;
+    if (best_ms) *best_ms = best;
+    return SGBEM_OK;
+}
+
+sgbem_status sgbem_batch_free(sgbem_ctx c, sgbem_batch b)
+{
+    if (!c) return set_err(SGBEM_E_INVAL, "ctx is NULL");
+    if (!b) return SGBEM_OK;
+    if (!valid_batch(c, b)) return set_err(SGBEM_E_INVAL, "batch handle does not belong to this context");
+    DeviceGuard g(c->device);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (size_t i = 0; i < c->batches.size(); ++i)
+        if (c->batches[i] == b) {
+            c->batches.erase(c->batches.begin() + i);
+            break;
+        }
+    (void)hipFree(b->mem);
+    delete b;
     return SGBEM_OK;
 }
 

@@ -1,0 +1,84 @@
+// Curve geometry at one parameter value (device side), shared by the single
+// and batched geometry kernels: f, f' and J = |f'| (eq. J).
+//  polar:   f = r(theta) (cos theta, sin theta), theta = 2 pi t, closed-form derivative;
+//  B-spline (periodic uniform knots, Section 3): de Boor's algorithm on the span
+//           containing n_ctrl t, and on the derivative curve with control points
+//           n_ctrl (Q_j - Q_{j-1}) at degree d-1.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace sgbem {
+
+__device__ __forceinline__ void eval_curve(const CurveDev &c, double t, double &x, double &y, double &J)
+{
+    const double *ca = c.inline_data ? c.inl : c.a;
+    const double *cphi = c.inline_data ? c.inl + 64 : c.phi;
+    const double *cq = c.inline_data ? c.inl : c.ctrl;
+    double dx, dy;
+    if (c.kind == 1) {
+        double sn, cs;
+        sincospi(2.0 * t, &sn, &cs);
+        const double th = 6.283185307179586476925286766559 * t;
+        double r = 1.0, dr = 0.0;
+        for (int k = 1; k <= c.n_modes; ++k) {
+            double sk, ck;
+            sincos(k * th + cphi[k - 1], &sk, &ck);
+            r += ca[k - 1] * ck;
+            dr -= k * ca[k - 1] * sk;
+        }
+        r *= c.r0;
+        dr *= c.r0;
+        x = r * cs;
+        y = r * sn;
+        dx = 6.283185307179586476925286766559 * (dr * cs - r * sn);
+        dy = 6.283185307179586476925286766559 * (dr * sn + r * cs);
+    } else {
+        const int d = c.degree, nc = c.n_ctrl;
+        const double u = t * nc;
+        int l = int(floor(u));
+        if (l >= nc) l = nc - 1;
+        if (l < 0) l = 0;
+        double px[8], py[8];
+        for (int i = 0; i <= d; ++i) {
+            int j = l - d + i;
+            j = ((j % nc) + nc) % nc;
+            px[i] = cq[2 * j];
+            py[i] = cq[2 * j + 1];
+        }
+        // derivative control points (degree d-1): n_ctrl (Q_j - Q_{j-1}), j = l-d+1 .. l
+        double qx[8], qy[8];
+        for (int i = 1; i <= d; ++i) {
+            qx[i - 1] = nc * (px[i] - px[i - 1]);
+            qy[i - 1] = nc * (py[i] - py[i - 1]);
+        }
+        // de Boor: B_j supported on [j, j + d + 1) in units of n_ctrl t
+        for (int r = 1; r <= d; ++r) {
+            for (int i = d; i >= r; --i) {
+                const int j = l - d + i;
+                const double al = (u - j) / double(d + 1 - r);
+                px[i] = (1.0 - al) * px[i - 1] + al * px[i];
+                py[i] = (1.0 - al) * py[i - 1] + al * py[i];
+            }
+        }
+        x = px[d];
+        y = py[d];
+        const int dd = d - 1;
+        for (int r = 1; r <= dd; ++r) {
+            for (int i = dd; i >= r; --i) {
+                const int j = l - dd + i;
+                const double al = (u - j) / double(dd + 1 - r);
+                qx[i] = (1.0 - al) * qx[i - 1] + al * qx[i];
+                qy[i] = (1.0 - al) * qy[i - 1] + al * qy[i];
+            }
+        }
+        dx = qx[dd];
+        dy = qy[dd];
+    }
+    J = sqrt(dx * dx + dy * dy);
+}
+
+
+}  // namespace sgbem

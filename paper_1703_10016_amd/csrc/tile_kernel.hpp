@@ -123,18 +123,18 @@ struct TileArgsF {          // FP32 copies of the per-support coefficients
     float coefB[64];
 };
 
-template <typename Real>
-__device__ __forceinline__ Real coef_a(const TileArgs &a, const TileArgsF &f, int q);
-template <>
-__device__ __forceinline__ double coef_a<double>(const TileArgs &a, const TileArgsF &, int q) { return a.coefA[q]; }
-template <>
-__device__ __forceinline__ float coef_a<float>(const TileArgs &, const TileArgsF &f, int q) { return f.coefA[q]; }
-template <typename Real>
-__device__ __forceinline__ Real coef_b(const TileArgs &a, const TileArgsF &f, int q);
-template <>
-__device__ __forceinline__ double coef_b<double>(const TileArgs &a, const TileArgsF &, int q) { return a.coefB[q]; }
-template <>
-__device__ __forceinline__ float coef_b<float>(const TileArgs &, const TileArgsF &f, int q) { return f.coefB[q]; }
+template <typename Real, typename Args, typename ArgsF>
+__device__ __forceinline__ Real coef_a(const Args &a, const ArgsF &f, int q)
+{
+    if constexpr (sizeof(Real) == 8) return a.coefA[q];
+    else return f.coefA[q];
+}
+template <typename Real, typename Args, typename ArgsF>
+__device__ __forceinline__ Real coef_b(const Args &a, const ArgsF &f, int q)
+{
+    if constexpr (sizeof(Real) == 8) return a.coefB[q];
+    else return f.coefB[q];
+}
 
 __device__ __forceinline__ void tile_coords(int nb, int b, int &bi, int &bj)
 {
@@ -148,8 +148,9 @@ __device__ __forceinline__ void tile_coords(int nb, int b, int &bi, int &bj)
     bj = r + (b - (r * nb - (r * (r - 1)) / 2));
 }
 
-template <int P, int Q, int S0, bool WQ, typename Real, typename OutT, int T, int S>
-__global__ __launch_bounds__(256) void tile_kernel(TileArgs a, TileArgsF af)
+// One T x T tile (bi <= bj) of one matrix: the whole sweep-and-contract.
+template <int P, int Q, int S0, bool WQ, typename Real, typename OutT, int T, int S, typename Args, typename ArgsF>
+__device__ __forceinline__ void tile_body(const Args &a, const ArgsF &af, int bi, int bj)
 {
     constexpr int L = P * (T - 1) + Q;     // points in each window
     constexpr int LT = 2 * L - 1;          // table slice for n2 - n1
@@ -168,9 +169,6 @@ __global__ __launch_bounds__(256) void tile_kernel(TileArgs a, TileArgsF af)
     if constexpr (kTableLog) build_log_tab(ltab);
 
     const int N = a.N, npts = a.npts;
-    const int nb = (N + T - 1) / T;
-    int bi, bj;
-    tile_coords(nb, blockIdx.x, bi, bj);
     const int I0 = bi * T, J0 = bj * T;
     const int start1 = (P * I0 + S0) % npts;
     const int start2 = (P * J0 + S0) % npts;
@@ -287,6 +285,16 @@ __global__ __launch_bounds__(256) void tile_kernel(TileArgs a, TileArgsF af)
             if (i < N && j < N) out[int64_t(i) * lda + j] = OutT(tileo[cl][rl]);
         }
     }
+    __syncthreads();   // LDS is reused by the next tile of a persistent block
+}
+
+template <int P, int Q, int S0, bool WQ, typename Real, typename OutT, int T, int S>
+__global__ __launch_bounds__(256) void tile_kernel(TileArgs a, TileArgsF af)
+{
+    const int nb = (a.N + T - 1) / T;
+    int bi, bj;
+    tile_coords(nb, blockIdx.x, bi, bj);
+    tile_body<P, Q, S0, WQ, Real, OutT, T, S>(a, af, bi, bj);
 }
 
 template <int P, int Q, int S0, bool WQ, typename Real, int T, int S>

@@ -70,6 +70,11 @@ def lib():
             "sgbem_assemble": [vp, cp, vp, i32, i32, i32, vp, i64],
             "sgbem_rhs": [vp, cp, vp, i32, i32, vp, vp],
             "sgbem_solve": [vp, i32, vp, i64, i32, vp, vp, dbl, i32, ctypes.POINTER(sgbem_solve_info)],
+            "sgbem_batch_create": [vp, i32, cp, ctypes.POINTER(vp), i32, ctypes.POINTER(vp), ctypes.POINTER(i64),
+                                   ctypes.POINTER(vp)],
+            "sgbem_batch_assemble": [vp, vp],
+            "sgbem_batch_tune": [vp, vp, i32, ctypes.POINTER(i32), ctypes.POINTER(dbl)],
+            "sgbem_batch_free": [vp, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -93,7 +98,8 @@ def exported_symbols():
     return ["sgbem_ctx_create", "sgbem_ctx_destroy", "sgbem_ctx_set_stream", "sgbem_ctx_set_timing",
             "sgbem_ctx_kernel_time", "sgbem_last_error", "sgbem_version",
             "sgbem_weights", "sgbem_rules_free", "sgbem_weights_host", "sgbem_nearfield_host", "sgbem_rhs_points",
-            "sgbem_assemble", "sgbem_rhs", "sgbem_solve"]
+            "sgbem_assemble", "sgbem_rhs", "sgbem_solve", "sgbem_batch_create", "sgbem_batch_assemble",
+            "sgbem_batch_tune", "sgbem_batch_free"]
 
 
 # ------------------------------------------------------------------ curve marshalling
@@ -211,3 +217,31 @@ def sgbem_solve(ctx, N, d_A_ptr, lda, a_prec, d_beta_ptr, d_x_ptr, tol=1e-12, ma
     if check:
         _check(st)
     return st, info
+
+
+def sgbem_batch_create(ctx, curves, rules, precision, d_A_ptrs, ldas):
+    """curves: list of curve descriptions; rules: list of handles; d_A_ptrs / ldas: lists."""
+    n = len(curves)
+    cs = [_as_curve(c) for c in curves]
+    arr = (sgbem_curve * n)(*[c.c for c in cs])
+    rl = (ctypes.c_void_p * n)(*[r.value for r in rules])
+    ptrs = (ctypes.c_void_p * n)(*d_A_ptrs)
+    ld = (ctypes.c_int64 * n)(*ldas)
+    h = ctypes.c_void_p()
+    _check(lib().sgbem_batch_create(ctx, n, arr, rl, int(precision), ptrs, ld, ctypes.byref(h)))
+    h._keep = (cs, arr)
+    return h
+
+
+def sgbem_batch_assemble(ctx, batch):
+    _check(lib().sgbem_batch_assemble(ctx, batch))
+
+
+def sgbem_batch_tune(ctx, batch, reps=3):
+    cfg, ms = ctypes.c_int32(), ctypes.c_double()
+    _check(lib().sgbem_batch_tune(ctx, batch, int(reps), ctypes.byref(cfg), ctypes.byref(ms)))
+    return cfg.value, ms.value
+
+
+def sgbem_batch_free(ctx, batch):
+    _check(lib().sgbem_batch_free(ctx, batch))
