@@ -285,25 +285,36 @@ std::vector<double> cyclic_band_solve(const std::vector<double> &g, int hb, int6
             }
         }
     }
+    // The columns of G11^{-1} G12 decay geometrically away from the wrap; values
+    // below 1e-290 are flushed to zero so that the substitutions never run on
+    // subnormal numbers (many times slower on the host, and far below rounding).
+    auto flush = [](double v) { return std::fabs(v) < 1e-290 ? 0.0 : v; };
     auto band_solve = [&](std::vector<double> &x, int nc) {   // x[k*nc + c], in place
         for (int64_t k = 0; k < m1; ++k) {
             for (int c = 0; c < nc; ++c) {
                 double s = x[k * nc + c];
                 for (int64_t i = std::max<int64_t>(0, k - hb); i < k; ++i) s -= Lb[k * (hb + 1) + (i - k + hb)] * x[i * nc + c];
-                x[k * nc + c] = s / Lb[k * (hb + 1) + hb];
+                x[k * nc + c] = flush(s / Lb[k * (hb + 1) + hb]);
             }
         }
         for (int64_t k = m1 - 1; k >= 0; --k) {
             for (int c = 0; c < nc; ++c) {
                 double s = x[k * nc + c];
                 for (int64_t i = k + 1; i <= std::min<int64_t>(m1 - 1, k + hb); ++i) s -= Lb[i * (hb + 1) + (k - i + hb)] * x[i * nc + c];
-                x[k * nc + c] = s / Lb[k * (hb + 1) + hb];
+                x[k * nc + c] = flush(s / Lb[k * (hb + 1) + hb]);
             }
         }
     };
     // X = G11^{-1} G12, z = G11^{-1} rhs1
-    std::vector<double> X(m1 * hb);
-    for (int64_t k = 0; k < m1; ++k)
+    // G12 couples the last hb unknowns only to rows within hb of the wrap:
+    // k < 2 hb or k >= m1 - 2 hb (every other entry of G12 is zero).
+    std::vector<int64_t> wrap_rows;
+    for (int64_t k = 0; k < m1; ++k) {
+        if (k == 2 * hb && m1 - 2 * hb > k) k = m1 - 2 * hb;
+        wrap_rows.push_back(k);
+    }
+    std::vector<double> X(m1 * hb, 0.0);
+    for (int64_t k : wrap_rows)
         for (int c = 0; c < hb; ++c) X[k * hb + c] = Gent(k, m1 + c);
     band_solve(X, hb);
     std::vector<double> z(m1 * nrhs);
@@ -315,7 +326,7 @@ std::vector<double> cyclic_band_solve(const std::vector<double> &g, int hb, int6
     for (int a = 0; a < hb; ++a) {
         for (int b = 0; b < hb; ++b) {
             double s = Gent(m1 + a, m1 + b);
-            for (int64_t k = 0; k < m1; ++k) {
+            for (int64_t k : wrap_rows) {
                 const double gk = Gent(k, m1 + a);
                 if (gk != 0.0) s -= gk * X[k * hb + b];
             }
@@ -323,7 +334,7 @@ std::vector<double> cyclic_band_solve(const std::vector<double> &g, int hb, int6
         }
         for (int r = 0; r < nrhs; ++r) {
             double s = rhs[(m1 + a) * nrhs + r];
-            for (int64_t k = 0; k < m1; ++k) {
+            for (int64_t k : wrap_rows) {
                 const double gk = Gent(k, m1 + a);
                 if (gk != 0.0) s -= gk * z[k * nrhs + r];
             }
@@ -413,34 +424,73 @@ WQRules build_wq_rules(int p, int N, int R)
     for (int q = 0; q < Q; ++q) W.bvals[q] = Mp((q + 1) / (2.0 * R));
 
     // ---- Alg. 2 for the two source classes s = 0 and s = 1/(2M).
-    // modified moments mu_k(s) = int Bbar_k(t) ln|sin(pi (t - s)) / pi| dt, piece by
-    // piece: ln|x| part by int_poly_log, ln sinc(x) part by 16-point Gauss.
+    // modified moments mu_k(s) = int Bbar_k(t) ln|sin(pi (t - s)) / pi| dt, summed
+    // over the p + 1 elements of supp Bbar_k.  On element e, in its local
+    // coordinate u (t = (e + u) / M) with sigma the local coordinate of the image of
+    // s nearest the element, the piece integrals
+    //   I[e][c] = int_0^1 P_c(u) ln|sin(pi (u - sigma) / M) / pi| du,  c = 0..p,
+    // are computed once per element:
+    //  * |sigma - 1/2| <= 1 (s on the element or half an element away): split into
+    //    ln|u - sigma| (int_poly_log) - ln M + ln sinc(pi (u - sigma) / M) (16-point Gauss);
+    //  * otherwise the integrand is analytic on the element with its singularity at
+    //    least one element away: one Gauss rule for the whole kernel, 12 points
+    //    when the singularity is within 3 elements, 8 points beyond (both reach the
+    //    rounding floor for polynomial pieces up to degree 6 at those distances).
+    // The kernel values at the Gauss points are shared by all p + 1 pieces.
     const Rules16 &RR = rules16();
     std::vector<double> pint(p + 1, 0.0);
     for (int c = 0; c <= p; ++c)
         for (int a = 0; a <= p; ++a) pint[c] += pc[c * (p + 1) + a] / (a + 1.0);
-    std::vector<double> sincpart(p + 1);
+    double gx12[12], gw12[12], gx8[8], gw8[8];
+    gauss_legendre01(12, gx12, gw12);
+    gauss_legendre01(8, gx8, gw8);
+    // weighted piece values w_g P_c(u_g) for both far rules
+    std::vector<double> wp12((p + 1) * 12), wp8((p + 1) * 8);
+    for (int c = 0; c <= p; ++c) {
+        for (int g = 0; g < 12; ++g) wp12[c * 12 + g] = gw12[g] * horner(&pc[c * (p + 1)], p, gx12[g]);
+        for (int g = 0; g < 8; ++g) wp8[c * 8 + g] = gw8[g] * horner(&pc[c * (p + 1)], p, gx8[g]);
+    }
     std::vector<double> mom(M * 2, 0.0);
+    std::vector<double> I(size_t(M) * (p + 1));
     const double lnM = std::log(double(M));
+    const double inv_pi = 1.0 / kPi;
     for (int par = 0; par < 2; ++par) {
+        for (int64_t e = 0; e < M; ++e) {
+            const double s0 = 0.5 * par - double(e);
+            const double s1 = s0 + double(M);
+            const double sigma = (std::fabs(s0 - 0.5) <= std::fabs(s1 - 0.5)) ? s0 : s1;
+            double *Ie = &I[size_t(e) * (p + 1)];
+            const double dist = std::fabs(sigma - 0.5) - 0.5;   // element lengths from s to the element
+            if (dist <= 0.5) {
+                for (int c = 0; c <= p; ++c) {
+                    const double *cc = &pc[c * (p + 1)];
+                    double sp = 0.0;
+                    for (int g = 0; g < 16; ++g) {
+                        const double x = (RR.gl_x[g] - sigma) / double(M);
+                        const double px = kPi * x;
+                        const double sinc = (px == 0.0) ? 1.0 : std::sin(px) / px;
+                        sp += RR.gl_w[g] * horner(cc, p, RR.gl_x[g]) * std::log(sinc);
+                    }
+                    Ie[c] = int_poly_log(cc, p, sigma) - lnM * pint[c] + sp;
+                }
+                continue;
+            }
+            const bool close = dist < 3.0;
+            const int ng = close ? 12 : 8;
+            const double *gx = close ? gx12 : gx8;
+            const double *wp = close ? wp12.data() : wp8.data();
+            double kv[12];
+            for (int g = 0; g < ng; ++g)
+                kv[g] = std::log(std::fabs(std::sin(kPi * ((gx[g] - sigma) / double(M)))) * inv_pi);
+            for (int c = 0; c <= p; ++c) {
+                double s = 0.0;
+                for (int g = 0; g < ng; ++g) s += wp[c * ng + g] * kv[g];
+                Ie[c] = s;
+            }
+        }
         for (int64_t k = 0; k < M; ++k) {
             double acc = 0.0;
-            for (int c = 0; c <= p; ++c) {
-                const int64_t e = (k + c) % M;
-                // local coordinate of the image of s nearest the element: sigma = M s* - e
-                const double s0 = 0.5 * par - double(e);
-                const double s1 = s0 + double(M);
-                const double sigma = (std::fabs(s0 - 0.5) <= std::fabs(s1 - 0.5)) ? s0 : s1;
-                const double *cc = &pc[c * (p + 1)];
-                double sp = 0.0;
-                for (int g = 0; g < 16; ++g) {
-                    const double x = (RR.gl_x[g] - sigma) / double(M);
-                    const double px = kPi * x;
-                    const double sinc = (px == 0.0) ? 1.0 : std::sin(px) / px;
-                    sp += RR.gl_w[g] * horner(cc, p, RR.gl_x[g]) * std::log(sinc);
-                }
-                acc += int_poly_log(cc, p, sigma) - lnM * pint[c] + sp;
-            }
+            for (int c = 0; c <= p; ++c) acc += I[size_t((k + c) % M) * (p + 1) + c];
             mom[k * 2 + par] = acc / double(M);
         }
     }
@@ -453,13 +503,17 @@ WQRules build_wq_rules(int p, int N, int R)
     // w = B^T y (minimum-norm solution), then the translation-invariant tables.
     W.ws.assign(2 * W.n_nodes, 0.0);
     const int64_t n2 = W.n_nodes;
+    // M_p at the half-integers x = j / 2, j = 0..2p+3 (zero outside (0, p+1))
+    std::vector<double> mh(2 * p + 4);
+    for (int j = 0; j < 2 * p + 4; ++j) mh[j] = Mp(0.5 * j);
     for (int par = 0; par < 2; ++par) {
         std::vector<double> wv(n2, 0.0);
         for (int64_t n = 0; n < n2; ++n) {
             const int64_t kh = n / 2;
             double s = 0.0;
             for (int64_t k = kh - p - 1; k <= kh; ++k) {
-                const double b = Mp(0.5 * double(n) - double(k));
+                const int64_t j = n - 2 * k;   // 2 (n/2 - k)
+                const double b = (j > 0 && j < 2 * p + 4) ? mh[j] : 0.0;
                 if (b != 0.0) s += b * y[(((k % M) + M) % M) * 2 + par];
             }
             wv[n] = s;
