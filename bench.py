@@ -70,6 +70,69 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def serve_sweep(S, rates, n_req, workers):
+    """Open-loop serving: for each rate, n_req star requests with Poisson
+    arrivals (N log-uniform in [256, 8192], p in {2, 3, 4}) go to one server;
+    each is assembled (fast form, FP64), its right-hand side formed and solved
+    (FP32 LU + FP64 refinement).  Latency runs from the request's arrival to
+    alpha in host memory; solves/s is completions over the span from the
+    first arrival to the last completion."""
+    import synth
+    budget = 24 << 30
+    srv = S.sgbem_server_create(workers=workers, budget_bytes=budget, precision=S.SGBEM_FP64, max_N=8192,
+                                max_rules=512, max_iter=30, tol=1e-12)
+    out = {"workers": workers, "budget_bytes": budget, "requests_per_rate": n_req, "matrix_precision": "fp64",
+           "rates": []}
+    try:
+        # warm every kernel the path launches (one request per degree), untimed
+        warm = [(synth.star(1), p, 512) for p in (2, 3, 4)]
+        xw = [np.zeros(512) for _ in warm]
+        for i, (cv, p, N) in enumerate(warm):
+            xy = S.sgbem_node_points_host(cv, N, 1)
+            S.sgbem_server_submit(srv, cv, p, N, synth.g_exp_cos(xy[:, 0], xy[:, 1]), xw[i], 0.0, i)
+        _serve_drain(S, srv, len(warm))
+        for rate in rates:
+            arrivals, probs = synth.config_serving(rate, n_req)
+            gs = []
+            for pb in probs:   # the client's boundary data at the fast form's node points
+                xy = S.sgbem_node_points_host(pb.curve, pb.N, 1)
+                gs.append(pb.g(xy[:, 0], xy[:, 1]))
+            xs = [np.zeros(pb.N) for pb in probs]
+            before = S.sgbem_server_stats(srv)
+            t0 = S.sgbem_server_clock(srv) + 0.05
+            for i, pb in enumerate(probs):
+                S.sgbem_server_submit(srv, pb.curve, pb.p, pb.N, gs[i], xs[i], t0 + float(arrivals[i]), i)
+            comp = _serve_drain(S, srv, len(probs))
+            after = S.sgbem_server_stats(srv)
+            ok = [c for c in comp if c.status == 0]
+            lat = np.array([c.t_done - c.t_arrival for c in ok]) * 1e3
+            span = max(c.t_done for c in comp) - t0
+            row = {"rate": rate, "completed": len(comp), "ok": len(ok),
+                   "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                   "solves_per_s": len(comp) / span,
+                   "mean_entries": float(np.mean([pb.N ** 2 for pb in probs])),
+                   "mean_queue_ms": float(np.mean([(c.t_admit - c.t_arrival) * 1e3 for c in ok])),
+                   "peak_in_flight": after["peak_in_flight"], "peak_bytes": after["peak_bytes"],
+                   "rules_misses": after["rules_misses"] - before["rules_misses"]}
+            out["rates"].append(row)
+            log(f"[bench] serving rate {rate:g}/s x {n_req}: p50 {row['p50_ms']:.2f} ms p99 {row['p99_ms']:.2f} ms, "
+                f"{row['solves_per_s']:.1f} solves/s, queue {row['mean_queue_ms']:.1f} ms, "
+                f"{len(ok)}/{len(comp)} ok")
+    finally:
+        S.sgbem_server_destroy(srv)
+    return out
+
+
+def _serve_drain(S, srv, n, timeout=600.0):
+    got = []
+    t_end = time.time() + timeout
+    while len(got) < n:
+        if time.time() > t_end:
+            raise RuntimeError(f"serving: {len(got)} of {n} completions before the time limit")
+        got += S.sgbem_server_poll(srv, 256, 1.0)
+    return got
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -79,6 +142,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-scale", action="store_true", help="skip the N = 16384 points")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-curve batch")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop sweep")
+    ap.add_argument("--serve-requests", type=int, default=100, help="requests per arrival rate (2000: full sweep)")
+    ap.add_argument("--serve-rates", type=str, default="10,30,100,300,1000", help="arrival rates, req/s")
+    ap.add_argument("--serve-workers", type=int, default=8)
     ap.add_argument("--solves", type=int, default=60)
     ap.add_argument("--profile-run", action="store_true",
                     help="only K direct WQ assemblies of the workload and one 256 MiB device copy "
@@ -291,6 +358,12 @@ def main():
             f"{ms_batch:.3f} ms ({entries/(ms_batch*1e-3):.3e} entries/s), tuned T={cfgs[cfg][0]} S={cfgs[cfg][1]}; "
             f"256 sequential launches {ms_seq:.3f} ms, with a sync each {ms_seq_sync:.3f} ms")
 
+    # ---------------------------------------------------------------- serving loop (Poisson arrivals)
+    serving = None
+    if not args.no_serving:
+        serving = serve_sweep(S, [float(r) for r in args.serve_rates.split(",")], args.serve_requests,
+                              args.serve_workers)
+
     # ---------------------------------------------------------------- CPU oracle
     cpu = None
     if not args.no_cpu_baseline:
@@ -346,6 +419,7 @@ def main():
                      "flops_per_launch": flops},
         "scale_N16384": scale,
         "batch_256_stars": batch,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

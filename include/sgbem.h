@@ -172,6 +172,15 @@ sgbem_status sgbem_rhs_points(sgbem_ctx ctx, const sgbem_curve *curve, sgbem_rul
                               double *d_xy, int64_t cap, int64_t *count);
 
 /*
+ * Host-only: the fast form's node points f(eta_n), eta_n = n / (2 n_ref N),
+ * n = 0 .. 2 n_ref N - 1 (Section 5), written to xy as [2 n_ref N][2] FP64, by
+ * the same curve evaluation as the device's (last-bit differences in the
+ * trigonometric functions are possible).  For clients that sample g on the host
+ * (sgbem_rhs with SGBEM_WQ, sgbem_server_submit).  Errors: E_INVAL.
+ */
+sgbem_status sgbem_node_points_host(const sgbem_curve *curve, int32_t N, int32_t n_ref, double *xy);
+
+/*
  * Assemble the N x N Galerkin matrix into device memory d_A (row-major, lda,
  * FP64 `double` or FP32 `float` as `precision` says).  Asynchronous.
  *  WQ (fast form): eqs. IK1e2 and IK1e2_bis by row assembly and sum
@@ -253,6 +262,96 @@ sgbem_status sgbem_batch_free(sgbem_ctx ctx, sgbem_batch batch);
 sgbem_status sgbem_solve(sgbem_ctx ctx, int32_t N, const void *d_A, int64_t lda, int32_t a_prec,
                          const double *d_beta, double *d_x, double tol, int32_t max_iter,
                          sgbem_solve_info *info);
+
+/* ---------------------------------------------------------------- serving */
+
+/*
+ * Continuous-batching server: a stream of independent problems (curve, p, N,
+ * Dirichlet data), each assembled by the fast form in the configured precision
+ * (eqs. IK1e2, IK1e2_bis, Alg. 3), its right-hand side formed (eq. final_b1)
+ * and the system (eq. sistlin) solved like sgbem_solve.  Threads of the library
+ * do the work: a dispatcher releases each request at its arrival time and
+ * admits it, first in first out, when one of `workers` slots is free and its
+ * device footprint fits into the free space of a device arena of
+ * `budget_bytes` (allocated once at creation; nothing is allocated per
+ * request).  Each slot is a host thread with its own HIP stream, so the kernels
+ * of admitted requests overlap on the device.  Quadrature rules are built on
+ * first use of a (p, N) by the slot that needs them and kept in a device cache
+ * of `max_rules` entries (least recently used evicted when unused).
+ * Per-request results are the same as running the request alone.
+ */
+typedef struct sgbem_server_s *sgbem_server;
+
+typedef struct {
+    int32_t device;
+    int32_t workers;        /* concurrent requests, 1 .. 64                        */
+    int64_t budget_bytes;   /* device arena for admitted requests                 */
+    int32_t precision;      /* storage of the assembled matrix (SGBEM_FP64 / FP32) */
+    int32_t max_N;          /* largest N accepted                                 */
+    int32_t max_rules;      /* rule-cache entries, at least 2 workers + 1         */
+    int32_t max_iter;       /* refinement limit of each solve                     */
+    double tol;             /* refinement tolerance of each solve                 */
+} sgbem_server_config;
+
+typedef struct {
+    sgbem_curve curve;      /* copied by submit (arrays included)                 */
+    int32_t p;              /* spline degree, 1 .. 6                              */
+    int32_t N;              /* elements, 2 (p + 1) .. max_N                       */
+    const double *g;        /* host [2N]: g(f(n / 2N)), see sgbem_node_points_host; copied */
+    double *x;              /* host [N]: alpha, written before the completion is posted */
+    double arrival_s;       /* release time on the server clock (sgbem_server_clock) */
+    uint64_t tag;           /* returned with the completion                       */
+} sgbem_request;
+
+typedef struct {
+    uint64_t tag;
+    int32_t status;         /* sgbem_status of the request                        */
+    int32_t iters;          /* refinement steps                                   */
+    double t_arrival;       /* server clock, seconds: release ...                 */
+    double t_admit;         /*   ... admission (memory and slot granted) ...      */
+    double t_done;          /*   ... result in x                                  */
+    double backward_err;
+    int64_t footprint;      /* device bytes the request held                      */
+    char message[96];       /* error text when status != SGBEM_OK                 */
+} sgbem_completion;
+
+typedef struct {
+    int64_t submitted, rejected, completed, failed;
+    int32_t waiting;        /* submitted, not admitted (released or not)          */
+    int32_t in_flight;      /* admitted, not completed                            */
+    int32_t peak_in_flight;
+    int32_t rules_cached;
+    int64_t arena_bytes;    /* budget_bytes                                       */
+    int64_t peak_bytes;     /* high-water mark of the admitted footprints         */
+    int64_t rules_hits, rules_misses;
+} sgbem_server_info;
+
+/* Device bytes one request of size N holds while admitted (host-only):
+ * A (N^2 in the matrix precision) + the solve workspace (4 N^2 + O(N)) + g,
+ * beta and x, each part 256-byte aligned.  Errors: E_INVAL. */
+sgbem_status sgbem_server_footprint(int32_t N, int32_t precision, int64_t *bytes);
+
+/* Create the server (allocates the arenas, starts the threads).
+ * Errors: E_INVAL (a field out of range), E_NOMEM, E_DEVICE. */
+sgbem_status sgbem_server_create(const sgbem_server_config *config, sgbem_server *out);
+
+/* Queue a request.  Rejected with E_NOMEM when its footprint exceeds the
+ * arena (it could never be admitted), E_INVAL / E_UNSUPPORTED for bad
+ * arguments; a rejected request produces no completion. */
+sgbem_status sgbem_server_submit(sgbem_server s, const sgbem_request *req);
+
+/* Move up to cap completions into out (oldest first), waiting up to
+ * timeout_s seconds for the first one.  *n receives the number moved. */
+sgbem_status sgbem_server_poll(sgbem_server s, sgbem_completion *out, int32_t cap, double timeout_s, int32_t *n);
+
+/* Seconds since the server was created (the clock of arrival_s and t_*). */
+sgbem_status sgbem_server_clock(sgbem_server s, double *now_s);
+
+sgbem_status sgbem_server_stats(sgbem_server s, sgbem_server_info *out);
+
+/* Stop: requests not yet admitted are dropped (no completion), admitted ones
+ * finish; then the threads end and the arenas are freed. */
+sgbem_status sgbem_server_destroy(sgbem_server s);
 
 #ifdef __cplusplus
 }

@@ -17,7 +17,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsgbem.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-HIP_UNITS = ["api.hip", "kernels.hip", "solve.hip", "batch.hip",
+HIP_UNITS = ["api.hip", "kernels.hip", "solve.hip", "batch.hip", "serve.hip",
              "asm_wq_f64.hip", "asm_wq_f32.hip", "asm_ebe_f64.hip", "asm_ebe_f32.hip"]
 CXX_UNITS = ["planner.cpp"]
 # the register-resident LU panel needs its 64 x 64 column loop fully unrolled
@@ -53,7 +53,7 @@ def build(jobs: int = 8, verbose: bool = False) -> str:
             if verbose and out.strip():
                 print(out)
     tmp = LIB + ".tmp%d" % os.getpid()
-    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs)
+    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", "-o", tmp] + objs)
     os.replace(tmp, LIB)
     return LIB
 

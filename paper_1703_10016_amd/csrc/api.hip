@@ -11,10 +11,12 @@
 #include <vector>
 
 #include "../../include/sgbem.h"
+#include "ctx.hpp"
 #include "kernels.hpp"
 #include "planner.hpp"
 #include "solve.hpp"
 #include "batch.hpp"
+#include "curve_eval.hpp"
 
 namespace sgbem {
 hipError_t launch_wq_f64(int p, int P, const TileArgs &a, hipStream_t s);
@@ -39,64 +41,15 @@ using namespace sgbem;
 
 namespace {
 thread_local std::string g_err;
-constexpr double kPi = 3.14159265358979323846264338327950288;
+}  // namespace
+
+namespace sgbem {
 
 sgbem_status set_err(sgbem_status st, const std::string &m)
 {
     g_err = m;
     return st;
 }
-
-#define HIPCHK(call)                                                                       \
-    do {                                                                                   \
-        hipError_t e_ = (call);                                                            \
-        if (e_ != hipSuccess)                                                              \
-            return set_err(e_ == hipErrorOutOfMemory ? SGBEM_E_NOMEM : SGBEM_E_DEVICE,     \
-                           std::string(#call) + ": " + hipGetErrorString(e_));             \
-    } while (0)
-
-// Grow-only device buffer owned by a context.
-struct DevBuf {
-    void *ptr = nullptr;
-    size_t bytes = 0;
-};
-}  // namespace
-
-struct sgbem_rules_s {
-    int p = 0, N = 0, R = 0, Q = 0;
-    int64_t M = 0, npts = 0;
-    std::vector<double> w0, bvals;
-    double *d_inv_s2 = nullptr, *d_ws = nullptr, *d_w0 = nullptr;
-    float *d_inv_s2f = nullptr, *d_wsf = nullptr;
-};
-
-struct sgbem_batch_s {
-    int n = 0, prec = 0, max_npts = 0;
-    int total32 = 0, total16 = 0;
-    int cfg = 0, grid = 0;
-    BatchDev d{};
-    void *mem = nullptr;     // one device allocation holding the whole description
-};
-
-struct sgbem_ctx_s {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    DevBuf geo, geo16, nearL, params, solve_ws;
-    std::vector<sgbem_rules_s *> rules;
-    std::vector<sgbem_batch_s *> batches;
-    // geometry-independent element-by-element tables, uploaded once per key:
-    // key p      -> u16, w16, mco, madj, M_p(a + u16)       (near pairs)
-    // key 1000 + 64p + G -> RHS coefficients w_g M_p(a + u_g) without h
-    std::map<int, double *> tables;
-    // autotuned batched tile configuration per precision (-1: not tuned yet)
-    int batch_cfg[2] = {-1, -1};
-    // optional HIP-event timing of the main kernel of each call
-    int timing = 0;
-    std::vector<hipEvent_t> ev;
-    size_t ev_used = 0;
-};
-
-namespace {
 
 sgbem_status ensure(sgbem_ctx c, DevBuf &b, size_t bytes)
 {
@@ -114,30 +67,98 @@ sgbem_status ensure(sgbem_ctx c, DevBuf &b, size_t bytes)
     return SGBEM_OK;
 }
 
-struct DeviceGuard {
-    int prev = -1;
-    explicit DeviceGuard(int dev)
-    {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (prev != dev) (void)hipSetDevice(dev);
-    }
-    ~DeviceGuard()
-    {
-        if (prev >= 0) (void)hipSetDevice(prev);
-    }
-};
+namespace {
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+}  // namespace
+
+size_t rules_block_bytes(int64_t npts)
+{
+    const size_t n = size_t(npts);
+    return align256(n * 8) + align256(2 * n * 8) + align256(64 * 8) + align256(n * 4) + align256(2 * n * 4);
+}
 
 void free_rules(sgbem_rules r)
 {
     if (!r) return;
-    (void)hipFree(r->d_inv_s2);
-    (void)hipFree(r->d_ws);
-    (void)hipFree(r->d_w0);
-    (void)hipFree(r->d_inv_s2f);
-    (void)hipFree(r->d_wsf);
+    if (r->owned) (void)hipFree(r->block);
     delete r;
 }
 
+sgbem_status make_rules(int p, int N, int R, void *block, hipStream_t stream, sgbem_rules &out)
+{
+    out = nullptr;
+    WQRules W;
+    try {
+        W = build_wq_rules(p, N, R);
+    } catch (const PlanError &e) {
+        return set_err(sgbem_status(e.status), e.msg);
+    } catch (const std::bad_alloc &) {
+        return set_err(SGBEM_E_NOMEM, "host allocation failed");
+    }
+    auto *r = new (std::nothrow) sgbem_rules_s;
+    if (!r) return set_err(SGBEM_E_NOMEM, "host allocation failed");
+    r->p = p;
+    r->N = N;
+    r->R = R;
+    r->Q = W.Q;
+    r->M = W.M;
+    r->npts = W.n_nodes;
+    r->w0 = W.w0;
+    r->bvals = W.bvals;
+    const size_t n = size_t(W.n_nodes);
+    std::vector<float> f_inv(n), f_ws(2 * n);
+    for (size_t i = 0; i < n; ++i) f_inv[i] = float(W.inv_s2[i]);
+    for (size_t i = 0; i < 2 * n; ++i) f_ws[i] = float(W.ws[i]);
+    hipError_t e = hipSuccess;
+    if (block) {
+        r->block = block;
+    } else {
+        e = hipMalloc(&r->block, rules_block_bytes(W.n_nodes));
+        r->owned = e == hipSuccess;
+    }
+    if (e == hipSuccess) {
+        char *b = static_cast<char *>(r->block);
+        r->d_inv_s2 = reinterpret_cast<double *>(b);
+        b += align256(n * 8);
+        r->d_ws = reinterpret_cast<double *>(b);
+        b += align256(2 * n * 8);
+        r->d_w0 = reinterpret_cast<double *>(b);
+        b += align256(64 * 8);
+        r->d_inv_s2f = reinterpret_cast<float *>(b);
+        b += align256(n * 4);
+        r->d_wsf = reinterpret_cast<float *>(b);
+    }
+    // pageable sources: each copy has completed when hipMemcpyAsync returns or at the final synchronisation
+    if (e == hipSuccess) e = hipMemcpyAsync(r->d_inv_s2, W.inv_s2.data(), n * 8, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(r->d_ws, W.ws.data(), 2 * n * 8, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(r->d_w0, W.w0.data(), W.w0.size() * 8, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(r->d_inv_s2f, f_inv.data(), n * 4, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(r->d_wsf, f_ws.data(), 2 * n * 4, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+        free_rules(r);
+        return set_err(e == hipErrorOutOfMemory ? SGBEM_E_NOMEM : SGBEM_E_DEVICE,
+                       std::string("uploading rules: ") + hipGetErrorString(e));
+    }
+    out = r;
+    return SGBEM_OK;
+}
+
+bool valid_rules(sgbem_ctx c, sgbem_rules r)
+{
+    if (r && r->shared) return true;
+    for (auto *x : c->rules)
+        if (x == r) return true;
+    return false;
+}
+
+}  // namespace sgbem
+
+namespace {
+
+}  // namespace
+
+namespace sgbem {
 sgbem_status check_curve(const sgbem_curve *c)
 {
     if (!c) return set_err(SGBEM_E_INVAL, "curve is NULL");
@@ -157,6 +178,10 @@ sgbem_status check_curve(const sgbem_curve *c)
     }
     return SGBEM_OK;
 }
+
+}  // namespace sgbem
+
+namespace {
 
 // Device description of a curve whose arrays fit the inline storage.
 sgbem_status inline_curve(const sgbem_curve *cv, CurveDev &d)
@@ -324,13 +349,6 @@ sgbem_status mark(sgbem_ctx c)
     return SGBEM_OK;
 }
 
-bool valid_rules(sgbem_ctx c, sgbem_rules r)
-{
-    for (auto *x : c->rules)
-        if (x == r) return true;
-    return false;
-}
-
 }  // namespace
 
 // ====================================================================== ABI
@@ -437,49 +455,40 @@ sgbem_status sgbem_nearfield_host(double *u16, double *w16, double *mco, double 
     return SGBEM_OK;
 }
 
+sgbem_status sgbem_node_points_host(const sgbem_curve *curve, int32_t N, int32_t n_ref, double *xy)
+{
+    if (!xy) return set_err(SGBEM_E_INVAL, "xy is NULL");
+    if (N < 1 || n_ref < 1 || n_ref > 4) return set_err(SGBEM_E_INVAL, "bad N or n_ref");
+    sgbem_status st = check_curve(curve);
+    if (st) return st;
+    CurveDev d;
+    std::memset(&d, 0, sizeof d);
+    d.kind = curve->kind;
+    d.degree = curve->degree;
+    d.n_ctrl = curve->n_ctrl;
+    d.n_modes = curve->n_modes;
+    d.r0 = curve->r0;
+    d.ctrl = curve->ctrl_xy;
+    d.a = curve->a;
+    d.phi = curve->phi;
+    const int64_t npts = int64_t(2) * n_ref * N;
+    for (int64_t n = 0; n < npts; ++n) {
+        double x, y, J;
+        eval_curve(d, double(n) / double(npts), x, y, J);
+        xy[2 * n] = x;
+        xy[2 * n + 1] = y;
+    }
+    return SGBEM_OK;
+}
+
 sgbem_status sgbem_weights(sgbem_ctx c, int32_t p, int32_t N, int32_t n_ref, sgbem_rules *out)
 {
     if (!c || !out) return set_err(SGBEM_E_INVAL, "ctx or out is NULL");
     *out = nullptr;
     DeviceGuard g(c->device);
-    WQRules W;
-    try {
-        W = build_wq_rules(p, N, n_ref);
-    } catch (const PlanError &e) {
-        return set_err(sgbem_status(e.status), e.msg);
-    } catch (const std::bad_alloc &) {
-        return set_err(SGBEM_E_NOMEM, "host allocation failed");
-    }
-    auto *r = new (std::nothrow) sgbem_rules_s;
-    if (!r) return set_err(SGBEM_E_NOMEM, "host allocation failed");
-    r->p = p;
-    r->N = N;
-    r->R = n_ref;
-    r->Q = W.Q;
-    r->M = W.M;
-    r->npts = W.n_nodes;
-    r->w0 = W.w0;
-    r->bvals = W.bvals;
-    const size_t n = size_t(W.n_nodes);
-    std::vector<float> f_inv(n), f_ws(2 * n);
-    for (size_t i = 0; i < n; ++i) f_inv[i] = float(W.inv_s2[i]);
-    for (size_t i = 0; i < 2 * n; ++i) f_ws[i] = float(W.ws[i]);
-    hipError_t e = hipSuccess;
-    if (e == hipSuccess) e = hipMalloc(&r->d_inv_s2, n * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc(&r->d_ws, 2 * n * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc(&r->d_w0, 64 * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc(&r->d_inv_s2f, n * sizeof(float));
-    if (e == hipSuccess) e = hipMalloc(&r->d_wsf, 2 * n * sizeof(float));
-    if (e == hipSuccess) e = hipMemcpy(r->d_inv_s2, W.inv_s2.data(), n * sizeof(double), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(r->d_ws, W.ws.data(), 2 * n * sizeof(double), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(r->d_w0, W.w0.data(), W.w0.size() * sizeof(double), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(r->d_inv_s2f, f_inv.data(), n * sizeof(float), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(r->d_wsf, f_ws.data(), 2 * n * sizeof(float), hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-        free_rules(r);
-        return set_err(e == hipErrorOutOfMemory ? SGBEM_E_NOMEM : SGBEM_E_DEVICE,
-                       std::string("uploading rules: ") + hipGetErrorString(e));
-    }
+    sgbem_rules r = nullptr;
+    sgbem_status st = make_rules(p, N, n_ref, nullptr, c->stream, r);
+    if (st) return st;
     c->rules.push_back(r);
     *out = r;
     return SGBEM_OK;
@@ -489,7 +498,7 @@ sgbem_status sgbem_rules_free(sgbem_ctx c, sgbem_rules r)
 {
     if (!c) return set_err(SGBEM_E_INVAL, "ctx is NULL");
     if (!r) return SGBEM_OK;
-    if (!valid_rules(c, r)) return set_err(SGBEM_E_INVAL, "rules handle does not belong to this context");
+    if (r->shared || !valid_rules(c, r)) return set_err(SGBEM_E_INVAL, "rules handle does not belong to this context");
     DeviceGuard g(c->device);
     HIPCHK(hipStreamSynchronize(c->stream));
     for (size_t i = 0; i < c->rules.size(); ++i)

@@ -1,0 +1,115 @@
+// Internal state behind the opaque handles of the C ABI (contexts, rule
+// handles, batches) and the helpers shared by the entry points and the
+// serving loop.  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/sgbem.h"
+#include "batch.hpp"
+
+namespace sgbem {
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+// Records the calling thread's error message and passes the status through.
+sgbem_status set_err(sgbem_status st, const std::string &m);
+
+#define HIPCHK(call)                                                                       \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return ::sgbem::set_err(e_ == hipErrorOutOfMemory ? SGBEM_E_NOMEM : SGBEM_E_DEVICE, \
+                                    std::string(#call) + ": " + hipGetErrorString(e_));    \
+    } while (0)
+
+// Grow-only device buffer owned by a context.
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace sgbem
+
+// Device tables of one rule set live in one block:
+//   inv_s2 [npts] f64 | ws [2][npts] f64 | w0 [64] f64 | inv_s2f [npts] f32 | wsf [2][npts] f32
+// (each part 256-byte aligned).  `owned`: the block was allocated for the
+// handle and is freed with it; otherwise it belongs to a caller's arena.
+// `shared`: the handle may be used with any context on its device.
+struct sgbem_rules_s {
+    int p = 0, N = 0, R = 0, Q = 0;
+    int64_t M = 0, npts = 0;
+    std::vector<double> w0, bvals;
+    double *d_inv_s2 = nullptr, *d_ws = nullptr, *d_w0 = nullptr;
+    float *d_inv_s2f = nullptr, *d_wsf = nullptr;
+    void *block = nullptr;
+    bool owned = false;
+    bool shared = false;
+};
+
+struct sgbem_batch_s {
+    int n = 0, prec = 0, max_npts = 0;
+    int total32 = 0, total16 = 0;
+    int cfg = 0, grid = 0;
+    sgbem::BatchDev d{};
+    void *mem = nullptr;     // one device allocation holding the whole description
+};
+
+struct sgbem_ctx_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    sgbem::DevBuf geo, geo16, nearL, params, solve_ws;
+    std::vector<sgbem_rules_s *> rules;
+    std::vector<sgbem_batch_s *> batches;
+    // geometry-independent element-by-element tables, uploaded once per key:
+    // key p      -> u16, w16, mco, madj, M_p(a + u16)       (near pairs)
+    // key 1000 + 64p + G -> RHS coefficients w_g M_p(a + u_g) without h
+    std::map<int, double *> tables;
+    // autotuned batched tile configuration per precision (-1: not tuned yet)
+    int batch_cfg[2] = {-1, -1};
+    // optional HIP-event timing of the main kernel of each call
+    int timing = 0;
+    std::vector<hipEvent_t> ev;
+    size_t ev_used = 0;
+};
+
+namespace sgbem {
+
+// Grow b to at least `bytes` (synchronises the context's stream before a
+// reallocation).
+sgbem_status ensure(sgbem_ctx c, DevBuf &b, size_t bytes);
+
+// Bytes of the device block of a rule set with npts nodes.
+size_t rules_block_bytes(int64_t npts);
+
+// Build the rules of (p, N, R) on the host and upload them on `stream`
+// (synchronised before return).  block: device memory of rules_block_bytes
+// bytes to hold the tables, or nullptr to allocate it.
+sgbem_status make_rules(int p, int N, int R, void *block, hipStream_t stream, sgbem_rules &out);
+void free_rules(sgbem_rules r);
+
+// Rules handles the given context can use (its own, or shared ones).
+bool valid_rules(sgbem_ctx c, sgbem_rules r);
+
+// Argument check of a curve description.
+sgbem_status check_curve(const sgbem_curve *c);
+
+}  // namespace sgbem

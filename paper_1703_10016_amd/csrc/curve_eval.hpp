@@ -1,5 +1,5 @@
-// Curve geometry at one parameter value (device side), shared by the single
-// and batched geometry kernels: f, f' and J = |f'| (eq. J).
+// Curve geometry at one parameter value, shared by the single and batched
+// geometry kernels and the host-side node points: f, f' and J = |f'| (eq. J).
 //  polar:   f = r(theta) (cos theta, sin theta), theta = 2 pi t, closed-form derivative;
 //  B-spline (periodic uniform knots, Section 3): de Boor's algorithm on the span
 //           containing n_ctrl t, and on the derivative curve with control points
@@ -8,11 +8,38 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
+
 #include "kernels.hpp"
 
 namespace sgbem {
 
-__device__ __forceinline__ void eval_curve(const CurveDev &c, double t, double &x, double &y, double &J)
+// sin and cos of pi x
+__host__ __device__ inline void sincos_pi(double x, double *s, double *c)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    sincospi(x, s, c);
+#else
+    // reduce to [-1/2, 1/2] so that the multiplication by pi stays accurate
+    const double k = std::nearbyint(x);
+    const double r = x - k;
+    const double sg = (static_cast<long long>(k) & 1) ? -1.0 : 1.0;
+    *s = sg * std::sin(3.14159265358979323846 * r);
+    *c = sg * std::cos(3.14159265358979323846 * r);
+#endif
+}
+
+__host__ __device__ inline void sin_cos(double x, double *s, double *c)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    sincos(x, s, c);
+#else
+    *s = std::sin(x);
+    *c = std::cos(x);
+#endif
+}
+
+__host__ __device__ __forceinline__ void eval_curve(const CurveDev &c, double t, double &x, double &y, double &J)
 {
     const double *ca = c.inline_data ? c.inl : c.a;
     const double *cphi = c.inline_data ? c.inl + 64 : c.phi;
@@ -20,12 +47,12 @@ __device__ __forceinline__ void eval_curve(const CurveDev &c, double t, double &
     double dx, dy;
     if (c.kind == 1) {
         double sn, cs;
-        sincospi(2.0 * t, &sn, &cs);
+        sincos_pi(2.0 * t, &sn, &cs);
         const double th = 6.283185307179586476925286766559 * t;
         double r = 1.0, dr = 0.0;
         for (int k = 1; k <= c.n_modes; ++k) {
             double sk, ck;
-            sincos(k * th + cphi[k - 1], &sk, &ck);
+            sin_cos(k * th + cphi[k - 1], &sk, &ck);
             r += ca[k - 1] * ck;
             dr -= k * ca[k - 1] * sk;
         }
@@ -38,7 +65,7 @@ __device__ __forceinline__ void eval_curve(const CurveDev &c, double t, double &
     } else {
         const int d = c.degree, nc = c.n_ctrl;
         const double u = t * nc;
-        int l = int(floor(u));
+        int l = int(std::floor(u));
         if (l >= nc) l = nc - 1;
         if (l < 0) l = 0;
         double px[8], py[8];
@@ -77,7 +104,7 @@ __device__ __forceinline__ void eval_curve(const CurveDev &c, double t, double &
         dx = qx[dd];
         dy = qy[dd];
     }
-    J = sqrt(dx * dx + dy * dy);
+    J = std::sqrt(dx * dx + dy * dy);
 }
 
 

@@ -43,6 +43,32 @@ class sgbem_solve_info(ctypes.Structure):
                 ("backward_err", ctypes.c_double)]
 
 
+class sgbem_server_config(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("workers", ctypes.c_int32), ("budget_bytes", ctypes.c_int64),
+                ("precision", ctypes.c_int32), ("max_N", ctypes.c_int32), ("max_rules", ctypes.c_int32),
+                ("max_iter", ctypes.c_int32), ("tol", ctypes.c_double)]
+
+
+class sgbem_request(ctypes.Structure):
+    _fields_ = [("curve", sgbem_curve), ("p", ctypes.c_int32), ("N", ctypes.c_int32),
+                ("g", ctypes.POINTER(ctypes.c_double)), ("x", ctypes.POINTER(ctypes.c_double)),
+                ("arrival_s", ctypes.c_double), ("tag", ctypes.c_uint64)]
+
+
+class sgbem_completion(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("status", ctypes.c_int32), ("iters", ctypes.c_int32),
+                ("t_arrival", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double),
+                ("backward_err", ctypes.c_double), ("footprint", ctypes.c_int64), ("message", ctypes.c_char * 96)]
+
+
+class sgbem_server_info(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("rejected", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("failed", ctypes.c_int64), ("waiting", ctypes.c_int32), ("in_flight", ctypes.c_int32),
+                ("peak_in_flight", ctypes.c_int32), ("rules_cached", ctypes.c_int32),
+                ("arena_bytes", ctypes.c_int64), ("peak_bytes", ctypes.c_int64),
+                ("rules_hits", ctypes.c_int64), ("rules_misses", ctypes.c_int64)]
+
+
 _lib = None
 
 
@@ -75,6 +101,14 @@ def lib():
             "sgbem_batch_assemble": [vp, vp],
             "sgbem_batch_tune": [vp, vp, i32, ctypes.POINTER(i32), ctypes.POINTER(dbl)],
             "sgbem_batch_free": [vp, vp],
+            "sgbem_node_points_host": [cp, i32, i32, dp],
+            "sgbem_server_footprint": [i32, i32, ctypes.POINTER(i64)],
+            "sgbem_server_create": [ctypes.POINTER(sgbem_server_config), ctypes.POINTER(vp)],
+            "sgbem_server_submit": [vp, ctypes.POINTER(sgbem_request)],
+            "sgbem_server_poll": [vp, ctypes.POINTER(sgbem_completion), i32, dbl, ctypes.POINTER(i32)],
+            "sgbem_server_clock": [vp, ctypes.POINTER(dbl)],
+            "sgbem_server_stats": [vp, ctypes.POINTER(sgbem_server_info)],
+            "sgbem_server_destroy": [vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -99,7 +133,9 @@ def exported_symbols():
             "sgbem_ctx_kernel_time", "sgbem_last_error", "sgbem_version",
             "sgbem_weights", "sgbem_rules_free", "sgbem_weights_host", "sgbem_nearfield_host", "sgbem_rhs_points",
             "sgbem_assemble", "sgbem_rhs", "sgbem_solve", "sgbem_batch_create", "sgbem_batch_assemble",
-            "sgbem_batch_tune", "sgbem_batch_free"]
+            "sgbem_batch_tune", "sgbem_batch_free", "sgbem_node_points_host", "sgbem_server_footprint",
+            "sgbem_server_create", "sgbem_server_submit", "sgbem_server_poll", "sgbem_server_clock",
+            "sgbem_server_stats", "sgbem_server_destroy"]
 
 
 # ------------------------------------------------------------------ curve marshalling
@@ -245,3 +281,64 @@ def sgbem_batch_tune(ctx, batch, reps=3):
 
 def sgbem_batch_free(ctx, batch):
     _check(lib().sgbem_batch_free(ctx, batch))
+
+
+# ------------------------------------------------------------------ host node points, serving
+def sgbem_node_points_host(curve, N, n_ref=1):
+    """f(n / (2 n_ref N)) as an array [2 n_ref N, 2] (host evaluation)."""
+    c = _as_curve(curve)
+    xy = np.zeros((2 * n_ref * N, 2))
+    _check(lib().sgbem_node_points_host(c.ref(), int(N), int(n_ref),
+                                        xy.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return xy
+
+
+def sgbem_server_footprint(N, precision=SGBEM_FP64):
+    b = ctypes.c_int64()
+    _check(lib().sgbem_server_footprint(int(N), int(precision), ctypes.byref(b)))
+    return b.value
+
+
+def sgbem_server_create(device=0, workers=4, budget_bytes=8 << 30, precision=SGBEM_FP64, max_N=8192,
+                        max_rules=256, max_iter=30, tol=1e-12):
+    cfg = sgbem_server_config(int(device), int(workers), int(budget_bytes), int(precision), int(max_N),
+                              int(max_rules), int(max_iter), float(tol))
+    h = ctypes.c_void_p()
+    _check(lib().sgbem_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+    return h
+
+
+def sgbem_server_submit(server, curve, p, N, g, x, arrival_s, tag):
+    """g: float64 host array [2N] (copied by the call); x: float64 host array [N]
+    that receives alpha and must stay alive until the request's completion."""
+    c = _as_curve(curve)
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    if g.size != 2 * N or x.dtype != np.float64 or x.size != N or not x.flags["C_CONTIGUOUS"]:
+        raise ValueError("g must have 2N and x N contiguous float64 entries")
+    dp = ctypes.POINTER(ctypes.c_double)
+    r = sgbem_request(c.c, int(p), int(N), g.ctypes.data_as(dp), x.ctypes.data_as(dp), float(arrival_s),
+                      int(tag))
+    _check(lib().sgbem_server_submit(server, ctypes.byref(r)))
+
+
+def sgbem_server_poll(server, cap=64, timeout_s=0.0):
+    buf = (sgbem_completion * cap)()
+    n = ctypes.c_int32()
+    _check(lib().sgbem_server_poll(server, buf, int(cap), float(timeout_s), ctypes.byref(n)))
+    return [buf[i] for i in range(n.value)]
+
+
+def sgbem_server_clock(server):
+    t = ctypes.c_double()
+    _check(lib().sgbem_server_clock(server, ctypes.byref(t)))
+    return t.value
+
+
+def sgbem_server_stats(server):
+    info = sgbem_server_info()
+    _check(lib().sgbem_server_stats(server, ctypes.byref(info)))
+    return {k: getattr(info, k) for k, _ in sgbem_server_info._fields_}
+
+
+def sgbem_server_destroy(server):
+    _check(lib().sgbem_server_destroy(server))

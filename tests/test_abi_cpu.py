@@ -82,3 +82,43 @@ def test_python_binding_has_no_compute_fallback():
     src = open(os.path.join(ROOT, "paper_1703_10016_amd", "sgbem.py")).read()
     src += open(os.path.join(ROOT, "paper_1703_10016_amd", "runtime.py")).read()
     assert "oracle" not in src and "scipy" not in src
+
+
+@pytest.mark.parametrize("which", ["circle", "ellipse", "star"])
+def test_node_points_host_match_oracle_curve(which):
+    """The host node points f(n / 2 n_ref N) agree with the oracle's curve
+    evaluation (de Boor / polar form, Section 3) to rounding."""
+    import synth
+    from oracle import curves
+    S = _lib()
+    curve = {"circle": synth.circle(0.5), "ellipse": synth.ellipse_bspline(), "star": synth.star(7)}[which]
+    for N, R in [(37, 1), (64, 2)]:
+        xy = S.sgbem_node_points_host(curve, N, R)
+        t = np.arange(2 * R * N) / (2 * R * N)
+        x, y = curves.evaluate(curve, t)[:2]
+        assert np.abs(xy[:, 0] - x).max() < 1e-14 and np.abs(xy[:, 1] - y).max() < 1e-14
+
+
+def test_server_footprint_formula():
+    """A request holds A (N^2 words of the matrix precision), the solve
+    workspace (4 N^2 bytes of FP32 LU plus O(N)), and g, beta, x (O(N))."""
+    S = _lib()
+    for N in (16, 256, 1000, 4099, 8192):
+        f64 = S.sgbem_server_footprint(N, S.SGBEM_FP64)
+        f32 = S.sgbem_server_footprint(N, S.SGBEM_FP32)
+        assert 12 * N * N <= f64 <= 12 * N * N + 4096 * N + 16384
+        assert 8 * N * N <= f32 <= 8 * N * N + 4096 * N + 16384
+        assert abs((f64 - f32) - 4 * N * N) < 256 and f64 % 256 == 0 and f32 % 256 == 0
+    for bad in [(0, 0), (70000, 0), (64, 2)]:
+        with pytest.raises(S.SgbemError) as e:
+            S.sgbem_server_footprint(*bad)
+        assert e.value.status == S.SGBEM_E_INVAL
+
+
+@pytest.mark.parametrize("kw", [dict(workers=0), dict(workers=65), dict(budget_bytes=0), dict(precision=3),
+                                dict(max_N=2), dict(workers=4, max_rules=8), dict(max_iter=-1), dict(tol=-1.0)])
+def test_server_rejects_bad_config_before_touching_the_device(kw):
+    S = _lib()
+    with pytest.raises(S.SgbemError) as e:
+        S.sgbem_server_create(**kw)
+    assert e.value.status == S.SGBEM_E_INVAL
