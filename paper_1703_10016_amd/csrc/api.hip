@@ -649,7 +649,8 @@ sgbem_status sgbem_batch_create(sgbem_ctx c, int32_t n, const sgbem_curve *curve
     *out = nullptr;
     DeviceGuard g(c->device);
     std::vector<CurveDev> cd(n);
-    std::vector<int> npts(n), deg(n), pre32(n + 1, 0), pre16(n + 1, 0);
+    std::vector<int> npts(n), deg(n);
+    std::vector<std::vector<int>> pre(kNumBatchConfigs, std::vector<int>(n + 1, 0));
     std::vector<int64_t> goff(n);
     std::vector<TileArgs> args(n);
     std::vector<TileArgsF> argsf(n);
@@ -668,11 +669,12 @@ sgbem_status sgbem_batch_create(sgbem_ctx c, int32_t n, const sgbem_curve *curve
         goff[b] = gsum;
         gsum += r->npts;
         if (npts[b] > max_npts) max_npts = npts[b];
-        const int64_t t32 = int64_t((r->N + 31) / 32) * ((r->N + 31) / 32 + 1) / 2;
-        const int64_t t16 = int64_t((r->N + 15) / 16) * ((r->N + 15) / 16 + 1) / 2;
-        if (int64_t(pre16[b]) + t16 > (int64_t(1) << 31) - 1) return set_err(SGBEM_E_INVAL, "batch: too many tiles");
-        pre32[b + 1] = pre32[b] + int(t32);
-        pre16[b + 1] = pre16[b] + int(t16);
+        for (int k = 0; k < kNumBatchConfigs; ++k) {
+            const int64_t T = kBatchConfigs[k].T, nb = (r->N + T - 1) / T;
+            const int64_t tiles = nb * (nb + 1) / 2;
+            if (int64_t(pre[k][b]) + tiles > (int64_t(1) << 31) - 1) return set_err(SGBEM_E_INVAL, "batch: too many tiles");
+            pre[k][b + 1] = pre[k][b] + int(tiles);
+        }
         TileArgs &ta = args[b];
         std::memset(&ta, 0, sizeof ta);
         ta.N = r->N;
@@ -691,7 +693,7 @@ sgbem_status sgbem_batch_create(sgbem_ctx c, int32_t n, const sgbem_curve *curve
         ta.out = d_A[b];
         ta.lda = lda[b];
     }
-    // one allocation: curves | npts | goff | args | argsf | deg | prefix32 | prefix16 | geometry
+    // one allocation: curves | npts | goff | args | argsf | deg | prefix per tile configuration | geometry
     auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
     const size_t o_curves = 0;
     const size_t o_npts = o_curves + al(sizeof(CurveDev) * n);
@@ -699,9 +701,8 @@ sgbem_status sgbem_batch_create(sgbem_ctx c, int32_t n, const sgbem_curve *curve
     const size_t o_args = o_goff + al(sizeof(int64_t) * n);
     const size_t o_argsf = o_args + al(sizeof(TileArgs) * n);
     const size_t o_deg = o_argsf + al(sizeof(TileArgsF) * n);
-    const size_t o_p32 = o_deg + al(sizeof(int) * n);
-    const size_t o_p16 = o_p32 + al(sizeof(int) * (n + 1));
-    const size_t o_geo = o_p16 + al(sizeof(int) * (n + 1));
+    const size_t o_pre = o_deg + al(sizeof(int) * n);
+    const size_t o_geo = o_pre + kNumBatchConfigs * al(sizeof(int) * (n + 1));
     const size_t total_bytes = o_geo + al(sizeof(double) * 3 * size_t(gsum));
     auto *bt = new (std::nothrow) sgbem_batch_s;
     if (!bt) return set_err(SGBEM_E_NOMEM, "host allocation failed");
@@ -717,8 +718,8 @@ sgbem_status sgbem_batch_create(sgbem_ctx c, int32_t n, const sgbem_curve *curve
     bt->d.args = reinterpret_cast<TileArgs *>(base + o_args);
     bt->d.argsf = reinterpret_cast<TileArgsF *>(base + o_argsf);
     bt->d.deg = reinterpret_cast<int *>(base + o_deg);
-    bt->d.prefix32 = reinterpret_cast<int *>(base + o_p32);
-    bt->d.prefix16 = reinterpret_cast<int *>(base + o_p16);
+    for (int k = 0; k < kNumBatchConfigs; ++k)
+        bt->d.prefix[k] = reinterpret_cast<int *>(base + o_pre + k * al(sizeof(int) * (n + 1)));
     bt->d.geo = reinterpret_cast<double *>(base + o_geo);
     for (int b = 0; b < n; ++b) {
         args[b].X = bt->d.geo + 3 * goff[b];
@@ -729,10 +730,11 @@ sgbem_status sgbem_batch_create(sgbem_ctx c, int32_t n, const sgbem_curve *curve
         void *dst;
         const void *src;
         size_t bytes;
-    } ups[] = {{bt->d.curves, cd.data(), sizeof(CurveDev) * n}, {bt->d.npts, npts.data(), sizeof(int) * n},
-               {bt->d.goff, goff.data(), sizeof(int64_t) * n}, {bt->d.args, args.data(), sizeof(TileArgs) * n},
-               {bt->d.argsf, argsf.data(), sizeof(TileArgsF) * n}, {bt->d.deg, deg.data(), sizeof(int) * n},
-               {bt->d.prefix32, pre32.data(), sizeof(int) * (n + 1)}, {bt->d.prefix16, pre16.data(), sizeof(int) * (n + 1)}};
+    };
+    std::vector<Up> ups = {{bt->d.curves, cd.data(), sizeof(CurveDev) * n}, {bt->d.npts, npts.data(), sizeof(int) * n},
+                           {bt->d.goff, goff.data(), sizeof(int64_t) * n}, {bt->d.args, args.data(), sizeof(TileArgs) * n},
+                           {bt->d.argsf, argsf.data(), sizeof(TileArgsF) * n}, {bt->d.deg, deg.data(), sizeof(int) * n}};
+    for (int k = 0; k < kNumBatchConfigs; ++k) ups.push_back({bt->d.prefix[k], pre[k].data(), sizeof(int) * (n + 1)});
     for (const Up &u : ups) {
         if ((e = hipMemcpy(u.dst, u.src, u.bytes, hipMemcpyHostToDevice)) != hipSuccess) {
             (void)hipFree(bt->mem);
@@ -743,11 +745,9 @@ sgbem_status sgbem_batch_create(sgbem_ctx c, int32_t n, const sgbem_curve *curve
     bt->n = n;
     bt->prec = precision;
     bt->max_npts = max_npts;
-    bt->total32 = pre32[n];
-    bt->total16 = pre16[n];
+    for (int k = 0; k < kNumBatchConfigs; ++k) bt->total[k] = pre[k][n];
     bt->cfg = c->batch_cfg[precision] >= 0 ? c->batch_cfg[precision] : 0;
-    const int tot = kBatchConfigs[bt->cfg].T == 32 ? bt->total32 : bt->total16;
-    bt->grid = batch_grid(c, bt->cfg, precision, tot);
+    bt->grid = batch_grid(c, bt->cfg, precision, bt->total[bt->cfg]);
     c->batches.push_back(bt);
     *out = bt;
     return SGBEM_OK;
@@ -758,7 +758,7 @@ sgbem_status sgbem_batch_assemble(sgbem_ctx c, sgbem_batch b)
     if (!c || !b || !valid_batch(c, b)) return set_err(SGBEM_E_INVAL, "batch handle does not belong to this context");
     DeviceGuard g(c->device);
     HIPCHK(launch_batch_geometry(b->d, b->n, b->max_npts, c->stream));
-    const int tot = kBatchConfigs[b->cfg].T == 32 ? b->total32 : b->total16;
+    const int tot = b->total[b->cfg];
     sgbem_status st;
     if ((st = mark(c))) return st;
     HIPCHK(launch_batch_tiles(b->cfg, b->prec, b->d, b->n, tot, b->grid, c->stream));
@@ -778,7 +778,7 @@ sgbem_status sgbem_batch_tune(sgbem_ctx c, sgbem_batch b, int32_t reps, int32_t 
     int bestc = 0;
     HIPCHK(launch_batch_geometry(b->d, b->n, b->max_npts, c->stream));
     for (int cfg = 0; cfg < kNumBatchConfigs; ++cfg) {
-        const int tot = kBatchConfigs[cfg].T == 32 ? b->total32 : b->total16;
+        const int tot = b->total[cfg];
         const int grid = batch_grid(c, cfg, b->prec, tot);
         HIPCHK(launch_batch_tiles(cfg, b->prec, b->d, b->n, tot, grid, c->stream));   // warm
         HIPCHK(hipEventRecord(e0, c->stream));
@@ -795,7 +795,7 @@ sgbem_status sgbem_batch_tune(sgbem_ctx c, sgbem_batch b, int32_t reps, int32_t 
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     b->cfg = bestc;
-    b->grid = batch_grid(c, bestc, b->prec, kBatchConfigs[bestc].T == 32 ? b->total32 : b->total16);
+    b->grid = batch_grid(c, bestc, b->prec, b->total[bestc]);
     c->batch_cfg[b->prec] = bestc;
     if (best_cfg) *best_cfg = bestc;
     if (best_ms) *best_ms = best;

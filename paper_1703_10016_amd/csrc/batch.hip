@@ -61,10 +61,10 @@ hipError_t launch_batch_geometry(const BatchDev &d, int n, int max_npts, hipStre
 
 namespace {
 template <typename Real, int T, int S>
-hipError_t launch_one(const BatchDev &d, int n, int total, int grid, hipStream_t s)
+hipError_t launch_one(const BatchDev &d, int cfg, int n, int total, int grid, hipStream_t s)
 {
     hipLaunchKernelGGL((batch_tile_kernel<Real, T, S>), dim3(grid), dim3(256), 0, s, d.args, d.argsf, d.deg,
-                       T == 32 ? d.prefix32 : d.prefix16, n, total);
+                       d.prefix[cfg], n, total);
     return hipGetLastError();
 }
 template <typename Real, int T, int S>
@@ -76,23 +76,26 @@ int occupancy_one()
 }
 }  // namespace
 
-const BatchConfig kBatchConfigs[kNumBatchConfigs] = {{32, 8}, {32, 16}, {16, 8}, {16, 4}};
+// 28 x 28 tiles with 7-column strips keep all 256 threads of the sweep busy for
+// p = 2..4 (2T + 2p - 1 rows x 4 strips = 236..252 items); the others are the
+// tuner's alternatives.
+const BatchConfig kBatchConfigs[kNumBatchConfigs] = {{28, 7}, {32, 8}, {24, 6}, {16, 4}};
 
 hipError_t launch_batch_tiles(int cfg, int prec, const BatchDev &d, int n, int total, int grid, hipStream_t s)
 {
     if (prec == 0) {
         switch (cfg) {
-        case 0: return launch_one<double, 32, 8>(d, n, total, grid, s);
-        case 1: return launch_one<double, 32, 16>(d, n, total, grid, s);
-        case 2: return launch_one<double, 16, 8>(d, n, total, grid, s);
-        default: return launch_one<double, 16, 4>(d, n, total, grid, s);
+        case 0: return launch_one<double, 28, 7>(d, 0, n, total, grid, s);
+        case 1: return launch_one<double, 32, 8>(d, 1, n, total, grid, s);
+        case 2: return launch_one<double, 24, 6>(d, 2, n, total, grid, s);
+        default: return launch_one<double, 16, 4>(d, 3, n, total, grid, s);
         }
     }
     switch (cfg) {
-    case 0: return launch_one<float, 32, 8>(d, n, total, grid, s);
-    case 1: return launch_one<float, 32, 16>(d, n, total, grid, s);
-    case 2: return launch_one<float, 16, 8>(d, n, total, grid, s);
-    default: return launch_one<float, 16, 4>(d, n, total, grid, s);
+    case 0: return launch_one<float, 28, 7>(d, 0, n, total, grid, s);
+    case 1: return launch_one<float, 32, 8>(d, 1, n, total, grid, s);
+    case 2: return launch_one<float, 24, 6>(d, 2, n, total, grid, s);
+    default: return launch_one<float, 16, 4>(d, 3, n, total, grid, s);
     }
 }
 
@@ -100,16 +103,16 @@ int batch_blocks_per_cu(int cfg, int prec)
 {
     if (prec == 0) {
         switch (cfg) {
-        case 0: return occupancy_one<double, 32, 8>();
-        case 1: return occupancy_one<double, 32, 16>();
-        case 2: return occupancy_one<double, 16, 8>();
+        case 0: return occupancy_one<double, 28, 7>();
+        case 1: return occupancy_one<double, 32, 8>();
+        case 2: return occupancy_one<double, 24, 6>();
         default: return occupancy_one<double, 16, 4>();
         }
     }
     switch (cfg) {
-    case 0: return occupancy_one<float, 32, 8>();
-    case 1: return occupancy_one<float, 32, 16>();
-    case 2: return occupancy_one<float, 16, 8>();
+    case 0: return occupancy_one<float, 28, 7>();
+    case 1: return occupancy_one<float, 32, 8>();
+    case 2: return occupancy_one<float, 24, 6>();
     default: return occupancy_one<float, 16, 4>();
     }
 }

@@ -10,6 +10,12 @@
 
 namespace sgbem {
 
+struct BatchConfig {
+    int T, S;              // tile edge, strip width
+};
+constexpr int kNumBatchConfigs = 4;
+extern const BatchConfig kBatchConfigs[kNumBatchConfigs];
+
 struct BatchDev {
     CurveDev *curves;      // [n]
     int *npts;             // [n] nodes of each curve (2N)
@@ -18,15 +24,8 @@ struct BatchDev {
     TileArgs *args;        // [n]
     TileArgsF *argsf;      // [n]
     int *deg;              // [n] spline degree p
-    int *prefix32;         // [n + 1] first tile of each curve for 32 x 32 tiles
-    int *prefix16;         // [n + 1] ... for 16 x 16 tiles
+    int *prefix[kNumBatchConfigs];   // [n + 1] first tile of each curve, per tile configuration
 };
-
-struct BatchConfig {
-    int T, S;              // tile edge, strip width
-};
-constexpr int kNumBatchConfigs = 4;
-extern const BatchConfig kBatchConfigs[kNumBatchConfigs];
 
 hipError_t launch_batch_geometry(const BatchDev &d, int n, int max_npts, hipStream_t s);
 hipError_t launch_batch_tiles(int cfg, int prec, const BatchDev &d, int n, int total, int grid, hipStream_t s);

@@ -67,7 +67,7 @@ struct sgbem_rules_s {
 
 struct sgbem_batch_s {
     int n = 0, prec = 0, max_npts = 0;
-    int total32 = 0, total16 = 0;
+    int total[sgbem::kNumBatchConfigs] = {};
     int cfg = 0, grid = 0;
     sgbem::BatchDev d{};
     void *mem = nullptr;     // one device allocation holding the whole description

@@ -4,8 +4,15 @@ Each unit holds one switch from (degree p, points per element P) to the
 kernel compiled for those compile-time sizes: WQ for p in 1..6 and
 n_ref in 1..4 (P = 2 n_ref, Q = P (p+1) - 1 support nodes, first support node
 1), EBE for p in 1..6 and G in 1..8 Gauss points (P = G, Q = G (p+1), first
-support point 0).  Tiles are 32 x 32 for P <= 4 and 16 x 16 above, 8-column
-strips.  Run from this directory: python gen_instances.py
+support point 0).
+
+Tile shapes: the sweep runs one work item per (node row, column strip), L x T/S
+items with L = P (T - 1) + Q rows; the shape is chosen so that the items fill the
+256 threads in one pass.  Fast form with n_ref = 1, p <= 4: 28 x 28 tiles with
+7-column strips (236..252 items), and in FP64 from N = 4096 an instance compiled
+for at least 4 waves per SIMD (FP32 reaches that occupancy anyway); p = 5, 6: 24 x 24 tiles, 6-column strips (228, 236
+items).  Otherwise 32 x 32 tiles for P <= 4 and 16 x 16 above, 8-column strips.
+Run from this directory: python gen_instances.py
 """
 import os
 
@@ -27,13 +34,17 @@ def wq_cases():
     for p in range(1, 7):
         for R in range(1, 5):
             P = 2 * R
-            yield p, P, P * (p + 1) - 1, 1, "true", 32 if P <= 4 else 16
+            if P == 2:
+                T, S = (28, 7) if p <= 4 else (24, 6)
+                yield p, P, P * (p + 1) - 1, 1, "true", T, S, (p <= 4)
+            else:
+                yield p, P, P * (p + 1) - 1, 1, "true", 32 if P <= 4 else 16, 8, False
 
 
 def ebe_cases():
     for p in range(1, 7):
         for G in range(1, 9):
-            yield p, G, G * (p + 1), 0, "false", 32 if G <= 4 else 16
+            yield p, G, G * (p + 1), 0, "false", 32 if G <= 4 else 16, 8, False
 
 
 def main():
@@ -42,8 +53,12 @@ def main():
         for prec, real, suf in (("FP64", "double", "f64"), ("FP32", "float", "f32")):
             fname = f"launch_{tag}_{suf}"
             s = HDR.format(what=what, prec=prec, fname=fname)
-            for (p, P, Q, S0, wq, T) in cases():
-                s += f"    case {p * 16 + P}: return launch_tile<{P}, {Q}, {S0}, {wq}, {real}, {T}, 8>(a, s);\n"
+            for (p, P, Q, S0, wq, T, S, big) in cases():
+                k = f"launch_tile<{P}, {Q}, {S0}, {wq}, {real}, {T}, {S}"
+                if big and real == "double":
+                    s += f"    case {p * 16 + P}: return a.N >= 4096 ? {k}, 4>(a, s) : {k}>(a, s);\n"
+                else:
+                    s += f"    case {p * 16 + P}: return {k}>(a, s);\n"
             s += "    default: return hipErrorInvalidValue;\n    }\n}\n\n}  // namespace sgbem\n"
             with open(os.path.join(HERE, f"asm_{tag}_{suf}.hip"), "w") as f:
                 f.write(s)

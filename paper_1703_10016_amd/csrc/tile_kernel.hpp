@@ -288,8 +288,11 @@ __device__ __forceinline__ void tile_body(const Args &a, const ArgsF &af, int bi
     __syncthreads();   // LDS is reused by the next tile of a persistent block
 }
 
-template <int P, int Q, int S0, bool WQ, typename Real, typename OutT, int T, int S>
-__global__ __launch_bounds__(256) void tile_kernel(TileArgs a, TileArgsF af)
+// WPE: minimum waves per SIMD the register allocation must allow (1: no
+// constraint).  Large matrices gain from 4 (more waves to hide the latency of
+// the logarithm's dependent chain), small ones lose to the extra spills.
+template <int P, int Q, int S0, bool WQ, typename Real, typename OutT, int T, int S, int WPE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void tile_kernel(TileArgs a, TileArgsF af)
 {
     const int nb = (a.N + T - 1) / T;
     int bi, bj;
@@ -297,7 +300,7 @@ __global__ __launch_bounds__(256) void tile_kernel(TileArgs a, TileArgsF af)
     tile_body<P, Q, S0, WQ, Real, OutT, T, S>(a, af, bi, bj);
 }
 
-template <int P, int Q, int S0, bool WQ, typename Real, int T, int S>
+template <int P, int Q, int S0, bool WQ, typename Real, int T, int S, int WPE = 1>
 hipError_t launch_tile(const TileArgs &a, hipStream_t s)
 {
     TileArgsF af;
@@ -308,7 +311,7 @@ hipError_t launch_tile(const TileArgs &a, hipStream_t s)
     const int nb = (a.N + T - 1) / T;
     const int blocks = nb * (nb + 1) / 2;
     using OutT = Real;
-    hipLaunchKernelGGL((tile_kernel<P, Q, S0, WQ, Real, OutT, T, S>), dim3(blocks), dim3(256), 0, s, a, af);
+    hipLaunchKernelGGL((tile_kernel<P, Q, S0, WQ, Real, OutT, T, S, WPE>), dim3(blocks), dim3(256), 0, s, a, af);
     return hipGetLastError();
 }
 

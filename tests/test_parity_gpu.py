@@ -119,6 +119,28 @@ def test_full_size_ebe_sampled_entries(ellipse_full):
     assert np.abs(A[ii, jj] - ref).max() < 1e-12 * np.abs(A).max()
 
 
+@pytest.mark.parametrize("p,N,prec", [(2, 4096, "fp64"), (4, 4096, "fp64"), (3, 16384, "fp64"), (3, 16384, "fp32")])
+def test_large_wq_sampled_rows(ctx, p, N, prec):
+    """Star curves at the sizes of the large configurations (the launch that
+    switches to the large-matrix tile instance from N = 4096): sampled rows
+    against the oracle's sparse row route, upper triangle and its mirror."""
+    import torch
+    curve = synth.star(11)
+    rows = [0, 1, N // 2 + 1, N - 1]
+    A = ctx.assemble(curve, p, N, "wq", precision=prec)
+    got = A[rows].double().cpu().numpy()
+    col = A[:, rows].double().cpu().numpy().T
+    del A
+    torch.cuda.empty_cache()
+    ref = wq.full_rows(curve, p, N, 1, rows)
+    tol = 1e-12 if prec == "fp64" else 2e-5
+    # the row formula (eq. IK1e2_bis) is not symmetric: entries j >= i come from
+    # row i, the others are mirrored from row j
+    for r, i in enumerate(rows):
+        assert np.abs(got[r, i:] - ref[r, i:]).max() < tol * np.abs(ref[r]).max()
+    assert got[1, 0] == got[0, 1] and np.array_equal(got, col)
+
+
 def test_full_size_wq_vs_ebe_quadrature_gap(ellipse_full):
     """Both forms approximate the same Galerkin matrix; their difference is the
     quadrature error of the weighted rules (near-diagonal, ~1e-4 relative)."""
