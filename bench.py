@@ -60,7 +60,7 @@ def ebe_flops_per_entry(p: int, G: int) -> float:
 def kernel_source_hash() -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in ("tile_kernel.hpp", "kernels.hpp"):
+    for f in ("tile_kernel.hpp", "kernels.hpp", "asm_wq_f64.hip"):
         with open(os.path.join(ROOT, "paper_1703_10016_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -66,9 +66,11 @@ __device__ __forceinline__ double log_tab64(double x, const double *tab)
 }
 
 // FP64 natural logarithm without tables: x = 2^e m, m in [sqrt(1/2), sqrt(2)),
-// s = (m - 1)/(m + 1) (|s| <= 0.1716; reciprocal by v_rcp_f64 and two Newton
-// steps, quotient corrected by its residual), log m = 2 atanh(s) = 2 sum_k s^(2k+1)/(2k+1)
-// to k = 11 (truncation s^23/23 < 1e-19 relative).
+// s = (m - 1)/(m + 1) (|s| <= 0.1716; reciprocal by v_rcp_f64 and one Newton
+// step, quotient corrected once by its residual, which leaves s exact to
+// rounding whenever the reciprocal carries more than ~27 bits),
+// log m = 2 atanh(s) = 2 sum_k s^(2k+1)/(2k+1) to k = 10 (first omitted term
+// 2 s^23/23 < 2.2e-19).
 __device__ __forceinline__ double log_atanh64(double x)
 {
     constexpr double ln2_hi = 0.69314718036912381649017333984375;   // ln 2 truncated to 32 fraction bits
@@ -81,12 +83,10 @@ __device__ __forceinline__ double log_atanh64(double x)
     const double num = m - 1.0, den = m + 1.0;
     double r = __builtin_amdgcn_rcp(den);
     r = fma(r, fma(-den, r, 1.0), r);
-    r = fma(r, fma(-den, r, 1.0), r);
     double s = num * r;
     s = fma(r, fma(-s, den, num), s);
     const double s2 = s * s;
-    double p = 1.0 / 23.0;
-    p = fma(p, s2, 1.0 / 21.0);
+    double p = 1.0 / 21.0;
     p = fma(p, s2, 1.0 / 19.0);
     p = fma(p, s2, 1.0 / 17.0);
     p = fma(p, s2, 1.0 / 15.0);
@@ -161,7 +161,7 @@ __device__ __forceinline__ void tile_body(const Args &a, const ArgsF &af, int bi
     __shared__ double sx1[L], sy1[L], sx2[L], sy2[L];
     __shared__ Real sJ1[L], sJ2[L];
     __shared__ int se1[WQ ? 1 : L], se2[WQ ? 1 : L];
-    __shared__ Real sinv[WQ ? LT : 1], sw0[WQ ? LT : 1], sw1[WQ ? LT : 1];
+    __shared__ Real sinv[WQ ? LT : 1], sw[WQ ? 2 * LT : 1];   // sw[par * LT + dl]
     __shared__ Real C1[L][T + 1];
     __shared__ Real tileo[T][T + 1];
     constexpr bool kTableLog = !WQ && sizeof(Real) == 8;
@@ -195,12 +195,12 @@ __device__ __forceinline__ void tile_body(const Args &a, const ArgsF &af, int bi
             const int d = (dbase + dl) % npts;
             if constexpr (sizeof(Real) == 8) {
                 sinv[dl] = Real(a.inv_s2[d]);
-                sw0[dl] = Real(a.ws[d]);
-                sw1[dl] = Real(a.ws[npts + d]);
+                sw[dl] = Real(a.ws[d]);
+                sw[LT + dl] = Real(a.ws[npts + d]);
             } else {
                 sinv[dl] = Real(a.inv_s2f[d]);
-                sw0[dl] = Real(a.wsf[d]);
-                sw1[dl] = Real(a.wsf[npts + d]);
+                sw[dl] = Real(a.wsf[d]);
+                sw[LT + dl] = Real(a.wsf[npts + d]);
             }
         }
     }
@@ -213,6 +213,7 @@ __device__ __forceinline__ void tile_body(const Args &a, const ArgsF &af, int bi
         const double x1 = sx1[r], y1 = sy1[r];
         const Real J1 = sJ1[r];
         const int par = (start1 + r) % npts & 1;
+        const Real *swp = WQ ? sw + par * LT : sw;     // singular weights of this row's node class
         const int e1 = WQ ? 0 : se1[r];
         Real acc[S];
 #pragma unroll
@@ -234,7 +235,7 @@ __device__ __forceinline__ void tile_body(const Args &a, const ArgsF &af, int bi
                 const Real inv = sinv[dl];
                 const Real ratio = (inv == Real(0)) ? J1 * J1 : r2 * inv;
                 U = Real(0.5) * k_log<Real, kTableLog>(ratio, ltab);
-                V = par ? sw1[dl] : sw0[dl];
+                V = swp[dl];
             } else {
                 int de = se2[c2] - e1;
                 if (de < 0) de += N;
