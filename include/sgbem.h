@@ -100,9 +100,11 @@ sgbem_status sgbem_ctx_destroy(sgbem_ctx ctx);
 sgbem_status sgbem_ctx_set_stream(sgbem_ctx ctx, void *hip_stream);
 
 /* Timing of the main kernel of every later assembly call: when `on`, the
- * library records a pair of HIP events on the context's stream around the
  * tile kernel of each sgbem_assemble call (WQ: the fused sweep-and-contract
- * kernel; EBE: its far-pair kernel).  Events are kept by the context. */
+ * kernel; EBE: its far-pair kernel) and of each sgbem_batch_assemble call is
+ * launched with a pair of HIP events that its own dispatch records at the start
+ * and the end of its execution, on the context's stream.  Events are kept by
+ * the context. */
 sgbem_status sgbem_ctx_set_timing(sgbem_ctx ctx, int32_t on);
 
 /* Wait for the recorded events and return the summed elapsed milliseconds and

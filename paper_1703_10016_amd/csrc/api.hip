@@ -19,15 +19,15 @@
 #include "curve_eval.hpp"
 
 namespace sgbem {
-hipError_t launch_wq_f64(int p, int P, const TileArgs &a, hipStream_t s);
-hipError_t launch_wq_f32(int p, int P, const TileArgs &a, hipStream_t s);
-hipError_t launch_ebe_f64(int p, int P, const TileArgs &a, hipStream_t s);
-hipError_t launch_ebe_f32(int p, int P, const TileArgs &a, hipStream_t s);
+hipError_t launch_wq_f64(int p, int P, const TileArgs &a, hipStream_t s, const KernelEvents *ev);
+hipError_t launch_wq_f32(int p, int P, const TileArgs &a, hipStream_t s, const KernelEvents *ev);
+hipError_t launch_ebe_f64(int p, int P, const TileArgs &a, hipStream_t s, const KernelEvents *ev);
+hipError_t launch_ebe_f32(int p, int P, const TileArgs &a, hipStream_t s, const KernelEvents *ev);
 
-hipError_t launch_assemble(int method, int prec, int p, int P, const TileArgs &a, hipStream_t s)
+hipError_t launch_assemble(int method, int prec, int p, int P, const TileArgs &a, hipStream_t s, const KernelEvents *ev)
 {
-    if (method == 0) return prec == 0 ? launch_wq_f64(p, P, a, s) : launch_wq_f32(p, P, a, s);
-    return prec == 0 ? launch_ebe_f64(p, P, a, s) : launch_ebe_f32(p, P, a, s);
+    if (method == 0) return prec == 0 ? launch_wq_f64(p, P, a, s, ev) : launch_wq_f32(p, P, a, s, ev);
+    return prec == 0 ? launch_ebe_f64(p, P, a, s, ev) : launch_ebe_f32(p, P, a, s, ev);
 }
 bool assemble_supported(int method, int, int p, int P)
 {
@@ -335,17 +335,21 @@ std::vector<double> gauss_basis_coef(int p, int G)
     return coef;
 }
 
-// Record an event on the context's stream when timing is on (pairs bracket the
-// main kernel of a call).
-sgbem_status mark(sgbem_ctx c)
+// When timing is on: the next pair of the context's events, to be recorded by
+// the main kernel's own dispatch (execution start and end); kev stays NULL
+// when timing is off.
+sgbem_status timing_events(sgbem_ctx c, KernelEvents &ke, const KernelEvents *&kev)
 {
+    kev = nullptr;
     if (!c->timing) return SGBEM_OK;
-    if (c->ev_used == c->ev.size()) {
+    while (c->ev.size() < c->ev_used + 2) {
         hipEvent_t e;
         HIPCHK(hipEventCreate(&e));
         c->ev.push_back(e);
     }
-    HIPCHK(hipEventRecord(c->ev[c->ev_used++], c->stream));
+    ke.start = c->ev[c->ev_used++];
+    ke.stop = c->ev[c->ev_used++];
+    kev = &ke;
     return SGBEM_OK;
 }
 
@@ -569,9 +573,10 @@ sgbem_status sgbem_assemble(sgbem_ctx c, const sgbem_curve *curve, sgbem_rules r
             ta.coefA[q] = r->w0[q];
             ta.coefB[q] = r->bvals[q];
         }
-        if ((st = mark(c))) return st;
-        HIPCHK(launch_assemble(0, precision, p, P, ta, c->stream));
-        if ((st = mark(c))) return st;
+        KernelEvents ke;
+        const KernelEvents *kev;
+        if ((st = timing_events(c, ke, kev))) return st;
+        HIPCHK(launch_assemble(0, precision, p, P, ta, c->stream, kev));
         return SGBEM_OK;
     }
     // ---- element by element: far part by the tile kernel, near pairs by their own rule
@@ -605,9 +610,10 @@ sgbem_status sgbem_assemble(sgbem_ctx c, const sgbem_curve *curve, sgbem_rules r
     ta.J = J;
     const std::vector<double> gc = gauss_basis_coef(p, G);
     for (size_t q = 0; q < gc.size(); ++q) ta.coefA[q] = gc[q] / N;      // h w_g M_p(a + u_g)
-    if ((st = mark(c))) return st;
-    HIPCHK(launch_assemble(1, precision, p, P, ta, c->stream));
-    if ((st = mark(c))) return st;
+    KernelEvents ke;
+    const KernelEvents *kev;
+    if ((st = timing_events(c, ke, kev))) return st;
+    HIPCHK(launch_assemble(1, precision, p, P, ta, c->stream, kev));
     HIPCHK(launch_band(precision, N, p, na.L, ta.scale, d_A, lda, c->stream));
     return SGBEM_OK;
 }
@@ -760,9 +766,10 @@ sgbem_status sgbem_batch_assemble(sgbem_ctx c, sgbem_batch b)
     HIPCHK(launch_batch_geometry(b->d, b->n, b->max_npts, c->stream));
     const int tot = b->total[b->cfg];
     sgbem_status st;
-    if ((st = mark(c))) return st;
-    HIPCHK(launch_batch_tiles(b->cfg, b->prec, b->d, b->n, tot, b->grid, c->stream));
-    if ((st = mark(c))) return st;
+    KernelEvents ke;
+    const KernelEvents *kev;
+    if ((st = timing_events(c, ke, kev))) return st;
+    HIPCHK(launch_batch_tiles(b->cfg, b->prec, b->d, b->n, tot, b->grid, c->stream, kev));
     return SGBEM_OK;
 }
 

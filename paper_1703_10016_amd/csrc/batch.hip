@@ -61,10 +61,14 @@ hipError_t launch_batch_geometry(const BatchDev &d, int n, int max_npts, hipStre
 
 namespace {
 template <typename Real, int T, int S>
-hipError_t launch_one(const BatchDev &d, int cfg, int n, int total, int grid, hipStream_t s)
+hipError_t launch_one(const BatchDev &d, int cfg, int n, int total, int grid, hipStream_t s, const KernelEvents *ev)
 {
-    hipLaunchKernelGGL((batch_tile_kernel<Real, T, S>), dim3(grid), dim3(256), 0, s, d.args, d.argsf, d.deg,
-                       d.prefix[cfg], n, total);
+    if (ev)
+        hipExtLaunchKernelGGL((batch_tile_kernel<Real, T, S>), dim3(grid), dim3(256), 0, s, ev->start, ev->stop, 0,
+                              d.args, d.argsf, d.deg, d.prefix[cfg], n, total);
+    else
+        hipLaunchKernelGGL((batch_tile_kernel<Real, T, S>), dim3(grid), dim3(256), 0, s, d.args, d.argsf, d.deg,
+                           d.prefix[cfg], n, total);
     return hipGetLastError();
 }
 template <typename Real, int T, int S>
@@ -81,21 +85,22 @@ int occupancy_one()
 // tuner's alternatives.
 const BatchConfig kBatchConfigs[kNumBatchConfigs] = {{28, 7}, {32, 8}, {24, 6}, {16, 4}};
 
-hipError_t launch_batch_tiles(int cfg, int prec, const BatchDev &d, int n, int total, int grid, hipStream_t s)
+hipError_t launch_batch_tiles(int cfg, int prec, const BatchDev &d, int n, int total, int grid, hipStream_t s,
+                              const KernelEvents *ev)
 {
     if (prec == 0) {
         switch (cfg) {
-        case 0: return launch_one<double, 28, 7>(d, 0, n, total, grid, s);
-        case 1: return launch_one<double, 32, 8>(d, 1, n, total, grid, s);
-        case 2: return launch_one<double, 24, 6>(d, 2, n, total, grid, s);
-        default: return launch_one<double, 16, 4>(d, 3, n, total, grid, s);
+        case 0: return launch_one<double, 28, 7>(d, 0, n, total, grid, s, ev);
+        case 1: return launch_one<double, 32, 8>(d, 1, n, total, grid, s, ev);
+        case 2: return launch_one<double, 24, 6>(d, 2, n, total, grid, s, ev);
+        default: return launch_one<double, 16, 4>(d, 3, n, total, grid, s, ev);
         }
     }
     switch (cfg) {
-    case 0: return launch_one<float, 28, 7>(d, 0, n, total, grid, s);
-    case 1: return launch_one<float, 32, 8>(d, 1, n, total, grid, s);
-    case 2: return launch_one<float, 24, 6>(d, 2, n, total, grid, s);
-    default: return launch_one<float, 16, 4>(d, 3, n, total, grid, s);
+    case 0: return launch_one<float, 28, 7>(d, 0, n, total, grid, s, ev);
+    case 1: return launch_one<float, 32, 8>(d, 1, n, total, grid, s, ev);
+    case 2: return launch_one<float, 24, 6>(d, 2, n, total, grid, s, ev);
+    default: return launch_one<float, 16, 4>(d, 3, n, total, grid, s, ev);
     }
 }
 

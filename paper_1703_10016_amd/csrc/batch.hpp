@@ -28,7 +28,8 @@ struct BatchDev {
 };
 
 hipError_t launch_batch_geometry(const BatchDev &d, int n, int max_npts, hipStream_t s);
-hipError_t launch_batch_tiles(int cfg, int prec, const BatchDev &d, int n, int total, int grid, hipStream_t s);
+hipError_t launch_batch_tiles(int cfg, int prec, const BatchDev &d, int n, int total, int grid, hipStream_t s,
+                              const KernelEvents *ev = nullptr);
 int batch_blocks_per_cu(int cfg, int prec);
 
 }  // namespace sgbem

@@ -24,7 +24,7 @@ HDR = '''// Instantiations of the tile kernel for {what} in {prec}: one kernel p
 
 namespace sgbem {{
 
-hipError_t {fname}(int p, int P, const TileArgs &a, hipStream_t s)
+hipError_t {fname}(int p, int P, const TileArgs &a, hipStream_t s, const KernelEvents *ev)
 {{
     switch (p * 16 + P) {{
 '''
@@ -56,9 +56,9 @@ def main():
             for (p, P, Q, S0, wq, T, S, big) in cases():
                 k = f"launch_tile<{P}, {Q}, {S0}, {wq}, {real}, {T}, {S}"
                 if big and real == "double":
-                    s += f"    case {p * 16 + P}: return a.N >= 4096 ? {k}, 4>(a, s) : {k}>(a, s);\n"
+                    s += f"    case {p * 16 + P}: return a.N >= 4096 ? {k}, 4>(a, s, ev) : {k}>(a, s, ev);\n"
                 else:
-                    s += f"    case {p * 16 + P}: return {k}>(a, s);\n"
+                    s += f"    case {p * 16 + P}: return {k}>(a, s, ev);\n"
             s += "    default: return hipErrorInvalidValue;\n    }\n}\n\n}  // namespace sgbem\n"
             with open(os.path.join(HERE, f"asm_{tag}_{suf}.hip"), "w") as f:
                 f.write(s)

@@ -53,7 +53,14 @@ struct TileArgs {
 // method 1 = EBE far part (P = G, Q = G (p+1), support starts at point 0).
 // prec 0 = FP64, 1 = FP32.  Returns hipErrorInvalidValue when no kernel is
 // compiled for (p, P).
-hipError_t launch_assemble(int method, int prec, int p, int P, const TileArgs &a, hipStream_t s);
+// Optional timing of a launch: events recorded by the kernel's own dispatch
+// (start and end of its execution), not by separate stream markers.
+struct KernelEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+
+hipError_t launch_assemble(int method, int prec, int p, int P, const TileArgs &a, hipStream_t s,
+                           const KernelEvents *ev = nullptr);
 bool assemble_supported(int method, int prec, int p, int P);
 
 // EBE near pairs: L[(e*2 + type)][a][b], type 0 = coincident, 1 = (e, e+1).

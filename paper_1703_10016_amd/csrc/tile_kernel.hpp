@@ -23,6 +23,7 @@
 // LDS, so the matrix is exactly symmetric (rows i <= j are the computed ones).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -302,7 +303,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, 8))) v
 }
 
 template <int P, int Q, int S0, bool WQ, typename Real, int T, int S, int WPE = 1>
-hipError_t launch_tile(const TileArgs &a, hipStream_t s)
+hipError_t launch_tile(const TileArgs &a, hipStream_t s, const KernelEvents *ev = nullptr)
 {
     TileArgsF af;
     for (int q = 0; q < 64; ++q) {
@@ -312,7 +313,11 @@ hipError_t launch_tile(const TileArgs &a, hipStream_t s)
     const int nb = (a.N + T - 1) / T;
     const int blocks = nb * (nb + 1) / 2;
     using OutT = Real;
-    hipLaunchKernelGGL((tile_kernel<P, Q, S0, WQ, Real, OutT, T, S, WPE>), dim3(blocks), dim3(256), 0, s, a, af);
+    if (ev)
+        hipExtLaunchKernelGGL((tile_kernel<P, Q, S0, WQ, Real, OutT, T, S, WPE>), dim3(blocks), dim3(256), 0, s,
+                              ev->start, ev->stop, 0, a, af);
+    else
+        hipLaunchKernelGGL((tile_kernel<P, Q, S0, WQ, Real, OutT, T, S, WPE>), dim3(blocks), dim3(256), 0, s, a, af);
     return hipGetLastError();
 }
 
