@@ -152,21 +152,45 @@ __global__ __launch_bounds__(1024) void panel_kernel(int N, float *LU, int k0, i
     }
 }
 
+// Wavefront-wide max / min of a 32-bit unsigned value by DPP row operations
+// (quad permutes, row shifts by 4 and 8, row broadcasts 15 and 31: lane 63
+// ends with the result), returned uniform.  Every lane of the wavefront must be
+// active.
+template <bool MAX>
+__device__ __forceinline__ unsigned wave_reduce_u32(unsigned v)
+{
+    auto op = [](unsigned a, unsigned b) { return MAX ? (a > b ? a : b) : (a < b ? a : b); };
+    v = op(v, unsigned(__builtin_amdgcn_update_dpp(int(v), int(v), 0xb1, 0xf, 0xf, false)));
+    v = op(v, unsigned(__builtin_amdgcn_update_dpp(int(v), int(v), 0x4e, 0xf, 0xf, false)));
+    v = op(v, unsigned(__builtin_amdgcn_update_dpp(int(v), int(v), 0x114, 0xf, 0xe, false)));
+    v = op(v, unsigned(__builtin_amdgcn_update_dpp(int(v), int(v), 0x118, 0xf, 0xc, false)));
+    v = op(v, unsigned(__builtin_amdgcn_update_dpp(int(v), int(v), 0x142, 0xa, 0xf, false)));
+    v = op(v, unsigned(__builtin_amdgcn_update_dpp(int(v), int(v), 0x143, 0xc, 0xf, false)));
+    return unsigned(__builtin_amdgcn_readlane(int(v), 63));
+}
+
 // Register-resident panel factorisation (one workgroup of 1024 threads, RT rows
 // per thread, W <= 32 columns): thread t owns the panel rows k0 + r*1024 + t
 // with all W columns in registers.  The column loop is unrolled, so every
 // register index is a compile-time constant.  Per column: pivot = largest
-// magnitude at or below the diagonal (lowest row on ties); the pivot row and
-// the diagonal row exchange their register rows through LDS (earlier L
-// multipliers included: a row interchange of the panel) -- only the two
-// owning wavefronts execute that copy; the rows below are scaled and updated.
-// Global memory is touched only to load the panel and to store it, the
-// pivots and info at the end; two barriers per column.
+// magnitude at or below the diagonal, lowest row on ties.  Each wavefront finds
+// its own candidate (two DPP reductions: the largest magnitude, then the lowest
+// row holding it) and publishes it with the candidate row's values; the owner
+// of the diagonal row publishes that row.  After the column's one barrier every
+// thread reduces the 16 candidates the same way (the winning wavefront is the
+// owner of the pivot row), interchanges the two rows in registers (earlier L
+// multipliers included: a row interchange of the panel), scales and updates
+// the rows below.  The published values are double-buffered by column parity:
+// a wavefront can write a buffer again only after the next column's barrier,
+// which every wavefront reaches after its last read of it.  Global memory is
+// touched only to load the panel and to store it, the pivots and info.
 template <int RT, int W>
 __global__ __launch_bounds__(1024) void panel_reg_kernel(int N, float *LU, int k0, int w, int *piv, int *info)
 {
-    __shared__ unsigned long long skey[16];
-    __shared__ float prow[W], jrow[W];
+    __shared__ unsigned smag[2][16];
+    __shared__ int srow[2][16];
+    __shared__ float crow[2][16][W];     // each wavefront's candidate row
+    __shared__ float jrow[2][W];         // the diagonal row
     __shared__ int pivs[W];
     __shared__ int sinfo;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -181,52 +205,51 @@ __global__ __launch_bounds__(1024) void panel_reg_kernel(int N, float *LU, int k
 #pragma unroll
     for (int j = 0; j < W; ++j) {
         if (j < w) {
-            const int gj = k0 + j;
-            // pivot key: |value| bits (monotone for non-negative floats) high, inverted row low,
-            // so the largest key is the largest magnitude with the lowest row on ties
-            unsigned long long key = 0ull;
+            const int gj = k0 + j, buf = j & 1;
+            // this thread's candidate: magnitude bits (monotone for non-negative floats), lowest row on ties
+            unsigned mag = 0u;
+            int row = 0x7fffffff;
 #pragma unroll
             for (int r = 0; r < RT; ++r) {
                 const int i = k0 + r * 1024 + tid;
-                if (i >= gj && i < N) {
-                    const unsigned long long k = (static_cast<unsigned long long>(__float_as_uint(fabsf(a[r][j]))) << 32) |
-                                                 static_cast<unsigned int>(0x7fffffff - i);
-                    key = k > key ? k : key;
+                const unsigned m = __float_as_uint(fabsf(a[r][j]));
+                if (i >= gj && i < N && (m > mag || (m == mag && i < row))) {
+                    mag = m;
+                    row = i;
                 }
             }
-            for (int off = 32; off > 0; off >>= 1) {
-                const unsigned long long o = __shfl_xor(key, off);
-                key = o > key ? o : key;
-            }
-            if (lane == 0) skey[wid] = key;
-            __syncthreads();
-            key = skey[lane & 15];
-            for (int off = 8; off > 0; off >>= 1) {
-                const unsigned long long o = __shfl_xor(key, off);
-                key = o > key ? o : key;
-            }
-            const float b = __uint_as_float(static_cast<unsigned int>(key >> 32));
-            int pr = 0x7fffffff - static_cast<int>(key & 0xffffffffull);
-            if (!(b > 0.0f)) pr = gj;
-            if (tid == 0) {
-                if (!(b > 0.0f) && sinfo == 0) sinfo = gj + 1;
-                pivs[j] = pr;
-            }
+            const unsigned wmag = wave_reduce_u32<true>(mag);
+            const int wrow = int(wave_reduce_u32<false>(mag == wmag ? unsigned(row) : 0x7fffffffu));
 #pragma unroll
             for (int r = 0; r < RT; ++r) {
                 const int i = k0 + r * 1024 + tid;
-                if (i == pr) {
+                if (i == wrow) {
 #pragma unroll
-                    for (int c = 0; c < W; ++c) prow[c] = a[r][c];
+                    for (int c = 0; c < W; ++c) crow[buf][wid][c] = a[r][c];
                 }
                 if (i == gj) {
 #pragma unroll
-                    for (int c = 0; c < W; ++c) jrow[c] = a[r][c];
+                    for (int c = 0; c < W; ++c) jrow[buf][c] = a[r][c];
                 }
             }
+            if (lane == 0) {
+                smag[buf][wid] = wmag;
+                srow[buf][wid] = wrow;
+            }
             __syncthreads();
+            const unsigned cm = smag[buf][lane & 15], cr = unsigned(srow[buf][lane & 15]);
+            const unsigned gm = wave_reduce_u32<true>(lane < 16 ? cm : 0u);
+            const int gr = int(wave_reduce_u32<false>(lane < 16 && cm == gm ? cr : 0x7fffffffu));
+            const float b = __uint_as_float(gm);
+            const bool ok = b > 0.0f;
+            const int pr = ok ? gr : gj;
+            const float *prow = ok ? crow[buf][((pr - k0) & 1023) >> 6] : jrow[buf];
+            if (tid == 0) {
+                if (!ok && sinfo == 0) sinfo = gj + 1;
+                pivs[j] = pr;
+            }
             const float d = prow[j];
-            const float inv = d != 0.0f ? 1.0f / d : 0.0f;
+            const float inv = ok ? 1.0f / d : 0.0f;
 #pragma unroll
             for (int r = 0; r < RT; ++r) {
                 const int i = k0 + r * 1024 + tid;
@@ -235,18 +258,15 @@ __global__ __launch_bounds__(1024) void panel_reg_kernel(int N, float *LU, int k
                     for (int c = 0; c < W; ++c) a[r][c] = prow[c];
                 } else if (i == pr) {
 #pragma unroll
-                    for (int c = 0; c < W; ++c) a[r][c] = jrow[c];
+                    for (int c = 0; c < W; ++c) a[r][c] = jrow[buf][c];
                 }
-                if (i > gj && i < N && d != 0.0f) {
+                if (i > gj && i < N && ok) {
                     const float l = a[r][j] * inv;
                     a[r][j] = l;
 #pragma unroll
                     for (int c = j + 1; c < W; ++c) a[r][c] -= l * prow[c];
                 }
             }
-            // No third barrier: skey/prow/jrow of the next column are written only
-            // after the next column's first barrier, which every wavefront reaches
-            // after its last read of this column's values.
         }
     }
 #pragma unroll
@@ -278,8 +298,12 @@ __global__ void laswp_kernel(int N, float *LU, int k0, int w, const int *piv)
     }
 }
 
-// U12 = L11^{-1} A12: one wavefront per column of A12, lane r holds row k0 + r.
-__global__ __launch_bounds__(256) void trsm_kernel(int N, float *LU, int k0, int w)
+// For the narrow panel at k0 (w <= 64 columns), on the block columns
+// [cb, ce) outside the panel: apply the panel's row interchanges, then for the
+// columns right of the panel solve U12 = L11^{-1} A12.  One wavefront per
+// column: lane 0 applies the interchanges in order, the workgroup barrier makes
+// them visible, then lane r holds row k0 + r for the solve.
+__global__ __launch_bounds__(256) void swap_trsm_kernel(int N, float *LU, int k0, int w, const int *piv, int cb, int ce)
 {
     __shared__ float L[NB][NB + 1];
     const int tid = threadIdx.x;
@@ -287,11 +311,24 @@ __global__ __launch_bounds__(256) void trsm_kernel(int N, float *LU, int k0, int
         const int r = e % w, c = e / w;
         L[r][c] = LU[int64_t(k0 + c) * N + k0 + r];
     }
-    __syncthreads();
     const int lane = tid & 63;
-    const int col = k0 + w + blockIdx.x * 4 + (tid >> 6);
-    if (col >= N) return;
-    float *cp = LU + int64_t(col) * N + k0;
+    int col = cb + blockIdx.x * 4 + (tid >> 6);
+    if (col >= k0) col += w;
+    const bool valid = col < ce;
+    float *cp = LU + int64_t(valid ? col : 0) * N;
+    if (valid && lane == 0) {
+        for (int j = k0; j < k0 + w; ++j) {
+            const int pr = piv[j];
+            if (pr != j) {
+                const float a = cp[j];
+                cp[j] = cp[pr];
+                cp[pr] = a;
+            }
+        }
+    }
+    __syncthreads();
+    if (!valid || col < k0) return;
+    cp += k0;
     float x = lane < w ? cp[lane] : 0.0f;
     for (int s = 0; s < w; ++s) {
         const float xs = __shfl(x, s);
@@ -300,48 +337,97 @@ __global__ __launch_bounds__(256) void trsm_kernel(int N, float *LU, int k0, int
     if (lane < w) cp[lane] = x;
 }
 
-// C -= L21 U12 on FP32 MFMA (16x16x4): the workgroup owns a 64 x 64 block of
-// the trailing matrix; each wavefront a 32 x 32 quarter as 2 x 2 MFMA tiles.
-// The MFMA "rows" index the columns of C and its "columns" the rows of C, so
-// each lane's results are contiguous in the column-major factor.
-__global__ __launch_bounds__(256) void gemm_update_kernel(int N, float *LU, int k0, int w)
+// U12 = L11^{-1} A12 for a block of bk <= 128 factored columns at K0, on the
+// columns [c0, N): L11 (unit lower) in LDS; each wavefront solves two columns
+// at once (their dependent chains interleave), lane l holding rows K0 + l and
+// K0 + 64 + l of both, the solved value of each step broadcast by readlane.
+__global__ __launch_bounds__(1024) void trsm_block_kernel(int N, float *LU, int K0, int bk, int c0)
 {
-    __shared__ float As[64][NB + 1];   // L21 block: [row][k]
-    __shared__ float Bs[64][NB + 1];   // U12 block transposed: [col][k]
-    const int m0 = k0 + w + blockIdx.x * 64;    // first row of C
-    const int n0 = k0 + w + blockIdx.y * 64;    // first column of C
+    __shared__ float L[128][129];
     const int tid = threadIdx.x;
-    for (int e = tid; e < 64 * w; e += blockDim.x) {
-        const int r = e & 63, k = e >> 6;
-        As[r][k] = (m0 + r < N) ? LU[int64_t(k0 + k) * N + m0 + r] : 0.0f;
-    }
-    for (int e = tid; e < 64 * w; e += blockDim.x) {
-        const int k = e % w, c = e / w;
-        Bs[c][k] = (n0 + c < N) ? LU[int64_t(n0 + c) * N + k0 + k] : 0.0f;
+    for (int e = tid; e < bk * bk; e += blockDim.x) {
+        const int r = e % bk, c = e / bk;
+        L[r][c] = LU[int64_t(K0 + c) * N + K0 + r];
     }
     __syncthreads();
+    const int lane = tid & 63, wave = tid >> 6;
+    const int ca = c0 + blockIdx.x * 32 + 2 * wave, cb = ca + 1;
+    if (ca >= N) return;
+    const bool hb = cb < N;
+    float *pa = LU + int64_t(ca) * N + K0;
+    float *pb = LU + int64_t(hb ? cb : ca) * N + K0;
+    float x0a = lane < bk ? pa[lane] : 0.0f, x1a = lane + 64 < bk ? pa[lane + 64] : 0.0f;
+    float x0b = lane < bk ? pb[lane] : 0.0f, x1b = lane + 64 < bk ? pb[lane + 64] : 0.0f;
+    for (int s = 0; s < bk; ++s) {
+        const float xa = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(s < 64 ? x0a : x1a), s & 63));
+        const float xb = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(s < 64 ? x0b : x1b), s & 63));
+        if (lane > s && lane < bk) {
+            const float l = L[lane][s];
+            x0a -= l * xa;
+            x0b -= l * xb;
+        }
+        if (lane + 64 > s && lane + 64 < bk) {
+            const float l = L[lane + 64][s];
+            x1a -= l * xa;
+            x1b -= l * xb;
+        }
+    }
+    if (lane < bk) pa[lane] = x0a;
+    if (lane + 64 < bk) pa[lane + 64] = x1a;
+    if (hb) {
+        if (lane < bk) pb[lane] = x0b;
+        if (lane + 64 < bk) pb[lane + 64] = x1b;
+    }
+}
+
+// C -= L21 U12 on FP32 MFMA (16x16x4) for C = LU[r0:N, c0:cend],
+// L21 = LU[r0:N, kb:kb+klen], U12 = LU[kb:kb+klen, c0:cend]: the workgroup owns a
+// 64 x 64 block of C, each wavefront a 32 x 32 quarter as 2 x 2 MFMA tiles; K
+// runs in chunks of 32 staged through LDS (zero-padded past klen).  The MFMA
+// "rows" index the columns of C and its "columns" the rows of C, so each lane's
+// results are contiguous in the column-major factor.
+__global__ __launch_bounds__(256) void gemm_update_kernel(int N, float *LU, int r0, int c0, int cend, int kb, int klen)
+{
+    __shared__ float As[64][33];   // L21 chunk: [row][k]
+    __shared__ float Bs[64][33];   // U12 chunk transposed: [col][k]
+    const int m0 = r0 + blockIdx.x * 64;    // first row of C
+    const int n0 = c0 + blockIdx.y * 64;    // first column of C
+    const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const int wc = (wave >> 1) * 32;    // C columns of this wave
     const int wr = (wave & 1) * 32;     // C rows of this wave
     floatx4 acc[2][2];
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b) acc[a][b] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-    for (int k = 0; k < w; k += 4) {
-        const int kk = k + (lane >> 4);
-        for (int a = 0; a < 2; ++a) {
-            const float av = Bs[wc + a * 16 + (lane & 15)][kk];   // MFMA A: [C column][k]
-            for (int b = 0; b < 2; ++b) {
-                const float bv = As[wr + b * 16 + (lane & 15)][kk]; // MFMA B: [k][C row]
-                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[a][b], 0, 0, 0);
+    for (int kc = 0; kc < klen; kc += 32) {
+        const int kl = min(32, klen - kc);
+        for (int e = tid; e < 64 * 32; e += blockDim.x) {
+            const int r = e & 63, k = e >> 6;
+            As[r][k] = (m0 + r < N && k < kl) ? LU[int64_t(kb + kc + k) * N + m0 + r] : 0.0f;
+        }
+        for (int e = tid; e < 64 * 32; e += blockDim.x) {
+            const int k = e & 31, c = e >> 5;
+            Bs[c][k] = (n0 + c < cend && k < kl) ? LU[int64_t(n0 + c) * N + kb + kc + k] : 0.0f;
+        }
+        __syncthreads();
+        for (int k = 0; k < kl; k += 4) {
+            const int kk = k + (lane >> 4);
+            for (int a = 0; a < 2; ++a) {
+                const float av = Bs[wc + a * 16 + (lane & 15)][kk];   // MFMA A: [C column][k]
+                for (int b = 0; b < 2; ++b) {
+                    const float bv = As[wr + b * 16 + (lane & 15)][kk]; // MFMA B: [k][C row]
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[a][b], 0, 0, 0);
+                }
             }
         }
+        __syncthreads();
     }
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b)
             for (int i = 0; i < 4; ++i) {
                 const int c = n0 + wc + a * 16 + 4 * (lane >> 4) + i;
                 const int r = m0 + wr + b * 16 + (lane & 15);
-                if (r < N && c < N) LU[int64_t(c) * N + r] -= acc[a][b][i];
+                if (r < N && c < cend) LU[int64_t(c) * N + r] -= acc[a][b][i];
             }
 }
 
@@ -520,37 +606,60 @@ size_t solve_workspace_bytes(int N)
 
 hipError_t lu_factor_f32(int N, float *LU, int *piv, int *info, void *diag_inv, hipStream_t s)
 {
+    // Two levels: blocks of BK columns, each factored by narrow register panels
+    // whose triangular solves and updates stay inside the block; then one
+    // triangular solve for the block's U12 and one rank-BK update of the
+    // trailing matrix (the MFMA-bound part).  Row interchanges always go to
+    // the full rows.  Up to N = 4096 one block spans the matrix (every narrow
+    // panel updates the whole trailing matrix): there the launches saved
+    // outweigh the traffic of the narrow updates (measured).
+    const int BK = N <= 4096 ? N : 128;
     hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(64), 0, s, info);
-    for (int k0 = 0; k0 < N;) {
-        const int m = N - k0;
-        int w;
-        // register panels while the rows fit (1, 2, 4, 8 rows per thread), narrower as they grow
-        if (m <= 1024) {
-            w = std::min(32, m);
-            hipLaunchKernelGGL((panel_reg_kernel<1, 32>), dim3(1), dim3(1024), 0, s, N, LU, k0, w, piv, info);
-        } else if (m <= 2048) {
-            w = 16;
-            hipLaunchKernelGGL((panel_reg_kernel<2, 16>), dim3(1), dim3(1024), 0, s, N, LU, k0, w, piv, info);
-        } else if (m <= 4096) {
-            w = 8;
-            hipLaunchKernelGGL((panel_reg_kernel<4, 8>), dim3(1), dim3(1024), 0, s, N, LU, k0, w, piv, info);
-        } else if (m <= 8192) {
-            w = 8;
-            hipLaunchKernelGGL((panel_reg_kernel<8, 8>), dim3(1), dim3(1024), 0, s, N, LU, k0, w, piv, info);
-        } else {
-            w = 32;
-            hipLaunchKernelGGL(panel_kernel, dim3(1), dim3(1024), 0, s, N, LU, k0, w, piv, info);
+    for (int K0 = 0; K0 < N; K0 += BK) {
+        const int KE = std::min(N, K0 + BK);
+        for (int k0 = K0; k0 < KE;) {
+            const int m = N - k0;
+            int w;
+            // register panels while the rows fit (1, 2, 4, 8 rows per thread), narrower as they grow
+            if (m <= 1024) {
+                w = std::min(32, KE - k0);
+                hipLaunchKernelGGL((panel_reg_kernel<1, 32>), dim3(1), dim3(1024), 0, s, N, LU, k0, w, piv, info);
+            } else if (m <= 2048) {
+                w = std::min(16, KE - k0);
+                hipLaunchKernelGGL((panel_reg_kernel<2, 16>), dim3(1), dim3(1024), 0, s, N, LU, k0, w, piv, info);
+            } else if (m <= 4096) {
+                w = std::min(8, KE - k0);
+                hipLaunchKernelGGL((panel_reg_kernel<4, 8>), dim3(1), dim3(1024), 0, s, N, LU, k0, w, piv, info);
+            } else if (m <= 8192) {
+                w = std::min(8, KE - k0);
+                hipLaunchKernelGGL((panel_reg_kernel<8, 8>), dim3(1), dim3(1024), 0, s, N, LU, k0, w, piv, info);
+            } else {
+                w = std::min(32, KE - k0);
+                hipLaunchKernelGGL(panel_kernel, dim3(1), dim3(1024), 0, s, N, LU, k0, w, piv, info);
+            }
+            // the panel's interchanges on the other block columns, U12 right of it
+            const int others = KE - K0 - w;
+            if (others > 0)
+                hipLaunchKernelGGL(swap_trsm_kernel, dim3((others + 3) / 4), dim3(256), 0, s, N, LU, k0, w, piv, K0, KE);
+            const int rin = KE - k0 - w;   // block columns right of the narrow panel
+            if (rin > 0)
+                hipLaunchKernelGGL(gemm_update_kernel, dim3((N - k0 - w + 63) / 64, (rin + 63) / 64), dim3(256), 0, s,
+                                   N, LU, k0 + w, k0 + w, KE, k0, w);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            k0 += w;
         }
-        if (N - w > 0) hipLaunchKernelGGL(laswp_kernel, dim3((N - w + 255) / 256), dim3(256), 0, s, N, LU, k0, w, piv);
-        const int rest = N - k0 - w;
+        // the block's interchanges on the columns outside it (left: L of earlier blocks; right: A12, A22)
+        if (N - (KE - K0) > 0)
+            hipLaunchKernelGGL(laswp_kernel, dim3((N - (KE - K0) + 255) / 256), dim3(256), 0, s, N, LU, K0, KE - K0, piv);
+        const int rest = N - KE;
         if (rest > 0) {
-            hipLaunchKernelGGL(trsm_kernel, dim3((rest + 3) / 4), dim3(256), 0, s, N, LU, k0, w);
+            hipLaunchKernelGGL(trsm_block_kernel, dim3((rest + 31) / 32), dim3(1024), 0, s, N, LU, K0, KE - K0, KE);
             const int nbk = (rest + 63) / 64;
-            hipLaunchKernelGGL(gemm_update_kernel, dim3(nbk, nbk), dim3(256), 0, s, N, LU, k0, w);
+            hipLaunchKernelGGL(gemm_update_kernel, dim3(nbk, nbk), dim3(256), 0, s, N, LU, KE, KE, N, K0, KE - K0);
         }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        k0 += w;
     }
     if (diag_inv) hipLaunchKernelGGL(invert_diag_kernel, dim3((N + 63) / 64), dim3(64), 0, s, N, LU, static_cast<float *>(diag_inv));
     return hipGetLastError();

@@ -175,7 +175,8 @@ def test_rhs_matches_oracle(ctx, method, R, G):
 
 
 # ------------------------------------------------------------------ solve
-@pytest.mark.parametrize("N,prec", [(256, "fp64"), (200, "fp32"), (1000, "fp64"), (2500, "fp64")])
+@pytest.mark.parametrize("N,prec", [(256, "fp64"), (200, "fp32"), (1000, "fp64"), (2500, "fp64"), (4500, "fp32"),
+                                    (9000, "fp64")])
 def test_mixed_solve_matches_fp64_solve(ctx, N, prec):
     curve, p = synth.star(13), 3
     A = ctx.assemble(curve, p, N, "wq", precision=prec)
