@@ -22,6 +22,10 @@ Parts:
 * ``wq`` (O3): the weighted-quadrature rules (Alg. 1, Alg. 2, modified moments)
   and the row assembly of eqs. IK1e2 / IK1e2_bis with dense linear algebra.
 * ``solve``: dense FP64 solve of A alpha = beta (eq. sistlin).
+* ``direct`` (O4): right-hand side of the direct formulation, eq. final_b2
+  with the rule of Section 5 (regular weighted outer rule, composite Gauss
+  inner rule), F = b1/2 - b2/(2 pi) (eq. seconda_BIE), and the outward flux of
+  a harmonic function for the convergence pin.
 
 Every function is FP64 and written for readability, not speed.
 """
