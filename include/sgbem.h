@@ -213,6 +213,29 @@ sgbem_status sgbem_assemble(sgbem_ctx ctx, const sgbem_curve *curve, sgbem_rules
 sgbem_status sgbem_rhs(sgbem_ctx ctx, const sgbem_curve *curve, sgbem_rules rules,
                        int32_t method, int32_t n_gauss, const double *d_g, double *d_beta);
 
+/*
+ * Right-hand side of the direct formulation (Section 2, eq. seconda_BIE in the
+ * weak form eq. weakpb), whose solution with the sgbem_assemble matrix is the
+ * outward flux q = du/dn:  F_i = b1_i / 2 - b2_i / (2 pi), FP64, with b1 of
+ * eq. final_b1 and b2 of eq. final_b2,
+ *   b2_i = int B_i(s) J(s) int Kbar(s, t) u_D(t) dt ds,
+ *   Kbar(s, t) = [(f1(t) - f1(s)) f2'(t) - (f2(t) - f2(s)) f1'(t)] / |f(s) - f(t)|^2
+ * (the normal derivative of ln|x - y| for the outward normal of a
+ * counter-clockwise curve, times J(t); the expression printed in Section 3.2
+ * has the opposite sign, that of a clockwise parametrisation), by the rule of
+ * Section 5: the regular weighted rule of `rules` outside, composite
+ * Gauss-Legendre with n_gauss points per element inside.
+ *  d_g_nodes: device [2 n_ref N] FP64, u_D at sgbem_rhs_points(SGBEM_WQ);
+ *  d_g_gauss: device [N n_gauss] FP64, u_D at sgbem_rhs_points(SGBEM_EBE, n_gauss);
+ *  d_F: device [N] FP64 (output); d_b2: device [N] FP64 or NULL (b2 alone).
+ * n_gauss in {2, 4, 6, 8} (even, so that no Gauss point falls on a node).
+ * Needs a curve with continuous curvature (Section 3.2); workspace of
+ * (5 N n_gauss + (chunks + 2) 2 n_ref N) doubles is kept by the context.
+ * Asynchronous.  Errors: E_INVAL, E_NOMEM, E_DEVICE.
+ */
+sgbem_status sgbem_rhs_direct(sgbem_ctx ctx, const sgbem_curve *curve, sgbem_rules rules, int32_t n_gauss,
+                              const double *d_g_nodes, const double *d_g_gauss, double *d_F, double *d_b2);
+
 /* ---------------------------------------------------------------- batches */
 
 /*

@@ -17,6 +17,7 @@
 #include "solve.hpp"
 #include "batch.hpp"
 #include "curve_eval.hpp"
+#include "dlayer.hpp"
 
 namespace sgbem {
 hipError_t launch_wq_f64(int p, int P, const TileArgs &a, hipStream_t s, const KernelEvents *ev);
@@ -394,7 +395,7 @@ sgbem_status sgbem_ctx_destroy(sgbem_ctx c)
     if (!c) return SGBEM_OK;
     DeviceGuard g(c->device);
     (void)hipStreamSynchronize(c->stream);
-    for (DevBuf *b : {&c->geo, &c->geo16, &c->nearL, &c->params, &c->solve_ws})
+    for (DevBuf *b : {&c->geo, &c->geo16, &c->nearL, &c->params, &c->solve_ws, &c->dl})
         if (b->ptr) (void)hipFree(b->ptr);
     for (auto &kv : c->tables) (void)hipFree(kv.second);
     for (auto *r : c->rules) free_rules(r);
@@ -644,6 +645,45 @@ sgbem_status sgbem_rhs(sgbem_ctx c, const sgbem_curve *curve, sgbem_rules r, int
     const double *dcoef = nullptr;
     if ((st = cached_table(c, 1000 + 64 * p + G, gauss_basis_coef(p, G), dcoef))) return st;
     HIPCHK(launch_rhs(N, grid.npts, G, 0, G * (p + 1), dcoef, 1.0 / N, J, d_g, d_beta, c->stream));
+    return SGBEM_OK;
+}
+
+sgbem_status sgbem_rhs_direct(sgbem_ctx c, const sgbem_curve *curve, sgbem_rules r, int32_t n_gauss,
+                              const double *d_g_nodes, const double *d_g_gauss, double *d_F, double *d_b2)
+{
+    if (!c || !r || !d_g_nodes || !d_g_gauss || !d_F) return set_err(SGBEM_E_INVAL, "NULL argument");
+    if (!valid_rules(c, r)) return set_err(SGBEM_E_INVAL, "rules handle does not belong to this context");
+    if (n_gauss < 2 || n_gauss > 8 || (n_gauss & 1))
+        return set_err(SGBEM_E_INVAL, "n_gauss must be 2, 4, 6 or 8 (even: no Gauss point on a node)");
+    DeviceGuard g(c->device);
+    CurveDev cd;
+    sgbem_status st = upload_curve(c, curve, cd);
+    if (st) return st;
+    const int N = r->N, G = n_gauss;
+    const GridDesc nodes = wq_grid(r);
+    double *X1, *Y1, *J1;
+    if ((st = geometry(c, cd, nodes, c->geo, X1, Y1, J1))) return st;
+    const GridDesc gg = gauss_grid(N, G);
+    GaussW gw;
+    {
+        double gx[32], gwt[32];
+        gauss_legendre01(G, gx, gwt);
+        for (int q = 0; q < 8; ++q) gw.w[q] = q < G ? gwt[q] / N : 0.0;
+    }
+    const int nn = nodes.npts, np = gg.npts;
+    const int nchunk = dl_chunks(nn, np);
+    const size_t bytes = sizeof(double) * (size_t(5) * np + size_t(nchunk) * nn + 2 * size_t(nn));
+    if ((st = ensure(c, c->dl, bytes))) return st;
+    double *X2 = static_cast<double *>(c->dl.ptr), *Y2 = X2 + np, *DX2 = Y2 + np, *DY2 = DX2 + np, *coef = DY2 + np;
+    double *part = coef + np, *h = part + size_t(nchunk) * nn, *v = h + nn;
+    HIPCHK(launch_dl_geometry(cd, gg, gw, d_g_gauss, X2, Y2, DX2, DY2, coef, c->stream));
+    KernelEvents ke;
+    const KernelEvents *kev;
+    if ((st = timing_events(c, ke, kev))) return st;
+    HIPCHK(launch_dl_sweep(nn, X1, Y1, np, X2, Y2, DX2, DY2, coef, nchunk, part, c->stream, kev));
+    HIPCHK(launch_dl_reduce(nn, nchunk, part, d_g_nodes, h, d_b2 ? v : nullptr, c->stream));
+    HIPCHK(launch_rhs(N, nn, 2 * r->R, 1, r->Q, r->d_w0, 1.0, J1, h, d_F, c->stream));
+    if (d_b2) HIPCHK(launch_rhs(N, nn, 2 * r->R, 1, r->Q, r->d_w0, 1.0, J1, v, d_b2, c->stream));
     return SGBEM_OK;
 }
 

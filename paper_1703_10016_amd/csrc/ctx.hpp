@@ -76,7 +76,7 @@ struct sgbem_batch_s {
 struct sgbem_ctx_s {
     int device = 0;
     hipStream_t stream = nullptr;
-    sgbem::DevBuf geo, geo16, nearL, params, solve_ws;
+    sgbem::DevBuf geo, geo16, nearL, params, solve_ws, dl;
     std::vector<sgbem_rules_s *> rules;
     std::vector<sgbem_batch_s *> batches;
     // geometry-independent element-by-element tables, uploaded once per key:

@@ -39,12 +39,13 @@ __host__ __device__ inline void sin_cos(double x, double *s, double *c)
 #endif
 }
 
-__host__ __device__ __forceinline__ void eval_curve(const CurveDev &c, double t, double &x, double &y, double &J)
+// f(t) and f'(t)
+__host__ __device__ __forceinline__ void eval_curve_d(const CurveDev &c, double t, double &x, double &y, double &dx,
+                                                      double &dy)
 {
     const double *ca = c.inline_data ? c.inl : c.a;
     const double *cphi = c.inline_data ? c.inl + 64 : c.phi;
     const double *cq = c.inline_data ? c.inl : c.ctrl;
-    double dx, dy;
     if (c.kind == 1) {
         double sn, cs;
         sincos_pi(2.0 * t, &sn, &cs);
@@ -104,6 +105,13 @@ __host__ __device__ __forceinline__ void eval_curve(const CurveDev &c, double t,
         dx = qx[dd];
         dy = qy[dd];
     }
+}
+
+// f(t) and J(t) = |f'(t)|
+__host__ __device__ __forceinline__ void eval_curve(const CurveDev &c, double t, double &x, double &y, double &J)
+{
+    double dx, dy;
+    eval_curve_d(c, t, x, y, dx, dy);
     J = std::sqrt(dx * dx + dy * dy);
 }
 

@@ -65,6 +65,16 @@ class Context:
                     beta.data_ptr())
         return beta
 
+    def rhs_direct(self, curve, p, N, g, n_gauss=4, n_ref=1, with_b2=False):
+        """F = b1/2 - b2/(2 pi) of the direct formulation (and b2 when asked)."""
+        gn = self.sample(g, self.rhs_points(curve, p, N, "wq", n_ref))
+        gg = self.sample(g, self.rhs_points(curve, p, N, "ebe", n_ref, n_gauss))
+        F = self.torch.empty(N, dtype=self.torch.float64, device=self.device)
+        b2 = self.torch.empty(N, dtype=self.torch.float64, device=self.device) if with_b2 else None
+        S.sgbem_rhs_direct(self.ctx, curve, self.rules(p, N, n_ref), n_gauss, gn.data_ptr(), gg.data_ptr(),
+                           F.data_ptr(), b2.data_ptr() if with_b2 else None)
+        return (F, b2) if with_b2 else F
+
     def solve(self, A, beta, tol=1e-12, max_iter=30, check=True):
         N = A.shape[0]
         prec = S.SGBEM_FP64 if A.dtype == self.torch.float64 else S.SGBEM_FP32

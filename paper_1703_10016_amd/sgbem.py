@@ -102,6 +102,7 @@ def lib():
             "sgbem_batch_tune": [vp, vp, i32, ctypes.POINTER(i32), ctypes.POINTER(dbl)],
             "sgbem_batch_free": [vp, vp],
             "sgbem_node_points_host": [cp, i32, i32, dp],
+            "sgbem_rhs_direct": [vp, cp, vp, i32, vp, vp, vp, vp],
             "sgbem_server_footprint": [i32, i32, ctypes.POINTER(i64)],
             "sgbem_server_create": [ctypes.POINTER(sgbem_server_config), ctypes.POINTER(vp)],
             "sgbem_server_submit": [vp, ctypes.POINTER(sgbem_request)],
@@ -135,7 +136,7 @@ def exported_symbols():
             "sgbem_assemble", "sgbem_rhs", "sgbem_solve", "sgbem_batch_create", "sgbem_batch_assemble",
             "sgbem_batch_tune", "sgbem_batch_free", "sgbem_node_points_host", "sgbem_server_footprint",
             "sgbem_server_create", "sgbem_server_submit", "sgbem_server_poll", "sgbem_server_clock",
-            "sgbem_server_stats", "sgbem_server_destroy"]
+            "sgbem_server_stats", "sgbem_server_destroy", "sgbem_rhs_direct"]
 
 
 # ------------------------------------------------------------------ curve marshalling
@@ -342,3 +343,10 @@ def sgbem_server_stats(server):
 
 def sgbem_server_destroy(server):
     _check(lib().sgbem_server_destroy(server))
+
+
+def sgbem_rhs_direct(ctx, curve, rules, n_gauss, d_g_nodes_ptr, d_g_gauss_ptr, d_F_ptr, d_b2_ptr=None):
+    c = _as_curve(curve)
+    _check(lib().sgbem_rhs_direct(ctx, c.ref(), rules, int(n_gauss), ctypes.c_void_p(d_g_nodes_ptr),
+                                  ctypes.c_void_p(d_g_gauss_ptr), ctypes.c_void_p(d_F_ptr),
+                                  ctypes.c_void_p(d_b2_ptr) if d_b2_ptr else None))
