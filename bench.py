@@ -17,6 +17,8 @@ Also measured in the same run (reported beside the headline value):
    solve), p50 / p99 over repeated requests;
  * the fused kernel's duration from HIP events on its stream -> roofline;
  * FP32 and FP64 throughput at N = 16384 (a star curve, one assembly each);
+ * the direct formulation's right-hand side (double-layer sweep, eq. final_b2)
+   at the workload and at N = 16384;
  * a batch of 256 star curves (N in [128, 2048], p in {2, 3}, FP32) in one
    autotuned persistent launch replayed from a HIP graph, against 256
    sequential single-curve launches;
@@ -40,6 +42,7 @@ PEAK_FP64 = 78.6e12          # MI355X FP64 vector, FLOP/s
 PEAK_FP32 = 157.3e12         # MI355X FP32 vector, FLOP/s
 PEAK_HBM = 8.0e12            # bytes/s
 FLOPS_PER_LOG = 20           # cost model of one logarithm
+DL_FLOPS_PER_EVAL = 11       # double-layer kernel value: 2 differences, numerator and denominator (3 each), 1 division, 1 multiply-add
 
 
 def wq_flops_per_entry(p: int, R: int) -> float:
@@ -306,6 +309,35 @@ def main():
             del Ab
         torch.cuda.empty_cache()
 
+    # ---------------------------------------------------------------- direct formulation: double-layer sweep
+    direct_rhs = {}
+    if not args.no_scale:
+        for label, crv, pd, Nd in (("ellipse", curve, p, N), ("star", synth.star(0), 3, 16384)):
+            G = 4
+            gn = ctx.sample(g, ctx.rhs_points(crv, pd, Nd, "wq"))
+            gg = ctx.sample(g, ctx.rhs_points(crv, pd, Nd, "ebe", 1, G))
+            Fd = torch.empty(Nd, dtype=torch.float64, device="cuda")
+            rl = ctx.rules(pd, Nd, 1)
+            S.sgbem_rhs_direct(ctx.ctx, crv, rl, G, gn.data_ptr(), gg.data_ptr(), Fd.data_ptr())
+            torch.cuda.synchronize()
+            S.sgbem_ctx_set_timing(ctx.ctx, 1)
+            reps = 20 if Nd <= 4096 else 3
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                S.sgbem_rhs_direct(ctx.ctx, crv, rl, G, gn.data_ptr(), gg.data_ptr(), Fd.data_ptr())
+            torch.cuda.synchronize()
+            call_ms = (time.perf_counter() - t0) * 1e3 / reps
+            tms, c2 = S.sgbem_ctx_kernel_time(ctx.ctx)
+            S.sgbem_ctx_set_timing(ctx.ctx, 0)
+            kms = tms / c2
+            evals = 2.0 * Nd * Nd * G            # 2N nodes x N G Gauss points
+            fl = evals * DL_FLOPS_PER_EVAL
+            direct_rhs[label] = {"N": Nd, "p": pd, "n_gauss": G, "sweep_us": kms * 1e3, "call_ms": call_ms,
+                                 "kernel_evals_per_s": evals / (kms * 1e-3), "tflops": fl / (kms * 1e-3) / 1e12,
+                                 "frac_of_fp64_peak": fl / (kms * 1e-3) / PEAK_FP64}
+            log(f"[bench] direct RHS ({label}, N={Nd}, G={G}): double-layer sweep {kms*1e3:.1f} us "
+                f"({evals/(kms*1e-3):.3e} kernel values/s, {fl/(kms*1e-3)/1e12:.2f} TFLOP/s FP64), whole call {call_ms:.3f} ms")
+
     # ---------------------------------------------------------------- batched persistent launch (256 stars)
     batch = None
     if not args.no_batch:
@@ -418,6 +450,7 @@ def main():
                      "kernel": "fused WQ sweep-and-contract (FP64)", "kernel_us": kern_ms * 1e3,
                      "flops_per_launch": flops},
         "scale_N16384": scale,
+        "direct_rhs": direct_rhs,
         "batch_256_stars": batch,
         "serving": serving,
         "cpu_baseline": cpu,
