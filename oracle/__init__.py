@@ -26,6 +26,8 @@ Parts:
   with the rule of Section 5 (regular weighted outer rule, composite Gauss
   inner rule), F = b1/2 - b2/(2 pi) (eq. seconda_BIE), and the outward flux of
   a harmonic function for the convergence pin.
+* ``collocation`` (O5): collocation BEM with the same rules (Conclusions):
+  the outer integral replaced by the value at the Greville abscissae.
 
 Every function is FP64 and written for readability, not speed.
 """
