@@ -236,6 +236,25 @@ sgbem_status sgbem_rhs(sgbem_ctx ctx, const sgbem_curve *curve, sgbem_rules rule
 sgbem_status sgbem_rhs_direct(sgbem_ctx ctx, const sgbem_curve *curve, sgbem_rules rules, int32_t n_gauss,
                               const double *d_g_nodes, const double *d_g_gauss, double *d_F, double *d_b2);
 
+/*
+ * Collocation BEM with the same rules (Conclusions: the outer collocation node
+ * fixed, the new rules for the inner integral): the N x N matrix, FP64,
+ * row-major in d_A with lda,
+ *   A_ij = -1/(2 pi) [ sum_n w_n^(j) K1(x_i, eta_n) J(eta_n)          (Alg. 1 rule of B_j)
+ *                      + sum_n w_n^(x_i) J(eta_n) B_j(eta_n) ]        (Alg. 2 rule at x_i),
+ * the single-layer equation V phi = u_D collocated at the Greville abscissae
+ * x_i = (i + (p+1)/2) / N, which are the nodes 2 n_ref i + n_ref (p+1) of
+ * sgbem_rhs_points(SGBEM_WQ).  Not symmetric.  n_ref in {1, 2}.  Asynchronous.
+ * Errors: E_INVAL, E_UNSUPPORTED, E_NOMEM, E_DEVICE.
+ */
+sgbem_status sgbem_assemble_collocation(sgbem_ctx ctx, const sgbem_curve *curve, sgbem_rules rules,
+                                        double *d_A, int64_t lda);
+
+/* Right-hand side of the collocation system: d_b[i] = u_D(x_i) picked from
+ * d_g_nodes (device [2 n_ref N] FP64, u_D at sgbem_rhs_points(SGBEM_WQ));
+ * d_b: device [N] FP64.  Asynchronous.  Errors: E_INVAL. */
+sgbem_status sgbem_collocation_rhs(sgbem_ctx ctx, sgbem_rules rules, const double *d_g_nodes, double *d_b);
+
 /* ---------------------------------------------------------------- batches */
 
 /*

@@ -17,7 +17,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsgbem.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-HIP_UNITS = ["api.hip", "kernels.hip", "solve.hip", "batch.hip", "serve.hip", "dlayer.hip",
+HIP_UNITS = ["api.hip", "kernels.hip", "solve.hip", "batch.hip", "serve.hip", "dlayer.hip", "colloc.hip",
              "asm_wq_f64.hip", "asm_wq_f32.hip", "asm_ebe_f64.hip", "asm_ebe_f32.hip"]
 CXX_UNITS = ["planner.cpp"]
 # the register-resident LU panel needs its 64 x 64 column loop fully unrolled

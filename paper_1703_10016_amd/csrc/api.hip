@@ -18,6 +18,7 @@
 #include "batch.hpp"
 #include "curve_eval.hpp"
 #include "dlayer.hpp"
+#include "colloc.hpp"
 
 namespace sgbem {
 hipError_t launch_wq_f64(int p, int P, const TileArgs &a, hipStream_t s, const KernelEvents *ev);
@@ -684,6 +685,52 @@ sgbem_status sgbem_rhs_direct(sgbem_ctx c, const sgbem_curve *curve, sgbem_rules
     HIPCHK(launch_dl_reduce(nn, nchunk, part, d_g_nodes, h, d_b2 ? v : nullptr, c->stream));
     HIPCHK(launch_rhs(N, nn, 2 * r->R, 1, r->Q, r->d_w0, 1.0, J1, h, d_F, c->stream));
     if (d_b2) HIPCHK(launch_rhs(N, nn, 2 * r->R, 1, r->Q, r->d_w0, 1.0, J1, v, d_b2, c->stream));
+    return SGBEM_OK;
+}
+
+sgbem_status sgbem_assemble_collocation(sgbem_ctx c, const sgbem_curve *curve, sgbem_rules r, double *d_A, int64_t lda)
+{
+    if (!c || !r || !d_A) return set_err(SGBEM_E_INVAL, "NULL argument");
+    if (!valid_rules(c, r)) return set_err(SGBEM_E_INVAL, "rules handle does not belong to this context");
+    if (lda < r->N) return set_err(SGBEM_E_INVAL, "lda < N");
+    const int p = r->p, P = 2 * r->R;
+    if (!colloc_supported(p, P)) return set_err(SGBEM_E_UNSUPPORTED, "collocation: n_ref in {1, 2} only");
+    DeviceGuard g(c->device);
+    CurveDev cd;
+    sgbem_status st = upload_curve(c, curve, cd);
+    if (st) return st;
+    const GridDesc grid = wq_grid(r);
+    double *X, *Y, *J;
+    if ((st = geometry(c, cd, grid, c->geo, X, Y, J))) return st;
+    TileArgs ta;
+    std::memset(&ta, 0, sizeof ta);
+    ta.N = r->N;
+    ta.npts = grid.npts;
+    ta.X = X;
+    ta.Y = Y;
+    ta.J = J;
+    ta.inv_s2 = r->d_inv_s2;
+    ta.ws = r->d_ws;
+    for (int q = 0; q < r->Q; ++q) {
+        ta.coefA[q] = r->w0[q];
+        ta.coefB[q] = r->bvals[q];
+    }
+    ta.scale = -1.0 / (2.0 * kPi);
+    ta.out = d_A;
+    ta.lda = lda;
+    KernelEvents ke;
+    const KernelEvents *kev;
+    if ((st = timing_events(c, ke, kev))) return st;
+    HIPCHK(launch_colloc(p, P, ta, c->stream, kev));
+    return SGBEM_OK;
+}
+
+sgbem_status sgbem_collocation_rhs(sgbem_ctx c, sgbem_rules r, const double *d_g_nodes, double *d_b)
+{
+    if (!c || !r || !d_g_nodes || !d_b) return set_err(SGBEM_E_INVAL, "NULL argument");
+    if (!valid_rules(c, r)) return set_err(SGBEM_E_INVAL, "rules handle does not belong to this context");
+    DeviceGuard g(c->device);
+    HIPCHK(launch_colloc_gather(r->N, int(r->npts), 2 * r->R, r->R * (r->p + 1), d_g_nodes, d_b, c->stream));
     return SGBEM_OK;
 }
 

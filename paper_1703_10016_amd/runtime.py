@@ -75,6 +75,19 @@ class Context:
                            F.data_ptr(), b2.data_ptr() if with_b2 else None)
         return (F, b2) if with_b2 else F
 
+    def assemble_collocation(self, curve, p, N, n_ref=1, out=None):
+        """The collocation matrix (FP64, not symmetric) at the Greville abscissae."""
+        if out is None:
+            out = self.torch.empty((N, N), dtype=self.torch.float64, device=self.device)
+        S.sgbem_assemble_collocation(self.ctx, curve, self.rules(p, N, n_ref), out.data_ptr(), out.stride(0))
+        return out
+
+    def collocation_rhs(self, curve, p, N, g, n_ref=1):
+        gn = self.sample(g, self.rhs_points(curve, p, N, "wq", n_ref))
+        b = self.torch.empty(N, dtype=self.torch.float64, device=self.device)
+        S.sgbem_collocation_rhs(self.ctx, self.rules(p, N, n_ref), gn.data_ptr(), b.data_ptr())
+        return b
+
     def solve(self, A, beta, tol=1e-12, max_iter=30, check=True):
         N = A.shape[0]
         prec = S.SGBEM_FP64 if A.dtype == self.torch.float64 else S.SGBEM_FP32

@@ -103,6 +103,8 @@ def lib():
             "sgbem_batch_free": [vp, vp],
             "sgbem_node_points_host": [cp, i32, i32, dp],
             "sgbem_rhs_direct": [vp, cp, vp, i32, vp, vp, vp, vp],
+            "sgbem_assemble_collocation": [vp, cp, vp, vp, i64],
+            "sgbem_collocation_rhs": [vp, vp, vp, vp],
             "sgbem_server_footprint": [i32, i32, ctypes.POINTER(i64)],
             "sgbem_server_create": [ctypes.POINTER(sgbem_server_config), ctypes.POINTER(vp)],
             "sgbem_server_submit": [vp, ctypes.POINTER(sgbem_request)],
@@ -136,7 +138,8 @@ def exported_symbols():
             "sgbem_assemble", "sgbem_rhs", "sgbem_solve", "sgbem_batch_create", "sgbem_batch_assemble",
             "sgbem_batch_tune", "sgbem_batch_free", "sgbem_node_points_host", "sgbem_server_footprint",
             "sgbem_server_create", "sgbem_server_submit", "sgbem_server_poll", "sgbem_server_clock",
-            "sgbem_server_stats", "sgbem_server_destroy", "sgbem_rhs_direct"]
+            "sgbem_server_stats", "sgbem_server_destroy", "sgbem_rhs_direct",
+            "sgbem_assemble_collocation", "sgbem_collocation_rhs"]
 
 
 # ------------------------------------------------------------------ curve marshalling
@@ -350,3 +353,12 @@ def sgbem_rhs_direct(ctx, curve, rules, n_gauss, d_g_nodes_ptr, d_g_gauss_ptr, d
     _check(lib().sgbem_rhs_direct(ctx, c.ref(), rules, int(n_gauss), ctypes.c_void_p(d_g_nodes_ptr),
                                   ctypes.c_void_p(d_g_gauss_ptr), ctypes.c_void_p(d_F_ptr),
                                   ctypes.c_void_p(d_b2_ptr) if d_b2_ptr else None))
+
+
+def sgbem_assemble_collocation(ctx, curve, rules, d_A_ptr, lda):
+    c = _as_curve(curve)
+    _check(lib().sgbem_assemble_collocation(ctx, c.ref(), rules, ctypes.c_void_p(d_A_ptr), int(lda)))
+
+
+def sgbem_collocation_rhs(ctx, rules, d_g_nodes_ptr, d_b_ptr):
+    _check(lib().sgbem_collocation_rhs(ctx, rules, ctypes.c_void_p(d_g_nodes_ptr), ctypes.c_void_p(d_b_ptr)))
