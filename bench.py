@@ -19,6 +19,7 @@ Also measured in the same run (reported beside the headline value):
  * FP32 and FP64 throughput at N = 16384 (a star curve, one assembly each);
  * the direct formulation's right-hand side (double-layer sweep, eq. final_b2)
    at the workload and at N = 16384;
+ * collocation BEM with the same rules at the workload and at N = 16384;
  * a batch of 256 star curves (N in [128, 2048], p in {2, 3}, FP32) in one
    autotuned persistent launch replayed from a HIP graph, against 256
    sequential single-curve launches;
@@ -338,6 +339,29 @@ def main():
             log(f"[bench] direct RHS ({label}, N={Nd}, G={G}): double-layer sweep {kms*1e3:.1f} us "
                 f"({evals/(kms*1e-3):.3e} kernel values/s, {fl/(kms*1e-3)/1e12:.2f} TFLOP/s FP64), whole call {call_ms:.3f} ms")
 
+    # ---------------------------------------------------------------- collocation BEM with the same rules
+    colloc = {}
+    if not args.no_scale:
+        for label, crv, pc, Nc in (("ellipse", curve, p, N), ("star", synth.star(0), 3, 16384)):
+            Ac = torch.empty((Nc, Nc), dtype=torch.float64, device="cuda")
+            ctx.assemble_collocation(crv, pc, Nc, out=Ac)
+            torch.cuda.synchronize()
+            S.sgbem_ctx_set_timing(ctx.ctx, 1)
+            reps = 20 if Nc <= 4096 else 3
+            for _ in range(reps):
+                ctx.assemble_collocation(crv, pc, Nc, out=Ac)
+            tms, c2 = S.sgbem_ctx_kernel_time(ctx.ctx)
+            S.sgbem_ctx_set_timing(ctx.ctx, 0)
+            kms = tms / c2
+            Qc = 2 * (pc + 1) - 1
+            fl = float(Nc) * Nc * (2 * (6 + FLOPS_PER_LOG) + 4 * Qc)
+            colloc[label] = {"N": Nc, "p": pc, "kernel_us": kms * 1e3, "entries_per_s": Nc * Nc / (kms * 1e-3),
+                             "tflops": fl / (kms * 1e-3) / 1e12, "frac_of_fp64_peak": fl / (kms * 1e-3) / PEAK_FP64}
+            log(f"[bench] collocation ({label}, N={Nc}, p={pc}): {kms*1e3:.1f} us -> {Nc*Nc/(kms*1e-3):.3e} entries/s, "
+                f"{fl/(kms*1e-3)/1e12:.2f} TFLOP/s FP64")
+            del Ac
+        torch.cuda.empty_cache()
+
     # ---------------------------------------------------------------- batched persistent launch (256 stars)
     batch = None
     if not args.no_batch:
@@ -451,6 +475,7 @@ def main():
                      "flops_per_launch": flops},
         "scale_N16384": scale,
         "direct_rhs": direct_rhs,
+        "collocation": colloc,
         "batch_256_stars": batch,
         "serving": serving,
         "cpu_baseline": cpu,
