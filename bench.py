@@ -74,7 +74,7 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def serve_sweep(S, rates, n_req, workers):
+def serve_sweep(S, rates, n_req, workers, one_at_a_time=True):
     """Open-loop serving: for each rate, n_req star requests with Poisson
     arrivals (N log-uniform in [256, 8192], p in {2, 3, 4}) go to one server;
     each is assembled (fast form, FP64), its right-hand side formed and solved
@@ -83,10 +83,29 @@ def serve_sweep(S, rates, n_req, workers):
     first arrival to the last completion."""
     import synth
     budget = 24 << 30
+    out = {"workers": workers, "budget_bytes": budget, "requests_per_rate": n_req, "matrix_precision": "fp64"}
+    out["rates"] = []
+    rows_by_workers = {}
+    for w in ([workers, 1] if one_at_a_time else [workers]):
+        out_w = _serve_rates(S, rates if w == workers else rates[-1:], n_req, w, budget)
+        rows_by_workers[w] = out_w
+    out["rates"] = rows_by_workers[workers]
+    if one_at_a_time:
+        one = rows_by_workers[1][0]
+        top = rows_by_workers[workers][-1]
+        out["one_at_a_time"] = one
+        out["speedup_vs_one_at_a_time"] = top["solves_per_s"] / one["solves_per_s"]
+        log(f"[bench] serving at {one['rate']:g} req/s: {workers} slots {top['solves_per_s']:.1f} solves/s vs one at a "
+            f"time {one['solves_per_s']:.1f} solves/s -> {out['speedup_vs_one_at_a_time']:.2f}x (same results: "
+            f"every kernel reduces in a fixed order)")
+    return out
+
+
+def _serve_rates(S, rates, n_req, workers, budget):
+    import synth
+    rows = []
     srv = S.sgbem_server_create(workers=workers, budget_bytes=budget, precision=S.SGBEM_FP64, max_N=8192,
                                 max_rules=512, max_iter=30, tol=1e-12)
-    out = {"workers": workers, "budget_bytes": budget, "requests_per_rate": n_req, "matrix_precision": "fp64",
-           "rates": []}
     try:
         # warm every kernel the path launches (one request per degree), untimed
         warm = [(synth.star(1), p, 512) for p in (2, 3, 4)]
@@ -118,13 +137,14 @@ def serve_sweep(S, rates, n_req, workers):
                    "mean_queue_ms": float(np.mean([(c.t_admit - c.t_arrival) * 1e3 for c in ok])),
                    "peak_in_flight": after["peak_in_flight"], "peak_bytes": after["peak_bytes"],
                    "rules_misses": after["rules_misses"] - before["rules_misses"]}
-            out["rates"].append(row)
-            log(f"[bench] serving rate {rate:g}/s x {n_req}: p50 {row['p50_ms']:.2f} ms p99 {row['p99_ms']:.2f} ms, "
+            rows.append(row)
+            log(f"[bench] serving ({workers} slot{'s' if workers > 1 else ''}) rate {rate:g}/s x {n_req}: "
+                f"p50 {row['p50_ms']:.2f} ms p99 {row['p99_ms']:.2f} ms, "
                 f"{row['solves_per_s']:.1f} solves/s, queue {row['mean_queue_ms']:.1f} ms, "
                 f"{len(ok)}/{len(comp)} ok")
     finally:
         S.sgbem_server_destroy(srv)
-    return out
+    return rows
 
 
 def _serve_drain(S, srv, n, timeout=600.0):
@@ -207,8 +227,9 @@ def main():
         " ".join(f"G={G}:{e:.3e}" for G, e in err_ebe.items()) + f" -> equal-error G = {G_eq}")
 
     # ---------------------------------------------------------------- timed steps (graph replay)
-    def graph_rate(method, steps, **kw):
-        A = torch.empty((N, N), dtype=torch.float64, device="cuda")
+    def graph_rate(method, steps, precision="fp64", **kw):
+        A = torch.empty((N, N), dtype=torch.float64 if precision == "fp64" else torch.float32, device="cuda")
+        kw = dict(kw, precision=precision)
         for _ in range(W):
             ctx.assemble(curve, p, N, method, out=A, **kw)
         torch.cuda.synchronize()
@@ -235,6 +256,22 @@ def main():
     ms_ebe, _ = graph_rate("ebe", max(10, K // 4), n_gauss=G_eq)
     ebe_rate = N * N / (ms_ebe * 1e-3)
     log(f"[bench] EBE FP64 G={G_eq} step {ms_ebe*1e3:.2f} us -> {ebe_rate:.3e} entries/s")
+
+    # FP32 kernel evaluation and contraction (FP64 node differences and rule tables): rate and
+    # error against the FP64 matrix (itself within 1e-12 of the oracle) and of the solution
+    ms_wq32, A_wq32 = graph_rate("wq", K, precision="fp32", n_ref=R)
+    A64h = A_wq.cpu().numpy()
+    mat_err32 = float(np.abs(A_wq32.double().cpu().numpy() - A64h).max() / np.abs(A64h).max())
+    beta_h = ctx.rhs(curve, p, N, g, method="wq", n_ref=R)
+    x64, _ = ctx.solve(A_wq, beta_h, tol=1e-12, max_iter=30)
+    x32, _ = ctx.solve(A_wq32, beta_h, tol=1e-12, max_iter=30)
+    sol_err32 = float(np.linalg.norm((x32 - x64).cpu().numpy()) / np.linalg.norm(x64.cpu().numpy()))
+    fp32 = {"ms_per_step": ms_wq32, "entries_per_s": N * N / (ms_wq32 * 1e-3),
+            "matrix_rel_err_vs_fp64": mat_err32, "solution_rel_err_vs_fp64": sol_err32,
+            "solution_err_vs_ebe8": err(x32.cpu().numpy())}
+    log(f"[bench] WQ FP32 step {ms_wq32*1e3:.2f} us -> {N*N/(ms_wq32*1e-3):.3e} entries/s; matrix error vs FP64 "
+        f"{mat_err32:.2e}, solution {sol_err32:.2e} (vs EBE G=8 reference {fp32['solution_err_vs_ebe8']:.2e})")
+    del A_wq32
 
     # direct launches (host enqueue included), for reference
     A = torch.empty((N, N), dtype=torch.float64, device="cuda")
@@ -474,6 +511,7 @@ def main():
                      "kernel": "fused WQ sweep-and-contract (FP64)", "kernel_us": kern_ms * 1e3,
                      "flops_per_launch": flops},
         "scale_N16384": scale,
+        "fp32_fast_form": fp32,
         "direct_rhs": direct_rhs,
         "collocation": colloc,
         "batch_256_stars": batch,
