@@ -11,7 +11,7 @@ items with L = P (T - 1) + Q rows; the shape is chosen so that the items fill th
 256 threads in one pass.  Fast form with n_ref = 1, p <= 4: 28 x 28 tiles with
 7-column strips (236..252 items), and in FP64 from N = 4096 an instance compiled
 for at least 4 waves per SIMD (FP32 reaches that occupancy anyway); p = 5, 6: 24 x 24 tiles, 6-column strips (228, 236
-items).  Otherwise 32 x 32 tiles for P <= 4 and 16 x 16 above, 8-column strips.
+items).  Otherwise the shape that function `shape` scores best.
 Run from this directory: python gen_instances.py
 """
 import os
@@ -30,6 +30,24 @@ hipError_t {fname}(int p, int P, const TileArgs &a, hipStream_t s, const KernelE
 '''
 
 
+SHAPES = [(32, 8), (28, 7), (24, 8), (24, 6), (21, 7), (20, 5), (16, 8), (16, 4), (12, 4), (8, 4)]
+
+
+def shape(P, Q, ideal):
+    """Tile edge T and strip width S for a sweep with P points per element and Q
+    support points: maximise (fraction of 256 threads busy over the passes the
+    L T/S items need) x (ideal kernel values per entry / values the tile
+    evaluates per entry, halos included), L = P (T - 1) + Q."""
+    def score(ts):
+        T, S = ts
+        L = P * (T - 1) + Q
+        items = L * (T // S)
+        passes = -(-items // 256)
+        per_entry = L * (T // S) * (P * (S - 1) + Q) / (T * T)
+        return items / (passes * 256) * ideal / per_entry
+    return max(SHAPES, key=score)
+
+
 def wq_cases():
     for p in range(1, 7):
         for R in range(1, 5):
@@ -38,13 +56,15 @@ def wq_cases():
                 T, S = (28, 7) if p <= 4 else (24, 6)
                 yield p, P, P * (p + 1) - 1, 1, "true", T, S, (p <= 4)
             else:
-                yield p, P, P * (p + 1) - 1, 1, "true", 32 if P <= 4 else 16, 8, False
+                T, S = shape(P, P * (p + 1) - 1, P * P)
+                yield p, P, P * (p + 1) - 1, 1, "true", T, S, False
 
 
 def ebe_cases():
     for p in range(1, 7):
         for G in range(1, 9):
-            yield p, G, G * (p + 1), 0, "false", 32 if G <= 4 else 16, 8, False
+            T, S = shape(G, G * (p + 1), G * G)
+            yield p, G, G * (p + 1), 0, "false", T, S, False
 
 
 def main():
