@@ -147,13 +147,17 @@ def _serve_rates(S, rates, n_req, workers, budget):
     return rows
 
 
-def _serve_drain(S, srv, n, timeout=600.0):
+def _serve_drain(S, srv, n, timeout=900.0):
     got = []
     t_end = time.time() + timeout
+    t_log = time.time() + 30.0
     while len(got) < n:
         if time.time() > t_end:
             raise RuntimeError(f"serving: {len(got)} of {n} completions before the time limit")
         got += S.sgbem_server_poll(srv, 256, 1.0)
+        if time.time() > t_log:     # progress of long sweeps (2000 requests at 10 req/s take 200 s)
+            log(f"[bench] serving: {len(got)} of {n} requests completed")
+            t_log = time.time() + 30.0
     return got
 
 
