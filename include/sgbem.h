@@ -3,8 +3,10 @@
  * single-layer operator with periodic B-splines on a closed curve, by
  * B-spline weighted quadrature with row assembly and sum factorisation (the
  * fast form) or element by element with Gauss rules (the plain form), plus
- * the right-hand side and a mixed-precision dense solve, on one AMD Instinct
- * MI355X (gfx950).
+ * the right-hand sides of the indirect and the direct formulation, a
+ * mixed-precision dense solve, collocation with the same rules, one launch for
+ * many curves and a continuous-batching server, on one AMD Instinct MI355X
+ * (gfx950).
  *
  * Method: Aimi, Calabro, Diligenti, Sampoli, Sangalli, Sestini, "Efficient
  * assembly based on B-spline tailored quadrature rules for the IgA-SGBEM".
@@ -23,7 +25,8 @@
  *    torch tensor's data_ptr); "host" pointers are ordinary host memory owned
  *    by the caller and only read during the call;
  *  - work is enqueued on the context's stream and is asynchronous unless
- *    stated otherwise; a context must be used from one host thread at a time;
+ *    stated otherwise; a context must be used from one host thread at a time
+ *    (a server, sgbem_server_*, may be called from any thread);
  *  - matrices are row-major: entry (i, j) at ptr[i * lda + j], lda >= N;
  *  - basis index convention: B_i is supported on [i/N, (i+p+1)/N) mod 1.
  */
