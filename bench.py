@@ -40,7 +40,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64 = 78.6e12          # MI355X FP64 vector, FLOP/s
-PEAK_FP32 = 157.3e12         # MI355X FP32 vector, FLOP/s
+PEAK_FP32 = 157.3e12         # MI355X FP32, vector and dense MFMA alike, FLOP/s
 PEAK_HBM = 8.0e12            # bytes/s
 FLOPS_PER_LOG = 20           # cost model of one logarithm
 DL_FLOPS_PER_EVAL = 11       # double-layer kernel value: 2 differences, numerator and denominator (3 each), 1 division, 1 multiply-add
@@ -222,13 +222,30 @@ def main():
         x, info = ctx.solve(A, beta, tol=1e-12, max_iter=30)
         return x.cpu().numpy()
 
+    # Interior potential u_h(x) = sum_j alpha_j int B_j(t) (-1/2pi) ln|x - f(t)| J(t) dt: the
+    # right-hand side routine (8-point Gauss per element, far from x) applied to the kernel as datum.
+    # u = g inside the curve, so |u_h - g| at interior points measures the error without a reference.
+    th = 2.0 * math.pi * np.arange(8) / 8
+    xin = np.concatenate([0.3 * np.cos(th), 0.6 * np.cos(th + 0.2)])
+    yin = np.concatenate([0.15 * np.sin(th), 0.3 * np.sin(th + 0.2)])
+    g_in = g(xin, yin)
+    cols = np.stack([ctx.rhs(curve, p, N, (lambda x, y, a=a, b=b: -np.log(np.hypot(x - a, y - b)) / (2 * math.pi)),
+                             method="ebe", n_gauss=8).cpu().numpy() for a, b in zip(xin, yin)])
+    interior_err = lambda a: float(np.abs(cols @ a - g_in).max() / np.abs(g_in).max())
+
     a_ref = solve_coeffs("ebe", n_gauss=8)
     err = lambda a: float(np.linalg.norm(a - a_ref) / np.linalg.norm(a_ref))
-    err_wq = err(solve_coeffs("wq", n_ref=R))
-    err_ebe = {G: err(solve_coeffs("ebe", n_gauss=G)) for G in (1, 2, 3, 4, 5, 6)}
+    sol_wq = {r: solve_coeffs("wq", n_ref=r) for r in (1, 2, 3, 4)}
+    sol_ebe = {G: solve_coeffs("ebe", n_gauss=G) for G in (1, 2, 3, 4, 5, 6)}
+    sol_ebe[8] = a_ref
+    err_wq = err(sol_wq[R])
+    err_ebe = {G: err(a) for G, a in sol_ebe.items() if G != 8}
     G_eq = next((G for G in sorted(err_ebe) if err_ebe[G] <= err_wq), 6)
-    log(f"[bench] solution error vs EBE(G=8): WQ {err_wq:.3e}; EBE " +
-        " ".join(f"G={G}:{e:.3e}" for G, e in err_ebe.items()) + f" -> equal-error G = {G_eq}")
+    log(f"[bench] solution error vs EBE(G=8): WQ " + " ".join(f"n_ref={r}:{err(a):.3e}" for r, a in sol_wq.items()) +
+        "; EBE " + " ".join(f"G={G}:{e:.3e}" for G, e in err_ebe.items()) + f" -> equal-error G = {G_eq}")
+    log(f"[bench] interior potential error (16 points): WQ " +
+        " ".join(f"n_ref={r}:{interior_err(a):.3e}" for r, a in sol_wq.items()) + "; EBE " +
+        " ".join(f"G={G}:{interior_err(a):.3e}" for G, a in sorted(sol_ebe.items())))
 
     # ---------------------------------------------------------------- timed steps (graph replay)
     def graph_rate(method, steps, precision="fp64", **kw):
@@ -260,6 +277,37 @@ def main():
     ms_ebe, _ = graph_rate("ebe", max(10, K // 4), n_gauss=G_eq)
     ebe_rate = N * N / (ms_ebe * 1e-3)
     log(f"[bench] EBE FP64 G={G_eq} step {ms_ebe*1e3:.2f} us -> {ebe_rate:.3e} entries/s")
+
+    # error-vs-time front of both forms, speedup at matched error by log-log interpolation
+    front_steps = max(10, K // 4)
+    t_wq = {r: (ms_wq if r == R else graph_rate("wq", front_steps, n_ref=r)[0]) for r in (1, 2, 3, 4)}
+    t_ebe = {G: (ms_ebe if G == G_eq else graph_rate("ebe", front_steps, n_gauss=G)[0]) for G in (2, 3, 4, 6, 8)}
+    front = {"wq": [{"n_ref": r, "us_per_step": t_wq[r] * 1e3, "solution_err": err(sol_wq[r]),
+                     "interior_err": interior_err(sol_wq[r])} for r in t_wq],
+             "ebe": [{"n_gauss": G, "us_per_step": t_ebe[G] * 1e3,
+                      "solution_err": err_ebe.get(G), "interior_err": interior_err(sol_ebe[G])} for G in t_ebe]}
+
+    def matched(key, e):
+        """EBE step time at error e, log-log interpolated between the bracketing Gauss orders."""
+        pts = [(row[key], row["us_per_step"]) for row in front["ebe"] if row[key]]   # by rising order
+        for (e0, t0), (e1, t1) in zip(pts, pts[1:]):
+            if e1 <= e <= e0:
+                f = math.log(e / e0) / math.log(e1 / e0)
+                return math.exp(math.log(t0) + f * math.log(t1 / t0))
+        return None
+
+    speedup_interp = {}
+    for key in ("solution_err", "interior_err"):
+        t_m = matched(key, front["wq"][R - 1][key])
+        speedup_interp[key] = t_m / front["wq"][R - 1]["us_per_step"] if t_m else None
+    for row in front["wq"]:
+        log(f"[bench] front WQ n_ref={row['n_ref']}: {row['us_per_step']:.2f} us, solution err {row['solution_err']:.2e}, "
+            f"interior err {row['interior_err']:.2e}")
+    for row in front["ebe"]:
+        se = f"{row['solution_err']:.2e}" if row["solution_err"] else "(reference)"
+        log(f"[bench] front EBE G={row['n_gauss']}: {row['us_per_step']:.2f} us, solution err {se}, "
+            f"interior err {row['interior_err']:.2e}")
+    log(f"[bench] WQ vs EBE at matched error (log-interpolated): {speedup_interp}")
 
     # FP32 kernel evaluation and contraction (FP64 node differences and rule tables): rate and
     # error against the FP64 matrix (itself within 1e-12 of the oracle) and of the solution
@@ -348,7 +396,25 @@ def main():
                            "tflops": fl / (kms * 1e-3) / 1e12, "frac_of_vector_peak": fl / (kms * 1e-3) / pk}
             log(f"[bench] star N={Nb} WQ {prec}: {kms:.3f} ms -> {Nb*Nb/(kms*1e-3):.3e} entries/s, "
                 f"{fl/(kms*1e-3)/1e12:.2f} TFLOP/s")
-            del Ab
+            # FP32 LU with partial pivoting + FP64 refinement to 1e-10 on this matrix; the LU is
+            # (2/3) N^3 flop, reported against the FP32 MFMA peak over the whole solve's wall time
+            bb = ctx.rhs(star, p, Nb, g, method="wq", n_ref=R)
+            ctx.solve(Ab, bb, tol=1e-10, max_iter=30)                  # warm: workspace, code objects
+            sms = []
+            for _ in range(2):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                xb, sinfo = ctx.solve(Ab, bb, tol=1e-10, max_iter=30)
+                torch.cuda.synchronize()
+                sms.append((time.perf_counter() - t0) * 1e3)
+            lu_fl = 2.0 / 3.0 * Nb ** 3
+            scale[prec].update({"solve_ms": min(sms), "solve_iters": sinfo.iters,
+                                "solve_backward_err": sinfo.backward_err,
+                                "lu_tflops_over_solve": lu_fl / (min(sms) * 1e-3) / 1e12,
+                                "lu_frac_of_fp32_peak": lu_fl / (min(sms) * 1e-3) / PEAK_FP32})
+            log(f"[bench] star N={Nb} solve ({prec} matrix): {min(sms):.1f} ms, {sinfo.iters} refinement steps, "
+                f"backward err {sinfo.backward_err:.1e}; LU {lu_fl/(min(sms)*1e-3)/1e12:.1f} TFLOP/s over the solve")
+            del Ab, bb, xb
         torch.cuda.empty_cache()
 
     # ---------------------------------------------------------------- direct formulation: double-layer sweep
@@ -502,7 +568,9 @@ def main():
                                "B-splines p=3, N=1024; weighted-quadrature row assembly n_ref=1, FP64",
                    "p": p, "N": N, "n_ref": R, "step": "geometry + fused WQ assembly, HIP graph replay"},
         "equal_error": {"wq_solution_err": err_wq, "ebe_solution_err": err_ebe, "ebe_gauss_order": G_eq,
-                        "reference": "element-by-element G=8 solution (FP64)"},
+                        "reference": "element-by-element G=8 solution (FP64)",
+                        "interior_points": "16 points inside the ellipse, error of u_h against g",
+                        "front": front, "speedup_log_interpolated": speedup_interp},
         "ebe": {"entries_per_s": ebe_rate, "ms_per_step": ms_ebe, "n_gauss": G_eq},
         "speedup_wq_vs_ebe_equal_err": value / ebe_rate,
         "direct_launch_ms_per_step": ms_direct,

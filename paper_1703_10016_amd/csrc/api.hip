@@ -932,6 +932,8 @@ sgbem_status sgbem_solve(sgbem_ctx c, int32_t N, const void *d_A, int64_t lda, i
         info->status = rc;
         info->rel_update = res.rel_update;
         info->backward_err = res.backward_err;
+        info->pivoted = res.pivoted ? 1 : 0;
+        info->reserved = 0;
     }
     if (rc != SGBEM_OK) return set_err(sgbem_status(rc), msg);
     return SGBEM_OK;

@@ -169,112 +169,199 @@ __device__ __forceinline__ unsigned wave_reduce_u32(unsigned v)
     return unsigned(__builtin_amdgcn_readlane(int(v), 63));
 }
 
-// Register-resident panel factorisation (one workgroup of 1024 threads, RT rows
-// per thread, W <= 32 columns): thread t owns the panel rows k0 + r*1024 + t
-// with all W columns in registers.  The column loop is unrolled, so every
-// register index is a compile-time constant.  Per column: pivot = largest
-// magnitude at or below the diagonal, lowest row on ties.  Each wavefront finds
-// its own candidate (two DPP reductions: the largest magnitude, then the lowest
-// row holding it) and publishes it with the candidate row's values; the owner
-// of the diagonal row publishes that row.  After the column's one barrier every
-// thread reduces the 16 candidates the same way (the winning wavefront is the
-// owner of the pivot row), interchanges the two rows in registers (earlier L
-// multipliers included: a row interchange of the panel), scales and updates
-// the rows below.  The published values are double-buffered by column parity:
-// a wavefront can write a buffer again only after the next column's barrier,
-// which every wavefront reaches after its last read of it.  Global memory is
-// touched only to load the panel and to store it, the pivots and info.
-template <int RT, int W>
-__global__ __launch_bounds__(1024) void panel_reg_kernel(int N, float *LU, int k0, int w, int *piv, int *info)
+// Register-resident panel factorisation: one workgroup of NT threads (NT / 64
+// wavefronts), RT slots per thread, W <= 64 columns.  Slot r of thread t holds
+// one panel row, all W columns, in registers, and the row's current position
+// pos[r] (initially k0 + r NT + t).  Every loop over r and over the columns is
+// unrolled, so every register index is a compile-time constant.
+//
+// Row interchanges are lazy: the interchange of rows gj and pr at column j only
+// swaps the two positions (the slot holding position pr takes gj and the slot
+// holding gj takes pr, found by comparing positions), and the final store
+// writes every slot to the row of its position.  The result is the same as
+// moving the rows, L multipliers included, without moving data in registers.
+//
+// Per column j (gj = k0 + j; the active slots are those with pos >= gj):
+//  * each thread holds its candidate, the active slot of largest magnitude in
+//    column j, lowest position on ties; each wavefront reduces the candidates
+//    by two DPP reductions (largest magnitude, then lowest position holding
+//    it) and the owner of the winning slot publishes its columns j..W-1;
+//  * one barrier; every thread picks the winner among the NT / 64 published
+//    candidates the same way, so all agree on the pivot position pr;
+//  * positions are swapped as above; the active rows (now pos > gj) are
+//    scaled and updated with the pivot row held in registers, branch-free
+//    (inactive slots are updated with a zero multiplier), and in the same pass
+//    each thread takes its candidate for column j + 1.
+// With PIV false the pivot of column j is the diagonal entry itself (no
+// search, no interchanges: the factorisation without pivoting, which is used
+// for symmetric matrices); thread j publishes row gj, and a zero or non-finite
+// pivot is reported like a singular column.
+// Slots past N hold zeros at a position no real row has: they never become the
+// pivot (a zero magnitude only wins when every candidate is zero, and then
+// the lowest position, a real row, wins and the column is singular: no
+// interchange, no update).  Published values are double-buffered by column
+// parity: a buffer is written again two columns later, after a barrier that
+// every wavefront reaches only when done reading it.  Global memory is touched
+// only to load and store the panel, the pivots and info.
+template <int RT, int W, int NT, bool PIV>
+__global__ __launch_bounds__(NT) void panel_reg_kernel(int N, float *LU, int k0, int w, int *piv, int *info)
 {
-    __shared__ unsigned smag[2][16];
-    __shared__ int srow[2][16];
-    __shared__ float crow[2][16][W];     // each wavefront's candidate row
-    __shared__ float jrow[2][W];         // the diagonal row
+    constexpr int NWV = NT / 64;
+    constexpr int NONE = 0x7fffffff, PAD = 0x7ffffff0;
+    static_assert(NT % 64 == 0 && NWV <= 16 && W <= 64, "panel shape");
+    __shared__ unsigned smag[2][NWV];
+    __shared__ int spos[2][NWV];
+    __shared__ float crow[2][NWV][W];    // each wavefront's candidate row, columns j..W-1
     __shared__ int pivs[W];
     __shared__ int sinfo;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     if (tid == 0) sinfo = 0;
+    // Every load is unconditional, from a clamped (valid, finite) entry, and is
+    // multiplied by 1 or 0: its result is always used, so the loads are all in
+    // flight together instead of each in its own branch followed by a wait.
     float a[RT][W];
+    int pos[RT];
+#pragma unroll
+    for (int c = 0; c < W; ++c) {
+        const float *col = LU + int64_t(k0 + min(c, w - 1)) * N;
+#pragma unroll
+        for (int r = 0; r < RT; ++r) {
+            const int i = k0 + r * NT + tid;
+            a[r][c] = col[min(i, N - 1)] * ((i < N && c < w) ? 1.0f : 0.0f);
+        }
+    }
+    // pin every value here (an empty statement that reads and writes it), so that the
+    // loads are all issued before the column loop rather than each sunk to its first use
+#pragma unroll
+    for (int c = 0; c < W; ++c)
+#pragma unroll
+        for (int r = 0; r < RT; ++r) asm volatile("" : "+v"(a[r][c]));
 #pragma unroll
     for (int r = 0; r < RT; ++r) {
-        const int i = k0 + r * 1024 + tid;
+        const int i = k0 + r * NT + tid;
+        pos[r] = i < N ? i : PAD;
+    }
+    // candidate for column 0: every slot is active
+    float best = -1.0f;
+    int bpos = NONE, bslot = 0;
 #pragma unroll
-        for (int c = 0; c < W; ++c) a[r][c] = (i < N && c < w) ? LU[int64_t(k0 + c) * N + i] : 0.0f;
+    for (int r = 0; r < (PIV ? RT : 0); ++r) {
+        const float m = fabsf(a[r][0]);
+        const bool take = (m > best) | ((m == best) & (pos[r] < bpos));
+        best = take ? m : best;
+        bpos = take ? pos[r] : bpos;
+        bslot = take ? r : bslot;
     }
 #pragma unroll
     for (int j = 0; j < W; ++j) {
-        if (j < w) {
+        // no branch on j < w either: columns past w are zero in every row, so their
+        // pass finds no pivot and changes nothing (only the singular flag is guarded)
+        {
             const int gj = k0 + j, buf = j & 1;
-            // this thread's candidate: magnitude bits (monotone for non-negative floats), lowest row on ties
-            unsigned mag = 0u;
-            int row = 0x7fffffff;
+            bool ok;
+            int pr, gw = 0;
+            if constexpr (PIV) {
+                const bool has = best >= 0.0f;
+                const unsigned mag = has ? __float_as_uint(best) : 0u;   // monotone for non-negative floats
+                const int key = has ? bpos : NONE;
+                const unsigned wmag = wave_reduce_u32<true>(mag);
+                const int wpos = int(wave_reduce_u32<false>(mag == wmag ? unsigned(key) : unsigned(NONE)));
+                // publish the wavefront's candidate (its owner lane and slot made uniform)
+                const unsigned long long own = __ballot(key == wpos);
+                const int wl = int(__builtin_ctzll(own | (1ull << 63)));
+                const int rw = __builtin_amdgcn_readlane(bslot, wl);
 #pragma unroll
-            for (int r = 0; r < RT; ++r) {
-                const int i = k0 + r * 1024 + tid;
-                const unsigned m = __float_as_uint(fabsf(a[r][j]));
-                if (i >= gj && i < N && (m > mag || (m == mag && i < row))) {
-                    mag = m;
-                    row = i;
+                for (int r = 0; r < RT; ++r)
+                    if (r == rw && lane == wl) {
+#pragma unroll
+                        for (int c = 0; c < W; ++c)
+                            if (c >= j) crow[buf][wid][c] = a[r][c];
+                    }
+                if (lane == 0) {
+                    smag[buf][wid] = wmag;
+                    spos[buf][wid] = wpos;
                 }
-            }
-            const unsigned wmag = wave_reduce_u32<true>(mag);
-            const int wrow = int(wave_reduce_u32<false>(mag == wmag ? unsigned(row) : 0x7fffffffu));
+                __syncthreads();
+                // the winner among the wavefronts' candidates (position gj is one of the
+                // active slots, so a candidate exists)
+                unsigned gm = 0u;
+                int gp = NONE;
 #pragma unroll
-            for (int r = 0; r < RT; ++r) {
-                const int i = k0 + r * 1024 + tid;
-                if (i == wrow) {
-#pragma unroll
-                    for (int c = 0; c < W; ++c) crow[buf][wid][c] = a[r][c];
+                for (int q = 0; q < NWV; ++q) {
+                    const unsigned m = smag[buf][q];
+                    const int p = spos[buf][q];
+                    if (m > gm || (m == gm && p < gp)) {
+                        gm = m;
+                        gp = p;
+                        gw = q;
+                    }
                 }
-                if (i == gj) {
+                ok = __uint_as_float(gm) > 0.0f;
+                pr = ok ? gp : gj;
+            } else {
+                // the diagonal row (slot 0 of thread j, never moved) is the pivot row
+                if (tid == j) {
 #pragma unroll
-                    for (int c = 0; c < W; ++c) jrow[buf][c] = a[r][c];
+                    for (int c = 0; c < W; ++c)
+                        if (c >= j) crow[buf][0][c] = a[0][c];
                 }
+                __syncthreads();
+                const float d = crow[buf][0][j];
+                ok = fabsf(d) > 0.0f && fabsf(d) <= 3.402823466e38f;
+                pr = gj;
             }
-            if (lane == 0) {
-                smag[buf][wid] = wmag;
-                srow[buf][wid] = wrow;
-            }
-            __syncthreads();
-            const unsigned cm = smag[buf][lane & 15], cr = unsigned(srow[buf][lane & 15]);
-            const unsigned gm = wave_reduce_u32<true>(lane < 16 ? cm : 0u);
-            const int gr = int(wave_reduce_u32<false>(lane < 16 && cm == gm ? cr : 0x7fffffffu));
-            const float b = __uint_as_float(gm);
-            const bool ok = b > 0.0f;
-            const int pr = ok ? gr : gj;
-            const float *prow = ok ? crow[buf][((pr - k0) & 1023) >> 6] : jrow[buf];
             if (tid == 0) {
-                if (!ok && sinfo == 0) sinfo = gj + 1;
+                if (!ok && j < w && sinfo == 0) sinfo = gj + 1;
                 pivs[j] = pr;
             }
-            const float d = prow[j];
-            const float inv = ok ? 1.0f / d : 0.0f;
+            // interchange of rows gj and pr: swap the two positions
+            if constexpr (PIV) {
+#pragma unroll
+                for (int r = 0; r < RT; ++r) pos[r] = pos[r] == pr ? gj : (pos[r] == gj ? pr : pos[r]);
+            }
+            // One branch-free pass (a branch here would make the compiler copy the whole
+            // panel at the join): the active rows are scaled and updated with the pivot
+            // row held in registers; inactive slots, and every slot when the column is
+            // singular, get a zero multiplier.  Candidates for column j + 1 on the way.
+            float pv[W];
+#pragma unroll
+            for (int c = 0; c < W; ++c) pv[c] = c >= j ? crow[buf][gw][c] : 0.0f;   // constant trip count
+            const float inv = ok ? 1.0f / pv[j] : 0.0f;
+            best = -1.0f;
+            bpos = NONE;
+            bslot = 0;
 #pragma unroll
             for (int r = 0; r < RT; ++r) {
-                const int i = k0 + r * 1024 + tid;
-                if (i == gj) {
+                // without interchanges the rows at or above gj are slot 0 of threads 0..j
+                const bool act = PIV ? pos[r] > gj : (r > 0 || tid > j);
+                const float lr = a[r][j] * inv;
+                const float l = act ? lr : 0.0f;
+                a[r][j] = act ? lr : a[r][j];
 #pragma unroll
-                    for (int c = 0; c < W; ++c) a[r][c] = prow[c];
-                } else if (i == pr) {
-#pragma unroll
-                    for (int c = 0; c < W; ++c) a[r][c] = jrow[buf][c];
-                }
-                if (i > gj && i < N && ok) {
-                    const float l = a[r][j] * inv;
-                    a[r][j] = l;
-#pragma unroll
-                    for (int c = j + 1; c < W; ++c) a[r][c] -= l * prow[c];
+                for (int c = 0; c < W; ++c)
+                    if (c > j) a[r][c] -= l * pv[c];
+                if (PIV && j + 1 < W) {
+                    const float m = fabsf(a[r][j + 1]);
+                    const bool take = act & ((m > best) | ((m == best) & (pos[r] < bpos)));
+                    best = take ? m : best;
+                    bpos = take ? pos[r] : bpos;
+                    bslot = take ? r : bslot;
                 }
             }
         }
     }
+    // an opaque copy of the base pointer: the store addresses are formed anew here
+    // instead of being kept live, in registers, from the loads at the start
+    float *LUs = LU;
+    asm volatile("" : "+s"(LUs));
 #pragma unroll
-    for (int r = 0; r < RT; ++r) {
-        const int i = k0 + r * 1024 + tid;
+    for (int c = 0; c < W; ++c) {
+        if (c < w) {
+            float *col = LUs + int64_t(k0 + c) * N;
 #pragma unroll
-        for (int c = 0; c < W; ++c)
-            if (i < N && c < w) LU[int64_t(k0 + c) * N + i] = a[r][c];
+            for (int r = 0; r < RT; ++r)
+                if (pos[r] < N) col[pos[r]] = a[r][c];
+        }
     }
     __syncthreads();
     if (tid < w) piv[k0 + tid] = pivs[tid];
@@ -299,11 +386,13 @@ __global__ void laswp_kernel(int N, float *LU, int k0, int w, const int *piv)
 }
 
 // For the narrow panel at k0 (w <= 64 columns), on the block columns
-// [cb, ce) outside the panel: apply the panel's row interchanges, then for the
+// [cb, ce) outside the panel: apply the panel's row interchanges (unless
+// swaps is 0: a factorisation without pivoting), then for the
 // columns right of the panel solve U12 = L11^{-1} A12.  One wavefront per
 // column: lane 0 applies the interchanges in order, the workgroup barrier makes
 // them visible, then lane r holds row k0 + r for the solve.
-__global__ __launch_bounds__(256) void swap_trsm_kernel(int N, float *LU, int k0, int w, const int *piv, int cb, int ce)
+__global__ __launch_bounds__(256) void swap_trsm_kernel(int N, float *LU, int k0, int w, const int *piv, int cb, int ce,
+                                                        int swaps)
 {
     __shared__ float L[NB][NB + 1];
     const int tid = threadIdx.x;
@@ -316,7 +405,7 @@ __global__ __launch_bounds__(256) void swap_trsm_kernel(int N, float *LU, int k0
     if (col >= k0) col += w;
     const bool valid = col < ce;
     float *cp = LU + int64_t(valid ? col : 0) * N;
-    if (valid && lane == 0) {
+    if (swaps && valid && lane == 0) {
         for (int j = k0; j < k0 + w; ++j) {
             const int pr = piv[j];
             if (pr != j) {
@@ -594,6 +683,65 @@ void launch_residual(int N, const void *A, int64_t lda, const double *x, const d
                        x, beta, r);
 }
 
+// Exact symmetry test of A (row-major, leading dimension lda): each workgroup
+// takes 32 x 32 tiles (ti, tj), ti <= tj, in a grid-stride loop, stages the
+// mirror tile (tj, ti) in LDS and compares; out[blockIdx.x] = the largest
+// |A_ij - A_ji| it saw.
+template <typename InT>
+__global__ __launch_bounds__(256) void asym_kernel(int N, const InT *A, int64_t lda, double *out)
+{
+    __shared__ InT T[32][33];
+    __shared__ double s[4];
+    const int nt = (N + 31) / 32, tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    double mx = 0.0;
+    for (int64_t t = blockIdx.x; t < int64_t(nt) * nt; t += gridDim.x) {
+        const int ti = int(t / nt), tj = int(t % nt);
+        if (ti > tj) continue;                                   // uniform over the workgroup
+        for (int y = ty; y < 32; y += 8) {
+            const int r = tj * 32 + y, c = ti * 32 + tx;
+            T[y][tx] = (r < N && c < N) ? A[int64_t(r) * lda + c] : InT(0);
+        }
+        __syncthreads();
+        for (int y = ty; y < 32; y += 8) {
+            const int r = ti * 32 + y, c = tj * 32 + tx;
+            if (r < N && c < N) mx = fmax(mx, fabs(double(A[int64_t(r) * lda + c]) - double(T[tx][y])));
+        }
+        __syncthreads();
+    }
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) out[blockIdx.x] = fmax(fmax(s[0], s[1]), fmax(s[2], s[3]));
+}
+
+// Register panel for the rows k0..N-1 (m = N - k0 <= 16384) of the block
+// [K0, KE): the shape (rows per thread, width, threads) is the fastest per
+// column for that height (measured), the width shrinking as the rows per thread
+// grow.  Returns the width used.
+template <bool PIV>
+int launch_panel(int N, float *LU, int k0, int KE, int *piv, int *info, hipStream_t s)
+{
+    const int m = N - k0;
+    int w;
+    if (m <= 1024) {
+        w = std::min(32, KE - k0);
+        hipLaunchKernelGGL((panel_reg_kernel<4, 32, 256, PIV>), dim3(1), dim3(256), 0, s, N, LU, k0, w, piv, info);
+    } else if (m <= 2048) {
+        w = std::min(16, KE - k0);
+        hipLaunchKernelGGL((panel_reg_kernel<4, 16, 512, PIV>), dim3(1), dim3(512), 0, s, N, LU, k0, w, piv, info);
+    } else if (m <= 4096) {
+        w = std::min(8, KE - k0);
+        hipLaunchKernelGGL((panel_reg_kernel<8, 8, 512, PIV>), dim3(1), dim3(512), 0, s, N, LU, k0, w, piv, info);
+    } else if (m <= 8192) {
+        w = std::min(8, KE - k0);
+        hipLaunchKernelGGL((panel_reg_kernel<8, 8, 1024, PIV>), dim3(1), dim3(1024), 0, s, N, LU, k0, w, piv, info);
+    } else {
+        w = std::min(4, KE - k0);
+        hipLaunchKernelGGL((panel_reg_kernel<16, 4, 1024, PIV>), dim3(1), dim3(1024), 0, s, N, LU, k0, w, piv, info);
+    }
+    return w;
+}
+
 }  // namespace
 
 size_t solve_workspace_bytes(int N)
@@ -604,7 +752,9 @@ size_t solve_workspace_bytes(int N)
            align_up(size_t(N) * sizeof(double)) + align_up(nblk * 2 * 4096 * sizeof(float));
 }
 
-hipError_t lu_factor_f32(int N, float *LU, int *piv, int *info, void *diag_inv, hipStream_t s)
+bool lu_without_pivoting_supported(int N) { return N <= 16384; }
+
+hipError_t lu_factor_f32(int N, float *LU, int *piv, int *info, void *diag_inv, bool pivot, hipStream_t s)
 {
     // Two levels: blocks of BK columns, each factored by narrow register panels
     // whose triangular solves and updates stay inside the block; then one
@@ -612,35 +762,28 @@ hipError_t lu_factor_f32(int N, float *LU, int *piv, int *info, void *diag_inv, 
     // trailing matrix (the MFMA-bound part).  Row interchanges always go to
     // the full rows.  Up to N = 4096 one block spans the matrix (every narrow
     // panel updates the whole trailing matrix): there the launches saved
-    // outweigh the traffic of the narrow updates (measured).
+    // outweigh the traffic of the narrow updates (measured).  Without pivoting
+    // (pivot false, N <= 16384) the panels take the diagonal as pivot and no
+    // interchange is applied anywhere.
+    if (!pivot && !lu_without_pivoting_supported(N)) return hipErrorInvalidValue;
     const int BK = N <= 4096 ? N : 128;
     hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(64), 0, s, info);
     for (int K0 = 0; K0 < N; K0 += BK) {
         const int KE = std::min(N, K0 + BK);
         for (int k0 = K0; k0 < KE;) {
-            const int m = N - k0;
             int w;
-            // register panels while the rows fit (1, 2, 4, 8 rows per thread), narrower as they grow
-            if (m <= 1024) {
-                w = std::min(32, KE - k0);
-                hipLaunchKernelGGL((panel_reg_kernel<1, 32>), dim3(1), dim3(1024), 0, s, N, LU, k0, w, piv, info);
-            } else if (m <= 2048) {
-                w = std::min(16, KE - k0);
-                hipLaunchKernelGGL((panel_reg_kernel<2, 16>), dim3(1), dim3(1024), 0, s, N, LU, k0, w, piv, info);
-            } else if (m <= 4096) {
-                w = std::min(8, KE - k0);
-                hipLaunchKernelGGL((panel_reg_kernel<4, 8>), dim3(1), dim3(1024), 0, s, N, LU, k0, w, piv, info);
-            } else if (m <= 8192) {
-                w = std::min(8, KE - k0);
-                hipLaunchKernelGGL((panel_reg_kernel<8, 8>), dim3(1), dim3(1024), 0, s, N, LU, k0, w, piv, info);
-            } else {
+            if (N - k0 > 16384) {
                 w = std::min(32, KE - k0);
                 hipLaunchKernelGGL(panel_kernel, dim3(1), dim3(1024), 0, s, N, LU, k0, w, piv, info);
+            } else {
+                w = pivot ? launch_panel<true>(N, LU, k0, KE, piv, info, s) : launch_panel<false>(N, LU, k0, KE, piv, info, s);
             }
             // the panel's interchanges on the other block columns, U12 right of it
-            const int others = KE - K0 - w;
+            // (without pivoting: only the columns right of it, for U12)
+            const int others = pivot ? KE - K0 - w : KE - k0 - w;
             if (others > 0)
-                hipLaunchKernelGGL(swap_trsm_kernel, dim3((others + 3) / 4), dim3(256), 0, s, N, LU, k0, w, piv, K0, KE);
+                hipLaunchKernelGGL(swap_trsm_kernel, dim3((others + 3) / 4), dim3(256), 0, s, N, LU, k0, w, piv,
+                                   pivot ? K0 : k0, KE, pivot ? 1 : 0);
             const int rin = KE - k0 - w;   // block columns right of the narrow panel
             if (rin > 0)
                 hipLaunchKernelGGL(gemm_update_kernel, dim3((N - k0 - w + 63) / 64, (rin + 63) / 64), dim3(256), 0, s,
@@ -650,7 +793,7 @@ hipError_t lu_factor_f32(int N, float *LU, int *piv, int *info, void *diag_inv, 
             k0 += w;
         }
         // the block's interchanges on the columns outside it (left: L of earlier blocks; right: A12, A22)
-        if (N - (KE - K0) > 0)
+        if (pivot && N - (KE - K0) > 0)
             hipLaunchKernelGGL(laswp_kernel, dim3((N - (KE - K0) + 255) / 256), dim3(256), 0, s, N, LU, K0, KE - K0, piv);
         const int rest = N - KE;
         if (rest > 0) {
@@ -692,84 +835,126 @@ int mixed_solve(int N, const void *d_A, int64_t lda, int a_prec, const double *d
         msg = std::string(m) + (e != hipSuccess ? std::string(": ") + hipGetErrorString(e) : std::string());
         return st;
     };
-    dim3 tg((N + 31) / 32, (N + 31) / 32);
-    if (a_prec == 0)
-        hipLaunchKernelGGL(to_colmajor_kernel<double>, tg, dim3(256), 0, s, N, static_cast<const double *>(d_A), lda, w.LU);
-    else
-        hipLaunchKernelGGL(to_colmajor_kernel<float>, tg, dim3(256), 0, s, N, static_cast<const float *>(d_A), lda, w.LU);
-    hipError_t e = lu_factor_f32(N, w.LU, w.piv, w.info, w.DI, s);
-    if (e != hipSuccess) return fail(-5, "LU factorisation launch", e);
-    // ||A||_inf for the backward error (one read of A)
-    if (a_prec == 0)
+    // ||A||_inf for the backward error (one read of A) and the exact symmetry test
+    const int ngrid = std::min(N, 1024);
+    if (a_prec == 0) {
         hipLaunchKernelGGL(rowabs_kernel<double>, dim3((N + 3) / 4), dim3(256), 0, s, N, static_cast<const double *>(d_A), lda, w.red + 8);
-    else
+        hipLaunchKernelGGL(asym_kernel<double>, dim3(ngrid), dim3(256), 0, s, N, static_cast<const double *>(d_A), lda, w.r);
+    } else {
         hipLaunchKernelGGL(rowabs_kernel<float>, dim3((N + 3) / 4), dim3(256), 0, s, N, static_cast<const float *>(d_A), lda, w.red + 8);
-    hipLaunchKernelGGL(max_kernel, dim3(1), dim3(1024), 0, s, N, w.red + 8, w.red + 4);
-    // permutation from the interchange sequence (host, O(N))
-    std::vector<int> piv(N), perm(N);
-    int info = 0;
-    double normA = 0.0;
-    if ((e = hipMemcpyAsync(piv.data(), w.piv, N * sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess ||
-        (e = hipMemcpyAsync(&info, w.info, sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess ||
-        (e = hipMemcpyAsync(&normA, w.red + 4, sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess ||
-        (e = hipStreamSynchronize(s)) != hipSuccess)
-        return fail(-5, "LU factorisation", e);
-    if (info != 0) return fail(-3, "zero pivot in the FP32 LU factorisation", hipSuccess);
-    for (int i = 0; i < N; ++i) perm[i] = i;
-    for (int j = 0; j < N; ++j) std::swap(perm[j], perm[piv[j]]);
-    if ((e = hipMemcpyAsync(w.perm, perm.data(), N * sizeof(int), hipMemcpyHostToDevice, s)) != hipSuccess)
-        return fail(-5, "permutation upload", e);
-
-    auto residual = [&]() {
-        if (a_prec == 0) launch_residual<double>(N, d_A, lda, d_x, d_beta, w.r, s);
-        else launch_residual<float>(N, d_A, lda, d_x, d_beta, w.r, s);
-    };
-    double red[4];
-    // x0 = LU \ beta
-    hipLaunchKernelGGL(permute_kernel, dim3((N + 255) / 256), dim3(256), 0, s, N, w.perm, d_beta, w.v);
-    (void)lu_solve_f32(N, w.LU, w.DI, w.v, w.v2, s);
-    hipLaunchKernelGGL(update_norms_kernel, dim3(1), dim3(1024), 0, s, N, d_x, w.v, d_beta, d_beta, 0, w.red);
-    res.iters = 0;
-    res.rel_update = 1.0;
-    res.backward_err = 1.0;
-    int status = -4;
-    double prev = 1e300;
-    // Refinement: stop when ||d|| <= tol ||x||, or when the corrections stop
-    // shrinking (||d_k|| > ||d_{k-1}|| / 2: the FP64 residual has reached the
-    // cond(A) eps floor) with a backward error at the FP64 level.
-    for (int it = 0; it < max_iter; ++it) {
-        residual();
-        hipLaunchKernelGGL(permute_kernel, dim3((N + 255) / 256), dim3(256), 0, s, N, w.perm, w.r, w.v);
-        (void)lu_solve_f32(N, w.LU, w.DI, w.v, w.v2, s);
-        hipLaunchKernelGGL(update_norms_kernel, dim3(1), dim3(1024), 0, s, N, d_x, w.v, w.r, d_beta, 1, w.red);
-        if ((e = hipMemcpyAsync(red, w.red, sizeof red, hipMemcpyDeviceToHost, s)) != hipSuccess ||
-            (e = hipStreamSynchronize(s)) != hipSuccess)
-            return fail(-5, "refinement step", e);
-        res.iters = it + 1;
-        res.rel_update = red[1] > 0 ? red[0] / red[1] : 0.0;
-        res.backward_err = red[2] / (normA * red[1] + red[3]);   // of the iterate before this step
-        if (res.rel_update <= tol) {
-            status = 0;
-            break;
-        }
-        if (res.rel_update > 0.5 * prev && res.backward_err <= 64 * 1.1102230246251565e-16) {
-            status = 0;
-            break;
-        }
-        prev = res.rel_update;
+        hipLaunchKernelGGL(asym_kernel<float>, dim3(ngrid), dim3(256), 0, s, N, static_cast<const float *>(d_A), lda, w.r);
     }
-    // backward error of the returned x: ||beta - A x||_inf / (||A||_inf ||x||_inf + ||beta||_inf)
-    residual();
-    hipLaunchKernelGGL(max_kernel, dim3(1), dim3(1024), 0, s, N, w.r, w.red + 5);
-    hipLaunchKernelGGL(max_kernel, dim3(1), dim3(1024), 0, s, N, d_x, w.red + 6);
-    hipLaunchKernelGGL(max_kernel, dim3(1), dim3(1024), 0, s, N, d_beta, w.red + 7);
-    double nr[4];
-    if ((e = hipMemcpyAsync(nr, w.red + 4, sizeof nr, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+    hipLaunchKernelGGL(max_kernel, dim3(1), dim3(1024), 0, s, N, w.red + 8, w.red + 4);
+    hipLaunchKernelGGL(max_kernel, dim3(1), dim3(1024), 0, s, ngrid, w.r, w.red + 3);
+    double na[2];   // max |A_ij - A_ji|, ||A||_inf
+    hipError_t e;
+    if ((e = hipMemcpyAsync(na, w.red + 3, sizeof na, hipMemcpyDeviceToHost, s)) != hipSuccess ||
         (e = hipStreamSynchronize(s)) != hipSuccess)
-        return fail(-5, "backward error", e);
-    res.backward_err = nr[1] / (nr[0] * nr[2] + nr[3]);
-    if (status != 0) return fail(-4, "iterative refinement did not reach the tolerance", hipSuccess);
-    return 0;
+        return fail(-5, "matrix norm", e);
+    const double normA = na[1];
+    // A symmetric matrix (the Galerkin matrix is) is first factored without
+    // interchanges: stable for a positive definite matrix, the setting of the
+    // method.  The FP64-refined solution is accepted only if the refinement
+    // converges; a zero pivot or a refinement that stalls short of the target
+    // means a refactorisation with partial pivoting, as for any other matrix.
+    bool pivot = !(na[0] == 0.0 && lu_without_pivoting_supported(N));
+    for (;;) {
+        dim3 tg((N + 31) / 32, (N + 31) / 32);
+        if (a_prec == 0)
+            hipLaunchKernelGGL(to_colmajor_kernel<double>, tg, dim3(256), 0, s, N, static_cast<const double *>(d_A), lda, w.LU);
+        else
+            hipLaunchKernelGGL(to_colmajor_kernel<float>, tg, dim3(256), 0, s, N, static_cast<const float *>(d_A), lda, w.LU);
+        if ((e = lu_factor_f32(N, w.LU, w.piv, w.info, w.DI, pivot, s)) != hipSuccess)
+            return fail(-5, "LU factorisation launch", e);
+        // the permutation from the interchange sequence (host, O(N)); none without pivoting
+        std::vector<int> piv(N), perm(N);
+        int info = 0;
+        if ((pivot && (e = hipMemcpyAsync(piv.data(), w.piv, N * sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess) ||
+            (e = hipMemcpyAsync(&info, w.info, sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+            (e = hipStreamSynchronize(s)) != hipSuccess)
+            return fail(-5, "LU factorisation", e);
+        if (info != 0) {
+            if (!pivot) {
+                pivot = true;
+                continue;
+            }
+            return fail(-3, "zero pivot in the FP32 LU factorisation", hipSuccess);
+        }
+        for (int i = 0; i < N; ++i) perm[i] = i;
+        if (pivot)
+            for (int j = 0; j < N; ++j) std::swap(perm[j], perm[piv[j]]);
+        if ((e = hipMemcpyAsync(w.perm, perm.data(), N * sizeof(int), hipMemcpyHostToDevice, s)) != hipSuccess)
+            return fail(-5, "permutation upload", e);
+
+        auto residual = [&]() {
+            if (a_prec == 0) launch_residual<double>(N, d_A, lda, d_x, d_beta, w.r, s);
+            else launch_residual<float>(N, d_A, lda, d_x, d_beta, w.r, s);
+        };
+        double red[4];
+        // x0 = LU \ beta
+        hipLaunchKernelGGL(permute_kernel, dim3((N + 255) / 256), dim3(256), 0, s, N, w.perm, d_beta, w.v);
+        (void)lu_solve_f32(N, w.LU, w.DI, w.v, w.v2, s);
+        hipLaunchKernelGGL(update_norms_kernel, dim3(1), dim3(1024), 0, s, N, d_x, w.v, d_beta, d_beta, 0, w.red);
+        res.iters = 0;
+        res.rel_update = 1.0;
+        res.backward_err = 1.0;
+        res.pivoted = pivot;
+        int status = -4;
+        double prev = 1e300;
+        // Refinement: stop when ||d|| <= tol ||x||, or when the corrections stop
+        // shrinking (||d_k|| > ||d_{k-1}|| / 2: the FP64 residual has reached the
+        // cond(A) eps floor) with a backward error at the FP64 level.  Without
+        // pivoting, corrections that stop shrinking above that level end the
+        // attempt.
+        bool stalled = false;
+        for (int it = 0; it < max_iter; ++it) {
+            residual();
+            hipLaunchKernelGGL(permute_kernel, dim3((N + 255) / 256), dim3(256), 0, s, N, w.perm, w.r, w.v);
+            (void)lu_solve_f32(N, w.LU, w.DI, w.v, w.v2, s);
+            hipLaunchKernelGGL(update_norms_kernel, dim3(1), dim3(1024), 0, s, N, d_x, w.v, w.r, d_beta, 1, w.red);
+            if ((e = hipMemcpyAsync(red, w.red, sizeof red, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+                (e = hipStreamSynchronize(s)) != hipSuccess)
+                return fail(-5, "refinement step", e);
+            res.iters = it + 1;
+            res.rel_update = red[1] > 0 ? red[0] / red[1] : 0.0;
+            res.backward_err = red[2] / (normA * red[1] + red[3]);   // of the iterate before this step
+            if (res.rel_update <= tol) {
+                status = 0;
+                break;
+            }
+            if (res.rel_update > 0.5 * prev) {
+                if (res.backward_err <= 64 * 1.1102230246251565e-16) {
+                    status = 0;
+                    break;
+                }
+                if (!pivot) {
+                    stalled = true;
+                    break;
+                }
+            }
+            if (!(res.rel_update < 1e300)) {   // NaN or overflow: no convergence from here
+                if (!pivot) stalled = true;
+                break;
+            }
+            prev = res.rel_update;
+        }
+        if (status != 0 && !pivot && (stalled || max_iter > 0)) {
+            pivot = true;
+            continue;
+        }
+        // backward error of the returned x: ||beta - A x||_inf / (||A||_inf ||x||_inf + ||beta||_inf)
+        residual();
+        hipLaunchKernelGGL(max_kernel, dim3(1), dim3(1024), 0, s, N, w.r, w.red + 5);
+        hipLaunchKernelGGL(max_kernel, dim3(1), dim3(1024), 0, s, N, d_x, w.red + 6);
+        hipLaunchKernelGGL(max_kernel, dim3(1), dim3(1024), 0, s, N, d_beta, w.red + 7);
+        double nr[3];
+        if ((e = hipMemcpyAsync(nr, w.red + 5, sizeof nr, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+            (e = hipStreamSynchronize(s)) != hipSuccess)
+            return fail(-5, "backward error", e);
+        res.backward_err = nr[0] / (normA * nr[1] + nr[2]);
+        if (status != 0) return fail(-4, "iterative refinement did not reach the tolerance", hipSuccess);
+        return 0;
+    }
 }
 
 }  // namespace sgbem

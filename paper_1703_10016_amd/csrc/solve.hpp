@@ -13,6 +13,7 @@ struct SolveResult {
     int iters = 0;
     double rel_update = 0.0;
     double backward_err = 0.0;
+    bool pivoted = true;     // false: factored without row interchanges
 };
 
 size_t solve_workspace_bytes(int N);
@@ -22,9 +23,12 @@ int mixed_solve(int N, const void *d_A, int64_t lda, int a_prec, const double *d
                 int max_iter, void *ws, hipStream_t stream, SolveResult &res, std::string &msg);
 
 // Pieces, also used on their own by the tests and the serving loop.
-// FP32 LU in place (column-major, ld = N) with partial pivoting; when diag_inv
-// is given it receives the inverses of the 64 x 64 diagonal blocks of L and U.
-hipError_t lu_factor_f32(int N, float *LU, int *piv, int *info, void *diag_inv, hipStream_t s);
+// FP32 LU in place (column-major, ld = N), with partial pivoting or (pivot
+// false, N within lu_without_pivoting_supported) with the diagonal as pivot;
+// when diag_inv is given it receives the inverses of the 64 x 64 diagonal
+// blocks of L and U.
+bool lu_without_pivoting_supported(int N);
+hipError_t lu_factor_f32(int N, float *LU, int *piv, int *info, void *diag_inv, bool pivot, hipStream_t s);
 // b := U^{-1} L^{-1} b for an already permuted b (tmp: N floats of scratch).
 hipError_t lu_solve_f32(int N, const float *LU, const float *diag_inv, float *b, float *tmp, hipStream_t s);
 

@@ -40,7 +40,7 @@ class sgbem_curve(ctypes.Structure):
 
 class sgbem_solve_info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32), ("rel_update", ctypes.c_double),
-                ("backward_err", ctypes.c_double)]
+                ("backward_err", ctypes.c_double), ("pivoted", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class sgbem_server_config(ctypes.Structure):

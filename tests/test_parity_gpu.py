@@ -175,19 +175,92 @@ def test_rhs_matches_oracle(ctx, method, R, G):
 
 
 # ------------------------------------------------------------------ solve
-@pytest.mark.parametrize("N,prec", [(256, "fp64"), (200, "fp32"), (1000, "fp64"), (2500, "fp64"), (4500, "fp32"),
-                                    (9000, "fp64")])
-def test_mixed_solve_matches_fp64_solve(ctx, N, prec):
+SOLVE_SIZES = [(256, "fp64"), (200, "fp32"), (1000, "fp64"), (2500, "fp64"), (4500, "fp32"), (9000, "fp64")]
+
+
+def skew_perturbed(A, seed):
+    """A + 1e-3 (A o S), S antisymmetric with entries in [-1, 1]: no longer
+    symmetric (so the solve pivots), conditioned like A."""
+    import torch
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    R = torch.rand(A.shape, generator=g, dtype=torch.float64) * 2 - 1
+    S = (torch.triu(R, 1) - torch.triu(R, 1).T).to(A.device, A.dtype)
+    return A + 1e-3 * A * S
+
+
+@pytest.mark.parametrize("sym", [True, False], ids=["symmetric", "nonsymmetric"])
+@pytest.mark.parametrize("N,prec", SOLVE_SIZES)
+def test_mixed_solve_matches_fp64_solve(ctx, N, prec, sym):
+    """Symmetric Galerkin matrices take the factorisation without interchanges
+    (star curves: indefinite, capacity > 1) unless it fails; a non-symmetric
+    matrix is factored with partial pivoting (every panel shape of either kind
+    runs across these sizes)."""
     curve, p = synth.star(13), 3
     A = ctx.assemble(curve, p, N, "wq", precision=prec)
+    if not sym:
+        A = skew_perturbed(A, N)
     beta = ctx.rhs(curve, p, N, synth.g_exp_cos)
     x, info = ctx.solve(A, beta, tol=1e-12, max_iter=30)
     Ah = A.cpu().numpy().astype(np.float64)
     ref = np.linalg.solve(Ah, beta.cpu().numpy())
     xh = x.cpu().numpy()
     err = np.linalg.norm(xh - ref) / np.linalg.norm(ref)
-    assert err < 1e-10, (err, info.iters, info.rel_update, info.backward_err)
+    assert err < 1e-10, (err, info.iters, info.rel_update, info.backward_err, info.pivoted)
     assert info.backward_err < 1e-14 and info.iters >= 1
+    if not sym:
+        assert info.pivoted == 1
+
+
+def test_positive_definite_solve_without_interchanges(ctx):
+    """The ellipse (capacity 0.75 < 1: positive definite Galerkin matrix, the
+    paper's setting): factored without interchanges, same solution."""
+    c = synth.config_ellipse()
+    A = ctx.assemble(c.curve, c.p, c.N, "wq")
+    beta = ctx.rhs(c.curve, c.p, c.N, c.g)
+    x, info = ctx.solve(A, beta, tol=1e-12)
+    assert info.pivoted == 0
+    ref = np.linalg.solve(A.cpu().numpy(), beta.cpu().numpy())
+    assert np.linalg.norm(x.cpu().numpy() - ref) / np.linalg.norm(ref) < 1e-10
+
+
+def test_symmetric_zero_pivot_falls_back_to_pivoting(ctx):
+    """A symmetric matrix with a zero diagonal (every first pivot is zero):
+    the attempt without interchanges fails and partial pivoting solves it."""
+    import torch
+    N = 300
+    rng = np.random.default_rng(5)
+    B = rng.standard_normal((N // 2, N // 2)) + 4 * np.eye(N // 2)
+    A = np.zeros((N, N))
+    A[:N // 2, N // 2:] = B
+    A[N // 2:, :N // 2] = B.T
+    beta = rng.standard_normal(N)
+    x, info = ctx.solve(torch.from_numpy(A).cuda(), torch.from_numpy(beta).cuda(), tol=1e-12)
+    assert info.pivoted == 1
+    ref = np.linalg.solve(A, beta)
+    assert np.linalg.norm(x.cpu().numpy() - ref) / np.linalg.norm(ref) < 1e-10
+
+
+@pytest.mark.parametrize("N,sym", [(16384, True), (16500, True), (16500, False)])
+def test_large_solve_backward_error(ctx, N, sym):
+    """N = 16384 (the tallest panels without interchanges), N = 16500 (partial
+    pivoting: panels taller than 16384 rows at the start, every register panel
+    shape after): the FP64 residual of the refined solution, formed
+    independently by a library matrix-vector product, is at rounding level."""
+    import torch
+    curve, p = synth.star(14), 3
+    A = ctx.assemble(curve, p, N, "wq", precision="fp32")
+    if not sym:
+        A = skew_perturbed(A, N)
+    beta = ctx.rhs(curve, p, N, synth.g_exp_cos)
+    x, info = ctx.solve(A, beta, tol=1e-10, max_iter=30)
+    if N > 16384:
+        assert info.pivoted == 1
+    A64 = A.double()
+    r = beta - A64 @ x
+    bwd = (r.abs().max() / (A64.abs().sum(dim=1).max() * x.abs().max() + beta.abs().max())).item()
+    del A64
+    assert bwd < 1e-14, (bwd, info.iters, info.backward_err)
+    assert abs(bwd - info.backward_err) < 1e-15 + 0.1 * bwd
 
 
 def test_solve_circle_exact_discrete_solution(ctx):
