@@ -728,8 +728,9 @@ __global__ __launch_bounds__(1024) void trsm_rows_kernel(int N, float *LU, int K
 // (the same arithmetic in each) and then updates its own rows.
 // Inverses of the 64 x 64 diagonal blocks of L (unit lower) and U, kept so
 // that every block step of the triangular solves is a plain matrix-vector
-// product.  DI[b][0] = inv(L_bb), DI[b][1] = inv(U_bb), row-major 64 x 64;
-// a partial last block is padded with the identity.
+// product.  DI[b][0] = inv(L_bb), DI[b][1] = inv(U_bb), column-major 64 x 64
+// (entry (r, k) at k * 64 + r: a wavefront reading row r = lane of column k is
+// coalesced); a partial last block is padded with the identity.
 __global__ __launch_bounds__(64) void invert_diag_kernel(int N, const float *LU, float *DI)
 {
     __shared__ float T[64][65];
@@ -744,7 +745,7 @@ __global__ __launch_bounds__(64) void invert_diag_kernel(int N, const float *LU,
         for (int k = 0; k < r; ++k) s -= T[r][k] * X[k][c];
         X[r][c] = s;
     }
-    for (int r = 0; r < 64; ++r) DI[(int64_t(blockIdx.x) * 2 + 0) * 4096 + r * 64 + c] = X[r][c];
+    for (int r = 0; r < 64; ++r) DI[(int64_t(blockIdx.x) * 2 + 0) * 4096 + c * 64 + r] = X[r][c];
     __syncthreads();
     // U X = I, column c: X[r][c] = (delta_rc - sum_{k>r} U[r][k] X[k][c]) / U[r][r]
     for (int r = 63; r >= 0; --r) {
@@ -752,12 +753,14 @@ __global__ __launch_bounds__(64) void invert_diag_kernel(int N, const float *LU,
         for (int k = r + 1; k < 64; ++k) s -= T[r][k] * X[k][c];
         X[r][c] = s / T[r][r];
     }
-    for (int r = 0; r < 64; ++r) DI[(int64_t(blockIdx.x) * 2 + 1) * 4096 + r * 64 + c] = X[r][c];
+    for (int r = 0; r < 64; ++r) DI[(int64_t(blockIdx.x) * 2 + 1) * 4096 + c * 64 + r] = X[r][c];
 }
 
 // Forward step for the 64-row block at b0: x_b = inv(L_bb) y_b (computed by
 // every workgroup), written to yout by workgroup 0; rows below are updated in
-// y (rows of the block itself are only read in this launch).
+// y (rows of the block itself are only read in this launch).  Both products
+// issue their 64 loads unconditionally (clamped addresses, the solved block
+// padded with zeros), so the loads are in flight together.
 __global__ __launch_bounds__(256) void trsv_lower_kernel(int N, const float *LU, const float *DI, float *y, float *yout, int b0)
 {
     __shared__ float yb[64], xb[64];
@@ -766,19 +769,26 @@ __global__ __launch_bounds__(256) void trsv_lower_kernel(int N, const float *LU,
     if (tid < 64) yb[tid] = tid < bw ? y[b0 + tid] : 0.0f;
     __syncthreads();
     if (tid < 64) {
-        const float *row = DI + (int64_t(b0 / 64) * 2 + 0) * 4096 + tid * 64;
+        const float *blk = DI + (int64_t(b0 / 64) * 2 + 0) * 4096 + tid;
+        float d[64];
+#pragma unroll
+        for (int k = 0; k < 64; ++k) d[k] = blk[k * 64];
         float s = 0.0f;
-        for (int k = 0; k < 64; ++k) s += row[k] * yb[k];
-        xb[tid] = s;
+#pragma unroll
+        for (int k = 0; k < 64; ++k) s += d[k] * yb[k];
+        xb[tid] = tid < bw ? s : 0.0f;
         if (blockIdx.x == 0 && tid < bw) yout[b0 + tid] = s;
     }
     __syncthreads();
     const int r = b0 + bw + blockIdx.x * blockDim.x + tid;
-    if (r < N) {
-        float s = 0.0f;
-        for (int k = 0; k < bw; ++k) s += LU[int64_t(b0 + k) * N + r] * xb[k];
-        y[r] -= s;
-    }
+    const float *col = LU + int64_t(b0) * N + min(r, N - 1);
+    float v[64];
+#pragma unroll
+    for (int k = 0; k < 64; ++k) v[k] = col[int64_t(min(k, bw - 1)) * N];
+    float s = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 64; ++k) s += v[k] * xb[k];
+    if (r < N) y[r] -= s;
 }
 
 __global__ __launch_bounds__(256) void trsv_upper_kernel(int N, const float *LU, const float *DI, float *y, float *yout, int b0, int bw)
@@ -788,19 +798,26 @@ __global__ __launch_bounds__(256) void trsv_upper_kernel(int N, const float *LU,
     if (tid < 64) yb[tid] = tid < bw ? y[b0 + tid] : 0.0f;
     __syncthreads();
     if (tid < 64) {
-        const float *row = DI + (int64_t(b0 / 64) * 2 + 1) * 4096 + tid * 64;
+        const float *blk = DI + (int64_t(b0 / 64) * 2 + 1) * 4096 + tid;
+        float d[64];
+#pragma unroll
+        for (int k = 0; k < 64; ++k) d[k] = blk[k * 64];
         float s = 0.0f;
-        for (int k = 0; k < 64; ++k) s += row[k] * yb[k];
-        xb[tid] = s;
+#pragma unroll
+        for (int k = 0; k < 64; ++k) s += d[k] * yb[k];
+        xb[tid] = tid < bw ? s : 0.0f;
         if (blockIdx.x == 0 && tid < bw) yout[b0 + tid] = s;
     }
     __syncthreads();
     const int r = blockIdx.x * blockDim.x + tid;
-    if (r < b0) {
-        float s = 0.0f;
-        for (int k = 0; k < bw; ++k) s += LU[int64_t(b0 + k) * N + r] * xb[k];
-        y[r] -= s;
-    }
+    const float *col = LU + int64_t(b0) * N + min(r, max(b0 - 1, 0));
+    float v[64];
+#pragma unroll
+    for (int k = 0; k < 64; ++k) v[k] = col[int64_t(min(k, bw - 1)) * N];
+    float s = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 64; ++k) s += v[k] * xb[k];
+    if (r < b0) y[r] -= s;
 }
 
 __global__ void permute_kernel(int N, const int *perm, const double *src, float *dst)
