@@ -723,6 +723,143 @@ __global__ __launch_bounds__(1024) void trsm_rows_kernel(int N, float *LU, int K
     }
 }
 
+// Small matrices (N <= 4096), without interchanges, in 64-column blocks: the
+// diagonal block is factored by one wavefront and inverted by two, and L21, U12
+// become plain products with the inverses (no dependent chain), so each block
+// takes three launches.
+//
+// diag64_kernel: wavefront 0 factors the bk x bk block (bk <= 64, padded with
+// the identity) with lane l holding row l in registers: per column j the
+// pivot row's entries come from lane j by readlane (every index a
+// compile-time constant: the loops are unrolled); then, from the factor staged
+// in LDS, wavefront 0 forms inv(L) and wavefront 1 inv(U), lane c holding
+// column c (forward / backward substitution against the identity, the factor
+// read by broadcast).  The inverses go to DI (the inverted diagonal blocks of
+// the triangular solves, column-major); a zero or non-finite pivot is
+// reported in info like a singular column.
+__global__ __launch_bounds__(128) void diag64_kernel(int N, float *LU, int K0, int bk, float *DI, int *info)
+{
+    __shared__ float F[64][65];      // the factor: unit-lower L below the diagonal, U on and above
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (wave == 0) {
+        float e[64];
+        const int lr = min(lane, bk - 1);
+#pragma unroll
+        for (int c = 0; c < 64; ++c) {
+            const bool in = lane < bk && c < bk;
+            e[c] = LU[int64_t(K0 + min(c, bk - 1)) * N + K0 + lr] * (in ? 1.0f : 0.0f) + ((!in && lane == c) ? 1.0f : 0.0f);
+        }
+#pragma unroll
+        for (int c = 0; c < 64; ++c) asm volatile("" : "+v"(e[c]));
+        int bad = 0;
+#pragma unroll
+        for (int j = 0; j < 64; ++j) {
+            const float d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(e[j]), j));
+            const bool ok = fabsf(d) > 0.0f && fabsf(d) <= 3.402823466e38f;
+            if (!ok && j < bk && bad == 0) bad = K0 + j + 1;
+            const float inv = ok ? 1.0f / d : 0.0f;
+            const float l = lane > j ? e[j] * inv : 0.0f;
+            e[j] = lane > j ? l : e[j];
+#pragma unroll
+            for (int c = j + 1; c < 64; ++c)
+                e[c] -= l * __int_as_float(__builtin_amdgcn_readlane(__float_as_int(e[c]), j));
+        }
+#pragma unroll
+        for (int c = 0; c < 64; ++c) F[lane][c] = e[c];
+        float *LUs = LU;
+        asm volatile("" : "+s"(LUs));
+#pragma unroll
+        for (int c = 0; c < 64; ++c)
+            if (c < bk && lane < bk) LUs[int64_t(K0 + c) * N + K0 + lane] = e[c];
+        if (lane == 0 && bad != 0 && *info == 0) *info = bad;
+    }
+    __syncthreads();
+    float x[64];
+    if (wave == 0) {
+        // inv(L), column lane: x_r = delta_{r,lane} - sum_{k<r} L_rk x_k
+#pragma unroll
+        for (int r = 0; r < 64; ++r) {
+            float sum = r == lane ? 1.0f : 0.0f;
+#pragma unroll
+            for (int k = 0; k < r; ++k) sum -= F[r][k] * x[k];
+            x[r] = sum;
+        }
+    } else {
+        // inv(U), column lane: x_r = (delta_{r,lane} - sum_{k>r} U_rk x_k) / U_rr
+#pragma unroll
+        for (int r = 63; r >= 0; --r) {
+            float sum = r == lane ? 1.0f : 0.0f;
+#pragma unroll
+            for (int k = r + 1; k < 64; ++k) sum -= F[r][k] * x[k];
+            x[r] = sum / F[r][r];
+        }
+    }
+    float *out = DI + (int64_t(K0 / 64) * 2 + wave) * 4096 + lane * 64;   // column lane, entries r
+#pragma unroll
+    for (int r = 0; r < 64; r += 4) *reinterpret_cast<float4 *>(out + r) = make_float4(x[r], x[r + 1], x[r + 2], x[r + 3]);
+}
+
+// After diag64_kernel: workgroups [0, nrb) form L21 = A21 inv(U11) on 64-row
+// blocks below the diagonal block, workgroups [nrb, 2 nrb) form
+// U12 = inv(L11) A12 on 64-column blocks right of it (a block of 64 x bk or
+// bk x 64 entries in LDS with the 64 x 64 inverse, one product, written back in
+// place: every workgroup reads and writes only its own entries).
+__global__ __launch_bounds__(256) void panel_mul_kernel(int N, float *LU, int K0, int bk, int KE, const float *DI, int nrb)
+{
+    __shared__ float X[64][65], V[64][65];
+    const int tid = threadIdx.x;
+    const bool rows = int(blockIdx.x) < nrb;
+    const int blk = rows ? blockIdx.x : blockIdx.x - nrb;
+    const int b0 = KE + 64 * blk, nb = min(64, N - b0);
+    // the inverse: V[r][k] = entry (r, k), DI column-major (entry (r, k) at k * 64 + r)
+    const float *inv = DI + (int64_t(K0 / 64) * 2 + (rows ? 1 : 0)) * 4096;
+    float v[16], xv[16];
+#pragma unroll
+    for (int it = 0; it < 16; ++it) {
+        const int e = tid + it * 256;
+        v[it] = inv[e];                                              // entry (e % 64, e / 64)
+        const int i = e & 63, j = e >> 6;
+        // rows: X[i][j] = A21(b0 + i, K0 + j); columns: X[i][j] = A12(K0 + i, b0 + j)
+        const int64_t a = rows ? int64_t(K0 + min(j, bk - 1)) * N + min(b0 + i, N - 1)
+                               : int64_t(min(b0 + j, N - 1)) * N + K0 + min(i, bk - 1);
+        const bool in = rows ? (i < nb && j < bk) : (i < bk && j < nb);
+        xv[it] = LU[a] * (in ? 1.0f : 0.0f);
+    }
+#pragma unroll
+    for (int it = 0; it < 16; ++it) {
+        const int e = tid + it * 256;
+        V[e & 63][e >> 6] = v[it];
+        X[e & 63][e >> 6] = xv[it];
+    }
+    __syncthreads();
+    // thread: output row i = tid % 64 and 16 output columns from j0 = (tid / 64) * 16
+    const int i = tid & 63, j0 = (tid >> 6) * 16;
+    float y[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) y[q] = 0.0f;
+#pragma unroll 8
+    for (int k = 0; k < 64; ++k) {
+        if (rows) {           // Y = X V: Y[i][j] = sum_k X[i][k] V[k][j]
+            const float xk = X[i][k];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) y[q] += xk * V[k][j0 + q];
+        } else {              // Y = V X: Y[i][j] = sum_k V[i][k] X[k][j]
+            const float vk = V[i][k];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) y[q] += vk * X[k][j0 + q];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int j = j0 + q;
+        if (rows) {
+            if (i < nb && j < bk) LU[int64_t(K0 + j) * N + b0 + i] = y[q];
+        } else {
+            if (i < bk && j < nb) LU[int64_t(b0 + j) * N + K0 + i] = y[q];
+        }
+    }
+}
+
 // ---------------------------------------------------------------- triangular solves
 // One launch per 64-row block; every workgroup solves the diagonal block
 // (the same arithmetic in each) and then updates its own rows.
@@ -974,6 +1111,15 @@ size_t solve_workspace_bytes(int N)
 
 bool lu_without_pivoting_supported(int N) { return N <= 16384; }
 
+namespace {
+// The rank-bk update of the trailing matrix [KE, N) x [KE, N).
+void trailing_update(int N, float *LU, int KE, int K0, int bk, hipStream_t s)
+{
+    const int nb = (N - KE + 63) / 64;
+    hipLaunchKernelGGL(gemm_update_kernel, dim3(nb, nb), dim3(256), 0, s, N, LU, KE, KE, N, K0, bk);
+}
+}  // namespace
+
 hipError_t lu_factor_f32(int N, float *LU, int *piv, int *info, void *diag_inv, bool pivot, hipStream_t s)
 {
     // Two levels: blocks of BK columns, each factored by narrow register panels
@@ -987,6 +1133,24 @@ hipError_t lu_factor_f32(int N, float *LU, int *piv, int *info, void *diag_inv, 
     // interchange is applied anywhere.
     if (!pivot && !lu_without_pivoting_supported(N)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(64), 0, s, info);
+    if (!pivot && N <= 4096 && diag_inv) {
+        // 64-column blocks: diagonal block factored and inverted (its inverses are
+        // the triangular solves' inverted diagonal blocks), then L21 and U12 as
+        // products with the inverses, then the rank-64 update
+        float *DI = static_cast<float *>(diag_inv);
+        for (int K0 = 0; K0 < N; K0 += 64) {
+            const int bk = std::min(64, N - K0), KE = K0 + bk, rest = N - KE;
+            hipLaunchKernelGGL(diag64_kernel, dim3(1), dim3(128), 0, s, N, LU, K0, bk, DI, info);
+            if (rest > 0) {
+                const int nrb = (rest + 63) / 64;
+                hipLaunchKernelGGL(panel_mul_kernel, dim3(2 * nrb), dim3(256), 0, s, N, LU, K0, bk, KE, DI, nrb);
+                trailing_update(N, LU, KE, K0, bk, s);
+            }
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        return hipGetLastError();
+    }
     if (!pivot) {
         // without interchanges the rows below a block are independent once its
         // diagonal block is factored: per block of 128 columns, the diagonal
@@ -998,8 +1162,7 @@ hipError_t lu_factor_f32(int N, float *LU, int *piv, int *info, void *diag_inv, 
             if (rest > 0) {
                 hipLaunchKernelGGL(trsm_rows_kernel, dim3((rest + 63) / 64), dim3(1024), 0, s, N, LU, K0, bk, KE);
                 hipLaunchKernelGGL(trsm_block_kernel, dim3((rest + 31) / 32), dim3(1024), 0, s, N, LU, K0, bk, KE);
-                const int nbk = (rest + 63) / 64;
-                hipLaunchKernelGGL(gemm_update_kernel, dim3(nbk, nbk), dim3(256), 0, s, N, LU, KE, KE, N, K0, bk);
+                trailing_update(N, LU, KE, K0, bk, s);
             }
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
@@ -1039,8 +1202,7 @@ hipError_t lu_factor_f32(int N, float *LU, int *piv, int *info, void *diag_inv, 
         const int rest = N - KE;
         if (rest > 0) {
             hipLaunchKernelGGL(trsm_block_kernel, dim3((rest + 31) / 32), dim3(1024), 0, s, N, LU, K0, KE - K0, KE);
-            const int nbk = (rest + 63) / 64;
-            hipLaunchKernelGGL(gemm_update_kernel, dim3(nbk, nbk), dim3(256), 0, s, N, LU, KE, KE, N, K0, KE - K0);
+            trailing_update(N, LU, KE, K0, KE - K0, s);
         }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
