@@ -223,16 +223,34 @@ def test_positive_definite_solve_without_interchanges(ctx):
     assert np.linalg.norm(x.cpu().numpy() - ref) / np.linalg.norm(ref) < 1e-10
 
 
-def test_symmetric_zero_pivot_falls_back_to_pivoting(ctx):
+@pytest.mark.parametrize("N", [300, 4200], ids=["64-column blocks", "128-column blocks"])
+def test_symmetric_zero_pivot_falls_back_to_pivoting(ctx, N):
     """A symmetric matrix with a zero diagonal (every first pivot is zero):
     the attempt without interchanges fails and partial pivoting solves it."""
     import torch
-    N = 300
     rng = np.random.default_rng(5)
     B = rng.standard_normal((N // 2, N // 2)) + 4 * np.eye(N // 2)
     A = np.zeros((N, N))
     A[:N // 2, N // 2:] = B
     A[N // 2:, :N // 2] = B.T
+    beta = rng.standard_normal(N)
+    x, info = ctx.solve(torch.from_numpy(A).cuda(), torch.from_numpy(beta).cuda(), tol=1e-12)
+    assert info.pivoted == 1
+    ref = np.linalg.solve(A, beta)
+    assert np.linalg.norm(x.cpu().numpy() - ref) / np.linalg.norm(ref) < 1e-10
+
+
+def test_symmetric_tiny_pivot_stalls_and_falls_back(ctx):
+    """A well-conditioned symmetric matrix whose first diagonal entry is tiny
+    but not zero: without interchanges the FP32 factors carry a growth of
+    ~1e12, the refinement stalls, and partial pivoting takes over."""
+    import torch
+    N = 200
+    rng = np.random.default_rng(6)
+    Q, _ = np.linalg.qr(rng.standard_normal((N, N)))
+    A = Q @ np.diag(np.linspace(1.0, 4.0, N)) @ Q.T
+    A = 0.5 * (A + A.T)
+    A[0, 0] = 1e-12
     beta = rng.standard_normal(N)
     x, info = ctx.solve(torch.from_numpy(A).cuda(), torch.from_numpy(beta).cuda(), tol=1e-12)
     assert info.pivoted == 1
