@@ -192,10 +192,6 @@ __device__ __forceinline__ unsigned wave_reduce_u32(unsigned v)
 //    scaled and updated with the pivot row held in registers, branch-free
 //    (inactive slots are updated with a zero multiplier), and in the same pass
 //    each thread takes its candidate for column j + 1.
-// With PIV false the pivot of column j is the diagonal entry itself (no
-// search, no interchanges: the factorisation without pivoting, which is used
-// for symmetric matrices); thread j publishes row gj, and a zero or non-finite
-// pivot is reported like a singular column.
 // Slots past N hold zeros at a position no real row has: they never become the
 // pivot (a zero magnitude only wins when every candidate is zero, and then
 // the lowest position, a real row, wins and the column is singular: no
@@ -203,7 +199,7 @@ __device__ __forceinline__ unsigned wave_reduce_u32(unsigned v)
 // parity: a buffer is written again two columns later, after a barrier that
 // every wavefront reaches only when done reading it.  Global memory is touched
 // only to load and store the panel, the pivots and info.
-template <int RT, int W, int NT, bool PIV>
+template <int RT, int W, int NT>
 __global__ __launch_bounds__(NT) void panel_reg_kernel(int N, float *LU, int k0, int w, int *piv, int *info)
 {
     constexpr int NWV = NT / 64;
@@ -245,7 +241,7 @@ __global__ __launch_bounds__(NT) void panel_reg_kernel(int N, float *LU, int k0,
     float best = -1.0f;
     int bpos = NONE, bslot = 0;
 #pragma unroll
-    for (int r = 0; r < (PIV ? RT : 0); ++r) {
+    for (int r = 0; r < RT; ++r) {
         const float m = fabsf(a[r][0]);
         const bool take = (m > best) | ((m == best) & (pos[r] < bpos));
         best = take ? m : best;
@@ -258,67 +254,50 @@ __global__ __launch_bounds__(NT) void panel_reg_kernel(int N, float *LU, int k0,
         // pass finds no pivot and changes nothing (only the singular flag is guarded)
         {
             const int gj = k0 + j, buf = j & 1;
-            bool ok;
-            int pr, gw = 0;
-            if constexpr (PIV) {
-                const bool has = best >= 0.0f;
-                const unsigned mag = has ? __float_as_uint(best) : 0u;   // monotone for non-negative floats
-                const int key = has ? bpos : NONE;
-                const unsigned wmag = wave_reduce_u32<true>(mag);
-                const int wpos = int(wave_reduce_u32<false>(mag == wmag ? unsigned(key) : unsigned(NONE)));
-                // publish the wavefront's candidate (its owner lane and slot made uniform)
-                const unsigned long long own = __ballot(key == wpos);
-                const int wl = int(__builtin_ctzll(own | (1ull << 63)));
-                const int rw = __builtin_amdgcn_readlane(bslot, wl);
+            const bool has = best >= 0.0f;
+            const unsigned mag = has ? __float_as_uint(best) : 0u;   // monotone for non-negative floats
+            const int key = has ? bpos : NONE;
+            const unsigned wmag = wave_reduce_u32<true>(mag);
+            const int wpos = int(wave_reduce_u32<false>(mag == wmag ? unsigned(key) : unsigned(NONE)));
+            // publish the wavefront's candidate (its owner lane and slot made uniform)
+            const unsigned long long own = __ballot(key == wpos);
+            const int wl = int(__builtin_ctzll(own | (1ull << 63)));
+            const int rw = __builtin_amdgcn_readlane(bslot, wl);
 #pragma unroll
-                for (int r = 0; r < RT; ++r)
-                    if (r == rw && lane == wl) {
-#pragma unroll
-                        for (int c = 0; c < W; ++c)
-                            if (c >= j) crow[buf][wid][c] = a[r][c];
-                    }
-                if (lane == 0) {
-                    smag[buf][wid] = wmag;
-                    spos[buf][wid] = wpos;
-                }
-                __syncthreads();
-                // the winner among the wavefronts' candidates (position gj is one of the
-                // active slots, so a candidate exists)
-                unsigned gm = 0u;
-                int gp = NONE;
-#pragma unroll
-                for (int q = 0; q < NWV; ++q) {
-                    const unsigned m = smag[buf][q];
-                    const int p = spos[buf][q];
-                    if (m > gm || (m == gm && p < gp)) {
-                        gm = m;
-                        gp = p;
-                        gw = q;
-                    }
-                }
-                ok = __uint_as_float(gm) > 0.0f;
-                pr = ok ? gp : gj;
-            } else {
-                // the diagonal row (slot 0 of thread j, never moved) is the pivot row
-                if (tid == j) {
+            for (int r = 0; r < RT; ++r)
+                if (r == rw && lane == wl) {
 #pragma unroll
                     for (int c = 0; c < W; ++c)
-                        if (c >= j) crow[buf][0][c] = a[0][c];
+                        if (c >= j) crow[buf][wid][c] = a[r][c];
                 }
-                __syncthreads();
-                const float d = crow[buf][0][j];
-                ok = fabsf(d) > 0.0f && fabsf(d) <= 3.402823466e38f;
-                pr = gj;
+            if (lane == 0) {
+                smag[buf][wid] = wmag;
+                spos[buf][wid] = wpos;
             }
+            __syncthreads();
+            // the winner among the wavefronts' candidates (position gj is one of the
+            // active slots, so a candidate exists)
+            unsigned gm = 0u;
+            int gp = NONE, gw = 0;
+#pragma unroll
+            for (int q = 0; q < NWV; ++q) {
+                const unsigned m = smag[buf][q];
+                const int p = spos[buf][q];
+                if (m > gm || (m == gm && p < gp)) {
+                    gm = m;
+                    gp = p;
+                    gw = q;
+                }
+            }
+            const bool ok = __uint_as_float(gm) > 0.0f;
+            const int pr = ok ? gp : gj;
             if (tid == 0) {
                 if (!ok && j < w && sinfo == 0) sinfo = gj + 1;
                 pivs[j] = pr;
             }
             // interchange of rows gj and pr: swap the two positions
-            if constexpr (PIV) {
 #pragma unroll
-                for (int r = 0; r < RT; ++r) pos[r] = pos[r] == pr ? gj : (pos[r] == gj ? pr : pos[r]);
-            }
+            for (int r = 0; r < RT; ++r) pos[r] = pos[r] == pr ? gj : (pos[r] == gj ? pr : pos[r]);
             // One branch-free pass (a branch here would make the compiler copy the whole
             // panel at the join): the active rows are scaled and updated with the pivot
             // row held in registers; inactive slots, and every slot when the column is
@@ -332,15 +311,14 @@ __global__ __launch_bounds__(NT) void panel_reg_kernel(int N, float *LU, int k0,
             bslot = 0;
 #pragma unroll
             for (int r = 0; r < RT; ++r) {
-                // without interchanges the rows at or above gj are slot 0 of threads 0..j
-                const bool act = PIV ? pos[r] > gj : (r > 0 || tid > j);
+                const bool act = pos[r] > gj;
                 const float lr = a[r][j] * inv;
                 const float l = act ? lr : 0.0f;
                 a[r][j] = act ? lr : a[r][j];
 #pragma unroll
                 for (int c = 0; c < W; ++c)
                     if (c > j) a[r][c] -= l * pv[c];
-                if (PIV && j + 1 < W) {
+                if (j + 1 < W) {
                     const float m = fabsf(a[r][j + 1]);
                     const bool take = act & ((m > best) | ((m == best) & (pos[r] < bpos)));
                     best = take ? m : best;
@@ -386,13 +364,11 @@ __global__ void laswp_kernel(int N, float *LU, int k0, int w, const int *piv)
 }
 
 // For the narrow panel at k0 (w <= 64 columns), on the block columns
-// [cb, ce) outside the panel: apply the panel's row interchanges (unless
-// swaps is 0: a factorisation without pivoting), then for the
+// [cb, ce) outside the panel: apply the panel's row interchanges, then for the
 // columns right of the panel solve U12 = L11^{-1} A12.  One wavefront per
 // column: lane 0 applies the interchanges in order, the workgroup barrier makes
 // them visible, then lane r holds row k0 + r for the solve.
-__global__ __launch_bounds__(256) void swap_trsm_kernel(int N, float *LU, int k0, int w, const int *piv, int cb, int ce,
-                                                        int swaps)
+__global__ __launch_bounds__(256) void swap_trsm_kernel(int N, float *LU, int k0, int w, const int *piv, int cb, int ce)
 {
     __shared__ float L[NB][NB + 1];
     const int tid = threadIdx.x;
@@ -405,7 +381,7 @@ __global__ __launch_bounds__(256) void swap_trsm_kernel(int N, float *LU, int k0
     if (col >= k0) col += w;
     const bool valid = col < ce;
     float *cp = LU + int64_t(valid ? col : 0) * N;
-    if (swaps && valid && lane == 0) {
+    if (valid && lane == 0) {
         for (int j = k0; j < k0 + w; ++j) {
             const int pr = piv[j];
             if (pr != j) {
@@ -1075,26 +1051,25 @@ __global__ __launch_bounds__(256) void asym_kernel(int N, const InT *A, int64_t 
 // [K0, KE): the shape (rows per thread, width, threads) is the fastest per
 // column for that height (measured), the width shrinking as the rows per thread
 // grow.  Returns the width used.
-template <bool PIV>
 int launch_panel(int N, float *LU, int k0, int KE, int *piv, int *info, hipStream_t s)
 {
     const int m = N - k0;
     int w;
     if (m <= 1024) {
         w = std::min(32, KE - k0);
-        hipLaunchKernelGGL((panel_reg_kernel<4, 32, 256, PIV>), dim3(1), dim3(256), 0, s, N, LU, k0, w, piv, info);
+        hipLaunchKernelGGL((panel_reg_kernel<4, 32, 256>), dim3(1), dim3(256), 0, s, N, LU, k0, w, piv, info);
     } else if (m <= 2048) {
         w = std::min(16, KE - k0);
-        hipLaunchKernelGGL((panel_reg_kernel<4, 16, 512, PIV>), dim3(1), dim3(512), 0, s, N, LU, k0, w, piv, info);
+        hipLaunchKernelGGL((panel_reg_kernel<4, 16, 512>), dim3(1), dim3(512), 0, s, N, LU, k0, w, piv, info);
     } else if (m <= 4096) {
         w = std::min(8, KE - k0);
-        hipLaunchKernelGGL((panel_reg_kernel<8, 8, 512, PIV>), dim3(1), dim3(512), 0, s, N, LU, k0, w, piv, info);
+        hipLaunchKernelGGL((panel_reg_kernel<8, 8, 512>), dim3(1), dim3(512), 0, s, N, LU, k0, w, piv, info);
     } else if (m <= 8192) {
         w = std::min(8, KE - k0);
-        hipLaunchKernelGGL((panel_reg_kernel<8, 8, 1024, PIV>), dim3(1), dim3(1024), 0, s, N, LU, k0, w, piv, info);
+        hipLaunchKernelGGL((panel_reg_kernel<8, 8, 1024>), dim3(1), dim3(1024), 0, s, N, LU, k0, w, piv, info);
     } else {
         w = std::min(4, KE - k0);
-        hipLaunchKernelGGL((panel_reg_kernel<16, 4, 1024, PIV>), dim3(1), dim3(1024), 0, s, N, LU, k0, w, piv, info);
+        hipLaunchKernelGGL((panel_reg_kernel<16, 4, 1024>), dim3(1), dim3(1024), 0, s, N, LU, k0, w, piv, info);
     }
     return w;
 }
@@ -1180,14 +1155,12 @@ hipError_t lu_factor_f32(int N, float *LU, int *piv, int *info, void *diag_inv, 
                 w = std::min(32, KE - k0);
                 hipLaunchKernelGGL(panel_kernel, dim3(1), dim3(1024), 0, s, N, LU, k0, w, piv, info);
             } else {
-                w = pivot ? launch_panel<true>(N, LU, k0, KE, piv, info, s) : launch_panel<false>(N, LU, k0, KE, piv, info, s);
+                w = launch_panel(N, LU, k0, KE, piv, info, s);
             }
             // the panel's interchanges on the other block columns, U12 right of it
-            // (without pivoting: only the columns right of it, for U12)
-            const int others = pivot ? KE - K0 - w : KE - k0 - w;
+            const int others = KE - K0 - w;
             if (others > 0)
-                hipLaunchKernelGGL(swap_trsm_kernel, dim3((others + 3) / 4), dim3(256), 0, s, N, LU, k0, w, piv,
-                                   pivot ? K0 : k0, KE, pivot ? 1 : 0);
+                hipLaunchKernelGGL(swap_trsm_kernel, dim3((others + 3) / 4), dim3(256), 0, s, N, LU, k0, w, piv, K0, KE);
             const int rin = KE - k0 - w;   // block columns right of the narrow panel
             if (rin > 0)
                 hipLaunchKernelGGL(gemm_update_kernel, dim3((N - k0 - w + 63) / 64, (rin + 63) / 64), dim3(256), 0, s,
@@ -1197,7 +1170,7 @@ hipError_t lu_factor_f32(int N, float *LU, int *piv, int *info, void *diag_inv, 
             k0 += w;
         }
         // the block's interchanges on the columns outside it (left: L of earlier blocks; right: A12, A22)
-        if (pivot && N - (KE - K0) > 0)
+        if (N - (KE - K0) > 0)
             hipLaunchKernelGGL(laswp_kernel, dim3((N - (KE - K0) + 255) / 256), dim3(256), 0, s, N, LU, K0, KE - K0, piv);
         const int rest = N - KE;
         if (rest > 0) {
