@@ -751,23 +751,25 @@ __global__ __launch_bounds__(128) void diag64_kernel(int N, float *LU, int K0, i
     }
     __syncthreads();
     float x[64];
+    // (each sum in four interleaved partial sums: four short dependent chains
+    // instead of one long one, on a wavefront that has its SIMD to itself)
     if (wave == 0) {
         // inv(L), column lane: x_r = delta_{r,lane} - sum_{k<r} L_rk x_k
 #pragma unroll
         for (int r = 0; r < 64; ++r) {
-            float sum = r == lane ? 1.0f : 0.0f;
+            float p4[4] = {r == lane ? 1.0f : 0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-            for (int k = 0; k < r; ++k) sum -= F[r][k] * x[k];
-            x[r] = sum;
+            for (int k = 0; k < r; ++k) p4[k & 3] -= F[r][k] * x[k];
+            x[r] = (p4[0] + p4[1]) + (p4[2] + p4[3]);
         }
     } else {
         // inv(U), column lane: x_r = (delta_{r,lane} - sum_{k>r} U_rk x_k) / U_rr
 #pragma unroll
         for (int r = 63; r >= 0; --r) {
-            float sum = r == lane ? 1.0f : 0.0f;
+            float p4[4] = {r == lane ? 1.0f : 0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-            for (int k = r + 1; k < 64; ++k) sum -= F[r][k] * x[k];
-            x[r] = sum / F[r][r];
+            for (int k = r + 1; k < 64; ++k) p4[k & 3] -= F[r][k] * x[k];
+            x[r] = ((p4[0] + p4[1]) + (p4[2] + p4[3])) / F[r][r];
         }
     }
     float *out = DI + (int64_t(K0 / 64) * 2 + wave) * 4096 + lane * 64;   // column lane, entries r
@@ -873,7 +875,8 @@ __global__ __launch_bounds__(64) void invert_diag_kernel(int N, const float *LU,
 // every workgroup), written to yout by workgroup 0; rows below are updated in
 // y (rows of the block itself are only read in this launch).  Both products
 // issue their 64 loads unconditionally (clamped addresses, the solved block
-// padded with zeros), so the loads are in flight together.
+// padded with zeros), so the loads are in flight together, and sum in four
+// interleaved partial sums (short dependent chains).
 __global__ __launch_bounds__(256) void trsv_lower_kernel(int N, const float *LU, const float *DI, float *y, float *yout, int b0)
 {
     __shared__ float yb[64], xb[64];
@@ -886,9 +889,10 @@ __global__ __launch_bounds__(256) void trsv_lower_kernel(int N, const float *LU,
         float d[64];
 #pragma unroll
         for (int k = 0; k < 64; ++k) d[k] = blk[k * 64];
-        float s = 0.0f;
+        float p4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int k = 0; k < 64; ++k) s += d[k] * yb[k];
+        for (int k = 0; k < 64; ++k) p4[k & 3] += d[k] * yb[k];
+        const float s = (p4[0] + p4[1]) + (p4[2] + p4[3]);
         xb[tid] = tid < bw ? s : 0.0f;
         if (blockIdx.x == 0 && tid < bw) yout[b0 + tid] = s;
     }
@@ -898,9 +902,10 @@ __global__ __launch_bounds__(256) void trsv_lower_kernel(int N, const float *LU,
     float v[64];
 #pragma unroll
     for (int k = 0; k < 64; ++k) v[k] = col[int64_t(min(k, bw - 1)) * N];
-    float s = 0.0f;
+    float p4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-    for (int k = 0; k < 64; ++k) s += v[k] * xb[k];
+    for (int k = 0; k < 64; ++k) p4[k & 3] += v[k] * xb[k];
+    const float s = (p4[0] + p4[1]) + (p4[2] + p4[3]);
     if (r < N) y[r] -= s;
 }
 
@@ -915,9 +920,10 @@ __global__ __launch_bounds__(256) void trsv_upper_kernel(int N, const float *LU,
         float d[64];
 #pragma unroll
         for (int k = 0; k < 64; ++k) d[k] = blk[k * 64];
-        float s = 0.0f;
+        float p4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int k = 0; k < 64; ++k) s += d[k] * yb[k];
+        for (int k = 0; k < 64; ++k) p4[k & 3] += d[k] * yb[k];
+        const float s = (p4[0] + p4[1]) + (p4[2] + p4[3]);
         xb[tid] = tid < bw ? s : 0.0f;
         if (blockIdx.x == 0 && tid < bw) yout[b0 + tid] = s;
     }
@@ -927,9 +933,10 @@ __global__ __launch_bounds__(256) void trsv_upper_kernel(int N, const float *LU,
     float v[64];
 #pragma unroll
     for (int k = 0; k < 64; ++k) v[k] = col[int64_t(min(k, bw - 1)) * N];
-    float s = 0.0f;
+    float p4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-    for (int k = 0; k < 64; ++k) s += v[k] * xb[k];
+    for (int k = 0; k < 64; ++k) p4[k & 3] += v[k] * xb[k];
+    const float s = (p4[0] + p4[1]) + (p4[2] + p4[3]);
     if (r < b0) y[r] -= s;
 }
 
