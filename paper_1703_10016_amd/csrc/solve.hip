@@ -1,7 +1,12 @@
 // Mixed-precision solve of the Galerkin system A alpha = beta (eq. sistlin):
-// FP32 LU with partial pivoting (blocked right-looking; panel on one
-// workgroup, trailing update on FP32 MFMA), FP64 iterative refinement with the
-// stored matrix.  The factor is kept column-major in the workspace.
+// FP32 LU, FP64 iterative refinement with the stored matrix.  An exactly
+// symmetric A (the Galerkin matrix) is first factored without row
+// interchanges (blocked right-looking: diagonal block on one workgroup, the
+// blocks below and right of it by triangular solves or products with its
+// inverses, trailing update on FP32 MFMA) and that factor is kept only if the
+// refinement converges; otherwise, and for any other A, LU with partial
+// pivoting (register panels on one workgroup, the same MFMA update).  The
+// factor is kept column-major in the workspace.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -1104,15 +1109,16 @@ void trailing_update(int N, float *LU, int KE, int K0, int bk, hipStream_t s)
 
 hipError_t lu_factor_f32(int N, float *LU, int *piv, int *info, void *diag_inv, bool pivot, hipStream_t s)
 {
-    // Two levels: blocks of BK columns, each factored by narrow register panels
-    // whose triangular solves and updates stay inside the block; then one
-    // triangular solve for the block's U12 and one rank-BK update of the
-    // trailing matrix (the MFMA-bound part).  Row interchanges always go to
-    // the full rows.  Up to N = 4096 one block spans the matrix (every narrow
-    // panel updates the whole trailing matrix): there the launches saved
-    // outweigh the traffic of the narrow updates (measured).  Without pivoting
-    // (pivot false, N <= 16384) the panels take the diagonal as pivot and no
-    // interchange is applied anywhere.
+    // Without pivoting (pivot false, N <= 16384): blocked LU in 64-column
+    // blocks up to N = 4096 (given diag_inv), 128-column blocks beyond (half
+    // the trailing matrix's traffic), the diagonal as pivot and no interchange
+    // anywhere.  With partial pivoting, two levels: blocks of BK columns, each
+    // factored by narrow register panels whose triangular solves and updates
+    // stay inside the block; then one triangular solve for the block's U12 and
+    // one rank-BK update of the trailing matrix (the MFMA-bound part).  Row
+    // interchanges always go to the full rows.  Up to N = 4096 one block spans
+    // the matrix (every narrow panel updates the whole trailing matrix): there
+    // the launches saved outweigh the traffic of the narrow updates (measured).
     if (!pivot && !lu_without_pivoting_supported(N)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(64), 0, s, info);
     if (!pivot && N <= 4096 && diag_inv) {
