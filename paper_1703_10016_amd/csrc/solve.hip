@@ -476,6 +476,19 @@ __global__ __launch_bounds__(256) void gemm_update_kernel(int N, float *LU, int 
     const int wave = tid >> 6, lane = tid & 63;
     const int wc = (wave >> 1) * 32;    // C columns of this wave
     const int wr = (wave & 1) * 32;     // C rows of this wave
+    // this lane's 16 entries of C, loaded before the K loop (clamped addresses)
+    // so that their HBM latency overlaps the multiplications
+    float cpre[2][2][4];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int c = n0 + wc + a * 16 + 4 * (lane >> 4) + i;
+                const int r = m0 + wr + b * 16 + (lane & 15);
+                cpre[a][b][i] = LU[int64_t(min(c, cend - 1)) * N + min(r, N - 1)];
+            }
     floatx4 acc[2][2];
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b) acc[a][b] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
@@ -521,7 +534,7 @@ __global__ __launch_bounds__(256) void gemm_update_kernel(int N, float *LU, int 
             for (int i = 0; i < 4; ++i) {
                 const int c = n0 + wc + a * 16 + 4 * (lane >> 4) + i;
                 const int r = m0 + wr + b * 16 + (lane & 15);
-                if (r < N && c < cend) LU[int64_t(c) * N + r] -= acc[a][b][i];
+                if (r < N && c < cend) LU[int64_t(c) * N + r] = cpre[a][b][i] - acc[a][b][i];
             }
 }
 
