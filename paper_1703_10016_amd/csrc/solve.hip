@@ -29,6 +29,7 @@ struct WS {
     float *v, *v2;
     double *red;     // reduction outputs
     float *DI;       // inverted diagonal blocks
+    float *DI2;      // off-diagonal blocks of the inverses of pairs of diagonal blocks
 };
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
@@ -54,6 +55,8 @@ WS carve(void *base, int N)
     w.red = reinterpret_cast<double *>(p);
     p += align_up(64 * sizeof(double)) + align_up(size_t(N) * sizeof(double));
     w.DI = reinterpret_cast<float *>(p);
+    p += align_up(size_t(N + 63) / 64 * 2 * 4096 * sizeof(float));
+    w.DI2 = reinterpret_cast<float *>(p);
     return w;
 }
 
@@ -958,6 +961,154 @@ __global__ __launch_bounds__(256) void trsv_upper_kernel(int N, const float *LU,
     if (r < b0) y[r] -= s;
 }
 
+// Pairs of 64-row blocks for the triangular solves: with the inverses A^-1,
+// B^-1 of two consecutive diagonal blocks, the inverse of the 128 x 128 block
+// they form has one more 64 x 64 block,
+//   unit lower  [[A, 0], [C, B]]:  -B^-1 C A^-1 (bottom left),
+//   upper       [[A, D], [0, B]]:  -A^-1 D B^-1 (top right),
+// which pair_inverse_kernel forms (two 64 x 64 x 64 products, one workgroup
+// per pair and triangle) into DI2[pair][0 / 1], column-major like DI.  Rows
+// past N (a partial last block) take no part: C and D are zero there.
+__global__ __launch_bounds__(256) void pair_inverse_kernel(int N, const float *LU, const float *DI, float *DI2)
+{
+    __shared__ float M[64][65], V[64][65], T[64][65];
+    const int tid = threadIdx.x, pr = blockIdx.x >> 1, up = blockIdx.x & 1;
+    const int b0 = 128 * pr;
+    const float *iA = DI + (int64_t(2 * pr) * 2 + up) * 4096;       // inverse of block 2 pr
+    const float *iB = DI + (int64_t(2 * pr + 1) * 2 + up) * 4096;   // inverse of block 2 pr + 1
+    // M = C (lower: rows of block B, columns of block A) or D (upper: rows of A, columns of B)
+    float v[16];
+#pragma unroll
+    for (int it = 0; it < 16; ++it) {
+        const int e = tid + it * 256, i = e & 63, k = e >> 6;
+        const int row = up ? b0 + i : b0 + 64 + i, col = up ? b0 + 64 + k : b0 + k;
+        v[it] = LU[int64_t(min(col, N - 1)) * N + min(row, N - 1)] * ((row < N && col < N) ? 1.0f : 0.0f);
+    }
+#pragma unroll
+    for (int it = 0; it < 16; ++it) {
+        const int e = tid + it * 256;
+        M[e & 63][e >> 6] = v[it];
+    }
+    // first product with the inverse on M's right (lower: A^-1) or left... done as
+    // lower: T = M iA, X = -iB T;  upper: T = M iB, Y = -iA T
+    const float *right = up ? iB : iA, *left = up ? iA : iB;
+#pragma unroll
+    for (int it = 0; it < 16; ++it) {
+        const int e = tid + it * 256;
+        V[e & 63][e >> 6] = right[e];                                // entry (e % 64, e / 64)
+    }
+    __syncthreads();
+    const int i = tid & 63, j0 = (tid >> 6) * 16;
+    float y[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) y[q] = 0.0f;
+#pragma unroll 8
+    for (int k = 0; k < 64; ++k) {
+        const float mk = M[i][k];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) y[q] += mk * V[k][j0 + q];
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) T[i][j0 + q] = y[q];
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < 16; ++it) {
+        const int e = tid + it * 256;
+        V[e & 63][e >> 6] = left[e];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) y[q] = 0.0f;
+#pragma unroll 8
+    for (int k = 0; k < 64; ++k) {
+        const float vk = V[i][k];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) y[q] += vk * T[k][j0 + q];
+    }
+    float *out = DI2 + (int64_t(pr) * 2 + up) * 4096;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) out[(j0 + q) * 64 + i] = -y[q];    // entry (i, j0 + q), column-major
+}
+
+// Forward step for the 128 rows of pair pr: x_A = A^-1 y_A, x_B = X y_A + B^-1 y_B
+// (every workgroup; workgroup 0 writes them to yout), then the rows below take
+// the pair's 128 columns of L.  Loads unconditional, sums in partial sums.
+__global__ __launch_bounds__(256) void trsv_lower2_kernel(int N, const float *LU, const float *DI, const float *DI2,
+                                                          float *y, float *yout, int pr)
+{
+    __shared__ float yb[128], xb[128];
+    const int b0 = 128 * pr, bw = min(128, N - b0);
+    const int tid = threadIdx.x;
+    if (tid < 128) yb[tid] = tid < bw ? y[b0 + tid] : 0.0f;
+    __syncthreads();
+    if (tid < 128) {
+        const int blk = tid < 64 ? 2 * pr : 2 * pr + 1, r = tid & 63;
+        const float *inv = DI + (int64_t(blk) * 2 + 0) * 4096 + r;
+        const float *x2 = DI2 + (int64_t(pr) * 2 + 0) * 4096 + r;
+        float d[64], e2[64];
+#pragma unroll
+        for (int k = 0; k < 64; ++k) d[k] = inv[k * 64];
+#pragma unroll
+        for (int k = 0; k < 64; ++k) e2[k] = x2[k * 64] * (tid < 64 ? 0.0f : 1.0f);   // unconditional loads
+        float p4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        const int off = tid < 64 ? 0 : 64;
+#pragma unroll
+        for (int k = 0; k < 64; ++k) p4[k & 3] += d[k] * yb[off + k] + e2[k] * yb[k];
+        const float s = (p4[0] + p4[1]) + (p4[2] + p4[3]);
+        xb[tid] = tid < bw ? s : 0.0f;
+        if (blockIdx.x == 0 && tid < bw) yout[b0 + tid] = s;
+    }
+    __syncthreads();
+    const int r = b0 + bw + blockIdx.x * blockDim.x + tid;
+    const float *col = LU + int64_t(b0) * N + min(r, N - 1);
+    float v[128];
+#pragma unroll
+    for (int k = 0; k < 128; ++k) v[k] = col[int64_t(min(k, bw - 1)) * N];
+    float p4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int k = 0; k < 128; ++k) p4[k & 3] += v[k] * xb[k];
+    if (r < N) y[r] -= (p4[0] + p4[1]) + (p4[2] + p4[3]);
+}
+
+// Backward step for the 128 rows of pair pr: x_B = B^-1 y_B, x_A = A^-1 y_A + Y y_B,
+// then the rows above take the pair's 128 columns of U.
+__global__ __launch_bounds__(256) void trsv_upper2_kernel(int N, const float *LU, const float *DI, const float *DI2,
+                                                          float *y, float *yout, int pr)
+{
+    __shared__ float yb[128], xb[128];
+    const int b0 = 128 * pr, bw = min(128, N - b0);
+    const int tid = threadIdx.x;
+    if (tid < 128) yb[tid] = tid < bw ? y[b0 + tid] : 0.0f;
+    __syncthreads();
+    if (tid < 128) {
+        const int blk = tid < 64 ? 2 * pr : 2 * pr + 1, r = tid & 63;
+        const float *inv = DI + (int64_t(blk) * 2 + 1) * 4096 + r;
+        const float *x2 = DI2 + (int64_t(pr) * 2 + 1) * 4096 + r;
+        float d[64], e2[64];
+#pragma unroll
+        for (int k = 0; k < 64; ++k) d[k] = inv[k * 64];
+#pragma unroll
+        for (int k = 0; k < 64; ++k) e2[k] = x2[k * 64] * (tid < 64 ? 1.0f : 0.0f);   // unconditional loads
+        float p4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        const int off = tid < 64 ? 0 : 64;
+#pragma unroll
+        for (int k = 0; k < 64; ++k) p4[k & 3] += d[k] * yb[off + k] + e2[k] * yb[64 + k];
+        const float s = (p4[0] + p4[1]) + (p4[2] + p4[3]);
+        xb[tid] = tid < bw ? s : 0.0f;
+        if (blockIdx.x == 0 && tid < bw) yout[b0 + tid] = s;
+    }
+    __syncthreads();
+    const int r = blockIdx.x * blockDim.x + tid;
+    const float *col = LU + int64_t(b0) * N + min(r, max(b0 - 1, 0));
+    float v[128];
+#pragma unroll
+    for (int k = 0; k < 128; ++k) v[k] = col[int64_t(min(k, bw - 1)) * N];
+    float p4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int k = 0; k < 128; ++k) p4[k & 3] += v[k] * xb[k];
+    if (r < b0) y[r] -= (p4[0] + p4[1]) + (p4[2] + p4[3]);
+}
+
 __global__ void permute_kernel(int N, const int *perm, const double *src, float *dst)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1106,7 +1257,8 @@ size_t solve_workspace_bytes(int N)
     const size_t nblk = size_t(N + 63) / 64;
     return align_up(size_t(N) * N * sizeof(float)) + 2 * align_up(size_t(N) * sizeof(int)) + align_up(16) +
            align_up(size_t(N) * sizeof(double)) + 2 * align_up(size_t(N) * sizeof(float)) + align_up(64 * sizeof(double)) +
-           align_up(size_t(N) * sizeof(double)) + align_up(nblk * 2 * 4096 * sizeof(float));
+           align_up(size_t(N) * sizeof(double)) + align_up(nblk * 2 * 4096 * sizeof(float)) +
+           align_up(std::max<size_t>(nblk / 2, 1) * 2 * 4096 * sizeof(float));
 }
 
 bool lu_without_pivoting_supported(int N) { return N <= 16384; }
@@ -1210,21 +1362,31 @@ hipError_t lu_factor_f32(int N, float *LU, int *piv, int *info, void *diag_inv, 
     return hipGetLastError();
 }
 
-hipError_t lu_solve_f32(int N, const float *LU, const float *diag_inv, float *b, float *tmp, hipStream_t s)
+hipError_t lu_solve_f32(int N, const float *LU, const float *diag_inv, const float *pair_inv, float *b, float *tmp,
+                        hipStream_t s)
 {
     // b is already permuted (b := P b).
-    // forward: b is updated below each block, solved blocks go to tmp;
-    // backward: tmp is updated above each block, solved blocks go to b.
-    for (int b0 = 0; b0 < N; b0 += 64) {
-        const int rest = std::max(0, N - b0 - 64);
-        hipLaunchKernelGGL(trsv_lower_kernel, dim3(std::max(1, (rest + 255) / 256)), dim3(256), 0, s, N, LU, diag_inv,
-                           b, tmp, b0);
+    // forward: b is updated below each step, solved blocks go to tmp;
+    // backward: tmp is updated above each step, solved blocks go to b.
+    // One launch per pair of 64-row blocks (pair_inv: the off-diagonal blocks of
+    // the pairs' inverses), one more for an odd last block.
+    const int nblk = (N + 63) / 64, npair = nblk / 2;
+    for (int pr = 0; pr < npair; ++pr) {
+        const int rest = std::max(0, N - 128 * pr - 128);
+        hipLaunchKernelGGL(trsv_lower2_kernel, dim3(std::max(1, (rest + 255) / 256)), dim3(256), 0, s, N, LU, diag_inv,
+                           pair_inv, b, tmp, pr);
     }
-    const int nblk = (N + 63) / 64;
-    for (int bk = nblk - 1; bk >= 0; --bk) {
-        const int b0 = bk * 64, bw = std::min(64, N - b0);
+    if (nblk & 1)
+        hipLaunchKernelGGL(trsv_lower_kernel, dim3(1), dim3(256), 0, s, N, LU, diag_inv, b, tmp, (nblk - 1) * 64);
+    if (nblk & 1) {
+        const int b0 = (nblk - 1) * 64;
         hipLaunchKernelGGL(trsv_upper_kernel, dim3(std::max(1, (b0 + 255) / 256)), dim3(256), 0, s, N, LU, diag_inv,
-                           tmp, b, b0, bw);
+                           tmp, b, b0, N - b0);
+    }
+    for (int pr = npair - 1; pr >= 0; --pr) {
+        const int b0 = 128 * pr;
+        hipLaunchKernelGGL(trsv_upper2_kernel, dim3(std::max(1, (b0 + 255) / 256)), dim3(256), 0, s, N, LU, diag_inv,
+                           pair_inv, tmp, b, pr);
     }
     return hipGetLastError();
 }
@@ -1268,6 +1430,8 @@ int mixed_solve(int N, const void *d_A, int64_t lda, int a_prec, const double *d
             hipLaunchKernelGGL(to_colmajor_kernel<float>, tg, dim3(256), 0, s, N, static_cast<const float *>(d_A), lda, w.LU);
         if ((e = lu_factor_f32(N, w.LU, w.piv, w.info, w.DI, pivot, s)) != hipSuccess)
             return fail(-5, "LU factorisation launch", e);
+        if ((N + 63) / 64 >= 2)     // at least one pair of diagonal blocks
+            hipLaunchKernelGGL(pair_inverse_kernel, dim3(2 * ((N + 63) / 64 / 2)), dim3(256), 0, s, N, w.LU, w.DI, w.DI2);
         // the permutation from the interchange sequence (host, O(N)); none without pivoting
         std::vector<int> piv(N), perm(N);
         int info = 0;
@@ -1295,7 +1459,7 @@ int mixed_solve(int N, const void *d_A, int64_t lda, int a_prec, const double *d
         double red[4];
         // x0 = LU \ beta
         hipLaunchKernelGGL(permute_kernel, dim3((N + 255) / 256), dim3(256), 0, s, N, w.perm, d_beta, w.v);
-        (void)lu_solve_f32(N, w.LU, w.DI, w.v, w.v2, s);
+        (void)lu_solve_f32(N, w.LU, w.DI, w.DI2, w.v, w.v2, s);
         hipLaunchKernelGGL(update_norms_kernel, dim3(1), dim3(1024), 0, s, N, d_x, w.v, d_beta, d_beta, 0, w.red);
         res.iters = 0;
         res.rel_update = 1.0;
@@ -1312,7 +1476,7 @@ int mixed_solve(int N, const void *d_A, int64_t lda, int a_prec, const double *d
         for (int it = 0; it < max_iter; ++it) {
             residual();
             hipLaunchKernelGGL(permute_kernel, dim3((N + 255) / 256), dim3(256), 0, s, N, w.perm, w.r, w.v);
-            (void)lu_solve_f32(N, w.LU, w.DI, w.v, w.v2, s);
+            (void)lu_solve_f32(N, w.LU, w.DI, w.DI2, w.v, w.v2, s);
             hipLaunchKernelGGL(update_norms_kernel, dim3(1), dim3(1024), 0, s, N, d_x, w.v, w.r, d_beta, 1, w.red);
             if ((e = hipMemcpyAsync(red, w.red, sizeof red, hipMemcpyDeviceToHost, s)) != hipSuccess ||
                 (e = hipStreamSynchronize(s)) != hipSuccess)

@@ -30,6 +30,9 @@ int mixed_solve(int N, const void *d_A, int64_t lda, int a_prec, const double *d
 bool lu_without_pivoting_supported(int N);
 hipError_t lu_factor_f32(int N, float *LU, int *piv, int *info, void *diag_inv, bool pivot, hipStream_t s);
 // b := U^{-1} L^{-1} b for an already permuted b (tmp: N floats of scratch).
-hipError_t lu_solve_f32(int N, const float *LU, const float *diag_inv, float *b, float *tmp, hipStream_t s);
+// pair_inv: the off-diagonal 64 x 64 blocks of the inverses of pairs of diagonal
+// blocks (formed after the factorisation whenever N > 64).
+hipError_t lu_solve_f32(int N, const float *LU, const float *diag_inv, const float *pair_inv, float *b, float *tmp,
+                        hipStream_t s);
 
 }  // namespace sgbem
