@@ -76,6 +76,7 @@ def test_collocation_rhs_and_solve_converge_to_the_exact_density(ctx):
         assert np.abs(b.cpu().numpy() - collocation.rhs(synth.circle(r), p, N, 1, g)).max() < 1e-14
         A = ctx.assemble_collocation(synth.circle(r), p, N)
         x, info = ctx.solve(A, b, tol=1e-13)
+        assert info.pivoted == 1          # not symmetric: partial pivoting from the start
         a = x.cpu().numpy()
         ph = sum(a[j] * bspline.periodic(p, N, j, ts) for j in range(N))
         errs.append(np.abs(ph - exact).max() / np.abs(exact).max())

@@ -212,15 +212,18 @@ def test_mixed_solve_matches_fp64_solve(ctx, N, prec, sym):
         assert info.pivoted == 1
 
 
-def test_positive_definite_solve_without_interchanges(ctx):
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_positive_definite_solve_without_interchanges(ctx, prec):
     """The ellipse (capacity 0.75 < 1: positive definite Galerkin matrix, the
-    paper's setting): factored without interchanges, same solution."""
+    paper's setting), assembled in either precision (exactly symmetric: the
+    lower triangle mirrors the upper): factored without interchanges, same
+    solution."""
     c = synth.config_ellipse()
-    A = ctx.assemble(c.curve, c.p, c.N, "wq")
+    A = ctx.assemble(c.curve, c.p, c.N, "wq", precision=prec)
     beta = ctx.rhs(c.curve, c.p, c.N, c.g)
     x, info = ctx.solve(A, beta, tol=1e-12)
     assert info.pivoted == 0
-    ref = np.linalg.solve(A.cpu().numpy(), beta.cpu().numpy())
+    ref = np.linalg.solve(A.cpu().numpy().astype(np.float64), beta.cpu().numpy())
     assert np.linalg.norm(x.cpu().numpy() - ref) / np.linalg.norm(ref) < 1e-10
 
 
