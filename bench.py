@@ -42,7 +42,7 @@ sys.path.insert(0, ROOT)
 PEAK_FP64 = 78.6e12          # MI355X FP64 vector, FLOP/s
 PEAK_FP32 = 157.3e12         # MI355X FP32, vector and dense MFMA alike, FLOP/s
 PEAK_HBM = 8.0e12            # bytes/s
-FLOPS_PER_LOG = 20           # cost model of one logarithm
+FLOPS_PER_LOG = 20           # cost model of one FP64 logarithm (the table-free series: ~20 FP64 operations)
 DL_FLOPS_PER_EVAL = 11       # double-layer kernel value: 2 differences, numerator and denominator (3 each), 1 division, 1 multiply-add
 
 
@@ -180,8 +180,9 @@ def main():
                          "(the copy calibrates the byte counters of a profiler run)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(the row-block sharding is described in DESIGN.md).", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: there is no multi-GPU path (the matrix would be "
+              "sharded by row blocks of tiles, each GPU assembling and factoring its own rows).",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
