@@ -46,7 +46,7 @@ typedef enum {
     SGBEM_E_SINGULAR = -3,     /* zero pivot in the LU factorisation                   */
     SGBEM_E_NOCONV = -4,       /* iterative refinement did not reach the tolerance     */
     SGBEM_E_DEVICE = -5,       /* a HIP runtime call failed                            */
-    SGBEM_E_UNSUPPORTED = -6   /* valid request outside what this build implements     */
+    SGBEM_E_UNSUPPORTED = -6   /* valid request with no kernel compiled for its shape    */
 } sgbem_status;
 
 typedef struct sgbem_ctx_s *sgbem_ctx;       /* one device + one HIP stream             */
