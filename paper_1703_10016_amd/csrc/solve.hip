@@ -1432,19 +1432,19 @@ int mixed_solve(int N, const void *d_A, int64_t lda, int a_prec, const double *d
             return fail(-5, "LU factorisation launch", e);
         if ((N + 63) / 64 >= 2)     // at least one pair of diagonal blocks
             hipLaunchKernelGGL(pair_inverse_kernel, dim3(2 * ((N + 63) / 64 / 2)), dim3(256), 0, s, N, w.LU, w.DI, w.DI2);
-        // the permutation from the interchange sequence (host, O(N)); none without pivoting
+        // the permutation from the interchange sequence (host, O(N)); none without
+        // pivoting, and then no wait here either: the zero-pivot flag is read with
+        // the first synchronisation the refinement makes anyway
         std::vector<int> piv(N), perm(N);
         int info = 0;
-        if ((pivot && (e = hipMemcpyAsync(piv.data(), w.piv, N * sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess) ||
-            (e = hipMemcpyAsync(&info, w.info, sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess ||
-            (e = hipStreamSynchronize(s)) != hipSuccess)
-            return fail(-5, "LU factorisation", e);
-        if (info != 0) {
-            if (!pivot) {
-                pivot = true;
-                continue;
-            }
-            return fail(-3, "zero pivot in the FP32 LU factorisation", hipSuccess);
+        bool info_read = false;
+        if (pivot) {
+            if ((e = hipMemcpyAsync(piv.data(), w.piv, N * sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+                (e = hipMemcpyAsync(&info, w.info, sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+                (e = hipStreamSynchronize(s)) != hipSuccess)
+                return fail(-5, "LU factorisation", e);
+            if (info != 0) return fail(-3, "zero pivot in the FP32 LU factorisation", hipSuccess);
+            info_read = true;
         }
         for (int i = 0; i < N; ++i) perm[i] = i;
         if (pivot)
@@ -1472,15 +1472,23 @@ int mixed_solve(int N, const void *d_A, int64_t lda, int a_prec, const double *d
         // cond(A) eps floor) with a backward error at the FP64 level.  Without
         // pivoting, corrections that stop shrinking above that level end the
         // attempt.
-        bool stalled = false;
+        bool stalled = false, zero_pivot = false;
         for (int it = 0; it < max_iter; ++it) {
             residual();
             hipLaunchKernelGGL(permute_kernel, dim3((N + 255) / 256), dim3(256), 0, s, N, w.perm, w.r, w.v);
             (void)lu_solve_f32(N, w.LU, w.DI, w.DI2, w.v, w.v2, s);
             hipLaunchKernelGGL(update_norms_kernel, dim3(1), dim3(1024), 0, s, N, d_x, w.v, w.r, d_beta, 1, w.red);
             if ((e = hipMemcpyAsync(red, w.red, sizeof red, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+                (!info_read && (e = hipMemcpyAsync(&info, w.info, sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess) ||
                 (e = hipStreamSynchronize(s)) != hipSuccess)
                 return fail(-5, "refinement step", e);
+            if (!info_read) {
+                info_read = true;
+                if (info != 0) {      // zero pivot without interchanges: this attempt is void
+                    zero_pivot = true;
+                    break;
+                }
+            }
             res.iters = it + 1;
             res.rel_update = red[1] > 0 ? red[0] / red[1] : 0.0;
             res.backward_err = red[2] / (normA * red[1] + red[3]);   // of the iterate before this step
@@ -1504,7 +1512,13 @@ int mixed_solve(int N, const void *d_A, int64_t lda, int a_prec, const double *d
             }
             prev = res.rel_update;
         }
-        if (status != 0 && !pivot && (stalled || max_iter > 0)) {
+        if (!info_read) {             // no refinement step ran: read the flag now
+            if ((e = hipMemcpyAsync(&info, w.info, sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+                (e = hipStreamSynchronize(s)) != hipSuccess)
+                return fail(-5, "LU factorisation", e);
+            zero_pivot = info != 0;
+        }
+        if (zero_pivot || (status != 0 && !pivot && (stalled || max_iter > 0))) {
             pivot = true;
             continue;
         }
