@@ -1032,81 +1032,96 @@ __global__ __launch_bounds__(256) void pair_inverse_kernel(int N, const float *L
 
 // Forward step for the 128 rows of pair pr: x_A = A^-1 y_A, x_B = X y_A + B^-1 y_B
 // (every workgroup; workgroup 0 writes them to yout), then the rows below take
-// the pair's 128 columns of L.  Loads unconditional, sums in partial sums.
+// the pair's 128 columns of L.  A workgroup owns 64 rows and splits the 128
+// columns in four quarters, one per wave, whose sums meet in LDS in a fixed
+// order.  Every load (the wave's quarter of L, the pair's y and inverse blocks)
+// is issued before the first wait: y reaches the lanes by readlane, not through
+// LDS, so the only barrier is the one that hands x to the four waves.  Loads
+// unconditional, sums in partial sums.
 __global__ __launch_bounds__(256) void trsv_lower2_kernel(int N, const float *LU, const float *DI, const float *DI2,
                                                           float *y, float *yout, int pr)
 {
-    __shared__ float yb[128], xb[128];
+    __shared__ float xb[128], part[4][64];
     const int b0 = 128 * pr, bw = min(128, N - b0);
-    const int tid = threadIdx.x;
-    if (tid < 128) yb[tid] = tid < bw ? y[b0 + tid] : 0.0f;
-    __syncthreads();
+    const int tid = threadIdx.x, lr = tid & 63, q = tid >> 6;
+    const int r = b0 + bw + blockIdx.x * 64 + lr;
+    const float *col = LU + int64_t(b0) * N + min(r, N - 1);
+    float v[32];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) v[k] = col[int64_t(min(q * 32 + k, bw - 1)) * N];
     if (tid < 128) {
-        const int blk = tid < 64 ? 2 * pr : 2 * pr + 1, r = tid & 63;
-        const float *inv = DI + (int64_t(blk) * 2 + 0) * 4096 + r;
-        const float *x2 = DI2 + (int64_t(pr) * 2 + 0) * 4096 + r;
+        // lane k of waves 0 and 1 holds y_A[k] and y_B[k]; readlane broadcasts them
+        const float yA = y[b0 + min(lr, bw - 1)] * (lr < bw ? 1.0f : 0.0f);
+        const float yB = y[b0 + min(64 + lr, bw - 1)] * (64 + lr < bw ? 1.0f : 0.0f);
+        const float ys = tid < 64 ? yA : yB;
+        const int blk = tid < 64 ? 2 * pr : 2 * pr + 1;
+        const float *inv = DI + (int64_t(blk) * 2 + 0) * 4096 + lr;
+        const float *x2 = DI2 + (int64_t(pr) * 2 + 0) * 4096 + lr;
         float d[64], e2[64];
 #pragma unroll
         for (int k = 0; k < 64; ++k) d[k] = inv[k * 64];
 #pragma unroll
         for (int k = 0; k < 64; ++k) e2[k] = x2[k * 64] * (tid < 64 ? 0.0f : 1.0f);   // unconditional loads
         float p4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-        const int off = tid < 64 ? 0 : 64;
 #pragma unroll
-        for (int k = 0; k < 64; ++k) p4[k & 3] += d[k] * yb[off + k] + e2[k] * yb[k];
+        for (int k = 0; k < 64; ++k)
+            p4[k & 3] += d[k] * __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ys), k)) +
+                         e2[k] * __int_as_float(__builtin_amdgcn_readlane(__float_as_int(yA), k));
         const float s = (p4[0] + p4[1]) + (p4[2] + p4[3]);
         xb[tid] = tid < bw ? s : 0.0f;
         if (blockIdx.x == 0 && tid < bw) yout[b0 + tid] = s;
     }
     __syncthreads();
-    const int r = b0 + bw + blockIdx.x * blockDim.x + tid;
-    const float *col = LU + int64_t(b0) * N + min(r, N - 1);
-    float v[128];
-#pragma unroll
-    for (int k = 0; k < 128; ++k) v[k] = col[int64_t(min(k, bw - 1)) * N];
     float p4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-    for (int k = 0; k < 128; ++k) p4[k & 3] += v[k] * xb[k];
-    if (r < N) y[r] -= (p4[0] + p4[1]) + (p4[2] + p4[3]);
+    for (int k = 0; k < 32; ++k) p4[k & 3] += v[k] * xb[q * 32 + k];
+    part[q][lr] = (p4[0] + p4[1]) + (p4[2] + p4[3]);
+    __syncthreads();
+    if (q == 0 && r < N) y[r] -= (part[0][lr] + part[1][lr]) + (part[2][lr] + part[3][lr]);
 }
 
 // Backward step for the 128 rows of pair pr: x_B = B^-1 y_B, x_A = A^-1 y_A + Y y_B,
-// then the rows above take the pair's 128 columns of U.
+// then the rows above take the pair's 128 columns of U (64 rows per workgroup,
+// column quarters per wave, as in the forward step).
 __global__ __launch_bounds__(256) void trsv_upper2_kernel(int N, const float *LU, const float *DI, const float *DI2,
                                                           float *y, float *yout, int pr)
 {
-    __shared__ float yb[128], xb[128];
+    __shared__ float xb[128], part[4][64];
     const int b0 = 128 * pr, bw = min(128, N - b0);
-    const int tid = threadIdx.x;
-    if (tid < 128) yb[tid] = tid < bw ? y[b0 + tid] : 0.0f;
-    __syncthreads();
+    const int tid = threadIdx.x, lr = tid & 63, q = tid >> 6;
+    const int r = blockIdx.x * 64 + lr;
+    const float *col = LU + int64_t(b0) * N + min(r, max(b0 - 1, 0));
+    float v[32];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) v[k] = col[int64_t(min(q * 32 + k, bw - 1)) * N];
     if (tid < 128) {
-        const int blk = tid < 64 ? 2 * pr : 2 * pr + 1, r = tid & 63;
-        const float *inv = DI + (int64_t(blk) * 2 + 1) * 4096 + r;
-        const float *x2 = DI2 + (int64_t(pr) * 2 + 1) * 4096 + r;
+        const float yA = y[b0 + min(lr, bw - 1)] * (lr < bw ? 1.0f : 0.0f);
+        const float yB = y[b0 + min(64 + lr, bw - 1)] * (64 + lr < bw ? 1.0f : 0.0f);
+        const float ys = tid < 64 ? yA : yB;
+        const int blk = tid < 64 ? 2 * pr : 2 * pr + 1;
+        const float *inv = DI + (int64_t(blk) * 2 + 1) * 4096 + lr;
+        const float *x2 = DI2 + (int64_t(pr) * 2 + 1) * 4096 + lr;
         float d[64], e2[64];
 #pragma unroll
         for (int k = 0; k < 64; ++k) d[k] = inv[k * 64];
 #pragma unroll
         for (int k = 0; k < 64; ++k) e2[k] = x2[k * 64] * (tid < 64 ? 1.0f : 0.0f);   // unconditional loads
         float p4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-        const int off = tid < 64 ? 0 : 64;
 #pragma unroll
-        for (int k = 0; k < 64; ++k) p4[k & 3] += d[k] * yb[off + k] + e2[k] * yb[64 + k];
+        for (int k = 0; k < 64; ++k)
+            p4[k & 3] += d[k] * __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ys), k)) +
+                         e2[k] * __int_as_float(__builtin_amdgcn_readlane(__float_as_int(yB), k));
         const float s = (p4[0] + p4[1]) + (p4[2] + p4[3]);
         xb[tid] = tid < bw ? s : 0.0f;
         if (blockIdx.x == 0 && tid < bw) yout[b0 + tid] = s;
     }
     __syncthreads();
-    const int r = blockIdx.x * blockDim.x + tid;
-    const float *col = LU + int64_t(b0) * N + min(r, max(b0 - 1, 0));
-    float v[128];
-#pragma unroll
-    for (int k = 0; k < 128; ++k) v[k] = col[int64_t(min(k, bw - 1)) * N];
     float p4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-    for (int k = 0; k < 128; ++k) p4[k & 3] += v[k] * xb[k];
-    if (r < b0) y[r] -= (p4[0] + p4[1]) + (p4[2] + p4[3]);
+    for (int k = 0; k < 32; ++k) p4[k & 3] += v[k] * xb[q * 32 + k];
+    part[q][lr] = (p4[0] + p4[1]) + (p4[2] + p4[3]);
+    __syncthreads();
+    if (q == 0 && r < b0) y[r] -= (part[0][lr] + part[1][lr]) + (part[2][lr] + part[3][lr]);
 }
 
 __global__ void permute_kernel(int N, const int *perm, const double *src, float *dst)
@@ -1373,7 +1388,7 @@ hipError_t lu_solve_f32(int N, const float *LU, const float *diag_inv, const flo
     const int nblk = (N + 63) / 64, npair = nblk / 2;
     for (int pr = 0; pr < npair; ++pr) {
         const int rest = std::max(0, N - 128 * pr - 128);
-        hipLaunchKernelGGL(trsv_lower2_kernel, dim3(std::max(1, (rest + 255) / 256)), dim3(256), 0, s, N, LU, diag_inv,
+        hipLaunchKernelGGL(trsv_lower2_kernel, dim3(std::max(1, (rest + 63) / 64)), dim3(256), 0, s, N, LU, diag_inv,
                            pair_inv, b, tmp, pr);
     }
     if (nblk & 1)
@@ -1385,7 +1400,7 @@ hipError_t lu_solve_f32(int N, const float *LU, const float *diag_inv, const flo
     }
     for (int pr = npair - 1; pr >= 0; --pr) {
         const int b0 = 128 * pr;
-        hipLaunchKernelGGL(trsv_upper2_kernel, dim3(std::max(1, (b0 + 255) / 256)), dim3(256), 0, s, N, LU, diag_inv,
+        hipLaunchKernelGGL(trsv_upper2_kernel, dim3(std::max(1, (b0 + 63) / 64)), dim3(256), 0, s, N, LU, diag_inv,
                            pair_inv, tmp, b, pr);
     }
     return hipGetLastError();
