@@ -831,32 +831,46 @@ __global__ __launch_bounds__(256) void panel_mul_kernel(int N, float *LU, int K0
         X[e & 63][e >> 6] = xv[it];
     }
     __syncthreads();
-    // thread: output row i = tid % 64 and 16 output columns from j0 = (tid / 64) * 16
-    const int i = tid & 63, j0 = (tid >> 6) * 16;
-    float y[16];
+    // Y = P Q (rows: P = X, Q = V; columns: P = V, Q = X) on v_mfma_f32_16x16x4_f32,
+    // a 32 x 32 block of Y per wavefront, with the operand layout of
+    // gemm_update_kernel: the first operand runs over Y's columns and the second
+    // over its rows, so 16 consecutive lanes hold 16 consecutive rows of a
+    // column of Y (one contiguous store).
+    const int wave = tid >> 6, lane = tid & 63;
+    const int wc = (wave >> 1) * 32, wr = (wave & 1) * 32;
+    float (*P)[65] = rows ? X : V;
+    float (*Q)[65] = rows ? V : X;
+    floatx4 acc[2][2];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) y[q] = 0.0f;
-#pragma unroll 8
-    for (int k = 0; k < 64; ++k) {
-        if (rows) {           // Y = X V: Y[i][j] = sum_k X[i][k] V[k][j]
-            const float xk = X[i][k];
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-            for (int q = 0; q < 16; ++q) y[q] += xk * V[k][j0 + q];
-        } else {              // Y = V X: Y[i][j] = sum_k V[i][k] X[k][j]
-            const float vk = V[i][k];
+        for (int b = 0; b < 2; ++b) acc[a][b] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-            for (int q = 0; q < 16; ++q) y[q] += vk * X[k][j0 + q];
+    for (int k = 0; k < 64; k += 4) {
+        const int kk = k + (lane >> 4);
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            const float av = Q[kk][wc + a * 16 + (lane & 15)];
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const float bv = P[wr + b * 16 + (lane & 15)][kk];
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[a][b], 0, 0, 0);
+            }
         }
     }
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const int j = j0 + q;
-        if (rows) {
-            if (i < nb && j < bk) LU[int64_t(K0 + j) * N + b0 + i] = y[q];
-        } else {
-            if (i < bk && j < nb) LU[int64_t(b0 + j) * N + K0 + i] = y[q];
-        }
-    }
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int j = wc + a * 16 + 4 * (lane >> 4) + q, i = wr + b * 16 + (lane & 15);
+                if (rows) {
+                    if (i < nb && j < bk) LU[int64_t(K0 + j) * N + b0 + i] = acc[a][b][q];
+                } else {
+                    if (i < bk && j < nb) LU[int64_t(b0 + j) * N + K0 + i] = acc[a][b][q];
+                }
+            }
 }
 
 // ---------------------------------------------------------------- triangular solves
