@@ -542,188 +542,9 @@ __global__ __launch_bounds__(256) void gemm_update_kernel(int N, float *LU, int 
 }
 
 // ---------------------------------------------------------------- blocked LU without interchanges
-// LU without interchanges of the bk x bk diagonal block at (K0, K0), bk <= 128,
-// in place, on one workgroup of 1024 threads (four wavefronts per SIMD, so the
-// LDS and barrier latencies of one hide behind the others): thread t owns the
-// rows ti + 32 a and the columns tc + 32 b (ti = t % 32, tc = t / 32, a, b < 4)
-// of the block, 16 entries in registers (a block smaller than 128 is padded
-// with the identity).  Per column j the owners of column j and of row j
-// publish them to LDS (double-buffered by parity), one barrier, then every
-// thread updates its entries below and right of (j, j) with one FMA each
-// (multipliers zero at or above j, row entries zero at or left of j) and the
-// owners of column j store its multipliers.  A zero or non-finite pivot is
-// reported in info like a singular column.
-__global__ __launch_bounds__(1024) void diag_lu_kernel(int N, float *LU, int K0, int bk, int *info)
-{
-    __shared__ float colb[2][128], rowb[2][128];
-    __shared__ int sinfo;
-    const int t = threadIdx.x, ti = t & 31, tc = t >> 5;
-    if (t == 0) sinfo = 0;
-    float e[4][4];
-    // unconditional loads from clamped entries, masked: all in flight together
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        const int c = tc + 32 * b;
-        const float *col = LU + int64_t(K0 + min(c, bk - 1)) * N + K0;
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            const int i = ti + 32 * a;
-            const bool in = i < bk && c < bk;
-            e[a][b] = col[min(i, bk - 1)] * (in ? 1.0f : 0.0f) + ((!in && i == c) ? 1.0f : 0.0f);
-        }
-    }
-#pragma unroll
-    for (int b = 0; b < 4; ++b)
-#pragma unroll
-        for (int a = 0; a < 4; ++a) asm volatile("" : "+v"(e[a][b]));
-    for (int j = 0; j < 128; ++j) {
-        const int buf = j & 1, jj = j & 31, jq = j >> 5;
-        if (tc == jj) {
-#pragma unroll
-            for (int b = 0; b < 4; ++b)
-                if (b == jq) {
-#pragma unroll
-                    for (int a = 0; a < 4; ++a) colb[buf][ti + 32 * a] = e[a][b];
-                }
-        }
-        if (ti == jj) {
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-                if (a == jq) {
-#pragma unroll
-                    for (int b = 0; b < 4; ++b) rowb[buf][tc + 32 * b] = e[a][b];
-                }
-        }
-        __syncthreads();
-        const float d = rowb[buf][j];
-        const bool ok = fabsf(d) > 0.0f && fabsf(d) <= 3.402823466e38f;
-        if (t == 0 && !ok && j < bk && sinfo == 0) sinfo = K0 + j + 1;
-        const float inv = ok ? 1.0f / d : 0.0f;
-        // (unconditional LDS reads scaled by 0 or 1: no branch around them; every
-        // published value is a finite matrix entry)
-        float l[4], rv[4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) l[a] = colb[buf][ti + 32 * a] * (ti + 32 * a > j ? inv : 0.0f);
-#pragma unroll
-        for (int b = 0; b < 4; ++b) rv[b] = rowb[buf][tc + 32 * b] * (tc + 32 * b > j ? 1.0f : 0.0f);
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) e[a][b] -= l[a] * rv[b];
-        if (tc == jj) {
-#pragma unroll
-            for (int b = 0; b < 4; ++b)
-                if (b == jq) {
-#pragma unroll
-                    for (int a = 0; a < 4; ++a) e[a][b] = ti + 32 * a > j ? l[a] : e[a][b];
-                }
-        }
-    }
-    float *LUs = LU;
-    asm volatile("" : "+s"(LUs));
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        const int c = tc + 32 * b;
-        if (c < bk) {
-            float *col = LUs + int64_t(K0 + c) * N + K0;
-#pragma unroll
-            for (int a = 0; a < 4; ++a) {
-                const int i = ti + 32 * a;
-                if (i < bk) col[i] = e[a][b];
-            }
-        }
-    }
-    __syncthreads();
-    if (t == 0 && sinfo != 0 && *info == 0) *info = sinfo;
-}
-
-// L21 = A21 U11^{-1} for the rows [r0, N) under a factored bk x bk diagonal
-// block at K0 (bk <= 128): each workgroup (16 wavefronts) stages U11 (its
-// strictly upper part and inverted diagonal) and 64 rows of A21 in LDS with
-// coalesced loads; every wavefront solves four rows at once (their dependent
-// chains interleave), lane l holding columns l and l + 64 of each; the solved
-// value of each step is broadcast by readlane.  The rows go back through LDS to
-// coalesced stores.
-__global__ __launch_bounds__(1024) void trsm_rows_kernel(int N, float *LU, int K0, int bk, int r0)
-{
-    __shared__ float U[128][129];    // strictly upper part of U11, zero elsewhere (and past bk)
-    __shared__ float X[64][129];
-    __shared__ float dinv[128];
-    const int tid = threadIdx.x;
-    const int rb = r0 + blockIdx.x * 64, nr = min(64, N - rb);
-    // unconditional loads from clamped entries, masked, unrolled: all in flight together
-    {
-        float v[16];
-#pragma unroll
-        for (int it = 0; it < 16; ++it) {
-            const int e = tid + it * 1024, r = e & 127, c = e >> 7;
-            v[it] = LU[int64_t(K0 + min(c, bk - 1)) * N + K0 + min(r, bk - 1)] * ((r < c && c < bk) ? 1.0f : 0.0f);
-        }
-#pragma unroll
-        for (int it = 0; it < 16; ++it) {
-            const int e = tid + it * 1024;
-            U[e & 127][e >> 7] = v[it];
-        }
-#pragma unroll
-        for (int it = 0; it < 8; ++it) {
-            const int e = tid + it * 1024, r = e & 63, c = e >> 6;
-            v[it] = LU[int64_t(K0 + min(c, bk - 1)) * N + rb + min(r, nr - 1)] * ((r < nr && c < bk) ? 1.0f : 0.0f);
-        }
-#pragma unroll
-        for (int it = 0; it < 8; ++it) {
-            const int e = tid + it * 1024;
-            X[e & 63][e >> 6] = v[it];
-        }
-    }
-    if (tid < 128) dinv[tid] = tid < bk ? 1.0f / LU[int64_t(K0 + tid) * N + K0 + tid] : 0.0f;
-    __syncthreads();
-    const int lane = tid & 63, wave = tid >> 6;
-    // step s: x_s is final once scaled by 1/U_ss; the rows' later entries take
-    // x_s U_sc (zero for c <= s and past bk, so no branch); lane s keeps x_s.
-    // The wavefront's four rows are four independent chains.
-    const int p0 = 4 * wave;
-    float x0[4], x1[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        x0[q] = X[p0 + q][lane];
-        x1[q] = X[p0 + q][lane + 64];
-    }
-    const int s0 = min(bk, 64);
-    for (int s = 0; s < s0; ++s) {
-        const float di = dinv[s], u0 = U[s][lane], u1 = U[s][lane + 64];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const float xs = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x0[q]), s)) * di;
-            x0[q] -= xs * u0;
-            x1[q] -= xs * u1;
-            x0[q] = lane == s ? xs : x0[q];
-        }
-    }
-    for (int s = 64; s < bk; ++s) {
-        const float di = dinv[s], u1 = U[s][lane + 64];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const float xs = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x1[q]), s - 64)) * di;
-            x1[q] -= xs * u1;
-            x1[q] = lane + 64 == s ? xs : x1[q];
-        }
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        X[p0 + q][lane] = x0[q];
-        X[p0 + q][lane + 64] = x1[q];
-    }
-    __syncthreads();
-    for (int e = tid; e < 64 * bk; e += blockDim.x) {
-        const int r = e & 63, c = e >> 6;
-        if (r < nr) LU[int64_t(K0 + c) * N + rb + r] = X[r][c];
-    }
-}
-
-// Small matrices (N <= 4096), without interchanges, in 64-column blocks: the
-// diagonal block is factored by one wavefront and inverted by two, and L21, U12
-// become plain products with the inverses (no dependent chain), so each block
-// takes three launches.
+// Without interchanges, every 64-column diagonal block is factored by one
+// wavefront and inverted by two, and L21, U12 become plain products with the
+// inverses (no dependent chain).
 //
 // diag64_kernel: wavefront 0 factors the bk x bk block (bk <= 64, padded with
 // the identity) with lane l holding row l in registers: per column j the
@@ -1303,19 +1124,20 @@ void trailing_update(int N, float *LU, int KE, int K0, int bk, hipStream_t s)
 
 hipError_t lu_factor_f32(int N, float *LU, int *piv, int *info, void *diag_inv, bool pivot, hipStream_t s)
 {
-    // Without pivoting (pivot false, N <= 16384): blocked LU in 64-column
-    // blocks up to N = 4096 (given diag_inv), 128-column blocks beyond (half
-    // the trailing matrix's traffic), the diagonal as pivot and no interchange
-    // anywhere.  With partial pivoting, two levels: blocks of BK columns, each
+    // Without pivoting (pivot false, N <= 16384, diag_inv required): blocked LU
+    // in 64-column blocks up to N = 4096, 128-column blocks of two 64-column
+    // halves beyond (half the trailing matrix's traffic), the diagonal as pivot
+    // and no interchange anywhere; the inverted 64 x 64 diagonal blocks go to
+    // diag_inv.  With partial pivoting, two levels: blocks of BK columns, each
     // factored by narrow register panels whose triangular solves and updates
     // stay inside the block; then one triangular solve for the block's U12 and
     // one rank-BK update of the trailing matrix (the MFMA-bound part).  Row
     // interchanges always go to the full rows.  Up to N = 4096 one block spans
     // the matrix (every narrow panel updates the whole trailing matrix): there
     // the launches saved outweigh the traffic of the narrow updates (measured).
-    if (!pivot && !lu_without_pivoting_supported(N)) return hipErrorInvalidValue;
+    if (!pivot && (!lu_without_pivoting_supported(N) || !diag_inv)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(64), 0, s, info);
-    if (!pivot && N <= 4096 && diag_inv) {
+    if (!pivot && N <= 4096) {
         // 64-column blocks: diagonal block factored and inverted (its inverses are
         // the triangular solves' inverted diagonal blocks), then L21 and U12 as
         // products with the inverses, then the rank-64 update
@@ -1334,23 +1156,34 @@ hipError_t lu_factor_f32(int N, float *LU, int *piv, int *info, void *diag_inv, 
         return hipGetLastError();
     }
     if (!pivot) {
-        // without interchanges the rows below a block are independent once its
-        // diagonal block is factored: per block of 128 columns, the diagonal
-        // block on one workgroup, L21 = A21 U11^{-1} and U12 = L11^{-1} A12 on
-        // many, then the rank-128 update of the trailing matrix
+        // beyond N = 4096: blocks of 128 columns made of two 64-column halves.
+        // Each half is factored and inverted by diag64_kernel and gets its L21
+        // and U12 from panel_mul_kernel; between the halves only the second
+        // half's column strip and row strip take the first half's rank-64
+        // update; the trailing matrix then takes one rank-128 update.
+        float *DI = static_cast<float *>(diag_inv);
         for (int K0 = 0; K0 < N; K0 += 128) {
-            const int bk = std::min(128, N - K0), KE = K0 + bk, rest = N - KE;
-            hipLaunchKernelGGL(diag_lu_kernel, dim3(1), dim3(1024), 0, s, N, LU, K0, bk, info);
-            if (rest > 0) {
-                hipLaunchKernelGGL(trsm_rows_kernel, dim3((rest + 63) / 64), dim3(1024), 0, s, N, LU, K0, bk, KE);
-                hipLaunchKernelGGL(trsm_block_kernel, dim3((rest + 31) / 32), dim3(1024), 0, s, N, LU, K0, bk, KE);
-                trailing_update(N, LU, KE, K0, bk, s);
+            const int bka = std::min(64, N - K0), KEa = K0 + bka;
+            hipLaunchKernelGGL(diag64_kernel, dim3(1), dim3(128), 0, s, N, LU, K0, bka, DI, info);
+            if (KEa < N) {
+                const int nra = (N - KEa + 63) / 64;
+                hipLaunchKernelGGL(panel_mul_kernel, dim3(2 * nra), dim3(256), 0, s, N, LU, K0, bka, KEa, DI, nra);
+                const int bkb = std::min(64, N - KEa), KEb = KEa + bkb;
+                // column strip (rows from KEa, the second half's columns), then its row strip
+                hipLaunchKernelGGL(gemm_update_kernel, dim3(nra, 1), dim3(256), 0, s, N, LU, KEa, KEa, KEb, K0, bka);
+                if (KEb < N)
+                    hipLaunchKernelGGL(gemm_update_kernel, dim3(1, (N - KEb + 63) / 64), dim3(256), 0, s, N, LU, KEa, KEb,
+                                       N, K0, bka);
+                hipLaunchKernelGGL(diag64_kernel, dim3(1), dim3(128), 0, s, N, LU, KEa, bkb, DI, info);
+                if (KEb < N) {
+                    const int nrb = (N - KEb + 63) / 64;
+                    hipLaunchKernelGGL(panel_mul_kernel, dim3(2 * nrb), dim3(256), 0, s, N, LU, KEa, bkb, KEb, DI, nrb);
+                    trailing_update(N, LU, KEb, K0, KEb - K0, s);
+                }
             }
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
-        if (diag_inv)
-            hipLaunchKernelGGL(invert_diag_kernel, dim3((N + 63) / 64), dim3(64), 0, s, N, LU, static_cast<float *>(diag_inv));
         return hipGetLastError();
     }
     const int BK = N <= 4096 ? N : 128;
