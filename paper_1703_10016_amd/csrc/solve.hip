@@ -975,8 +975,20 @@ __global__ __launch_bounds__(256) void residual_kernel(int N, const InT *A, int6
     const int lane = threadIdx.x & 63;
     if (row >= N) return;
     const InT *a = A + int64_t(row) * lda;
-    double s = 0.0;
-    for (int j = lane; j < N; j += 64) s += double(a[j]) * x[j];
+    // eight loads of the row (and of x) in flight per lane, four partial sums
+    double p4[4] = {0.0, 0.0, 0.0, 0.0};
+    int j = lane;
+    for (; j + 7 * 64 < N; j += 8 * 64) {
+        double av[8], xv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) av[u] = double(a[j + 64 * u]);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) xv[u] = x[j + 64 * u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) p4[u & 3] += av[u] * xv[u];
+    }
+    for (; j < N; j += 64) p4[0] += double(a[j]) * x[j];
+    double s = (p4[0] + p4[1]) + (p4[2] + p4[3]);
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
     if (lane == 0) r[row] = beta[row] - s;
 }
@@ -988,8 +1000,17 @@ __global__ __launch_bounds__(256) void rowabs_kernel(int N, const InT *A, int64_
     const int lane = threadIdx.x & 63;
     if (row >= N) return;
     const InT *a = A + int64_t(row) * lda;
-    double s = 0.0;
-    for (int j = lane; j < N; j += 64) s += fabs(double(a[j]));
+    double p4[4] = {0.0, 0.0, 0.0, 0.0};
+    int j = lane;
+    for (; j + 7 * 64 < N; j += 8 * 64) {
+        double av[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) av[u] = double(a[j + 64 * u]);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) p4[u & 3] += fabs(av[u]);
+    }
+    for (; j < N; j += 64) p4[0] += fabs(double(a[j]));
+    double s = (p4[0] + p4[1]) + (p4[2] + p4[3]);
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
     if (lane == 0) rs[row] = s;
 }
@@ -1056,14 +1077,23 @@ __global__ __launch_bounds__(256) void asym_kernel(int N, const InT *A, int64_t 
     for (int64_t t = blockIdx.x; t < int64_t(nt) * nt; t += gridDim.x) {
         const int ti = int(t / nt), tj = int(t % nt);
         if (ti > tj) continue;                                   // uniform over the workgroup
-        for (int y = ty; y < 32; y += 8) {
-            const int r = tj * 32 + y, c = ti * 32 + tx;
-            T[y][tx] = (r < N && c < N) ? A[int64_t(r) * lda + c] : InT(0);
+        // loads from clamped addresses, all issued before any is used; entries
+        // outside the matrix are masked by selection
+        InT va[4], vb[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int y = ty + 8 * q;
+            va[q] = A[int64_t(min(tj * 32 + y, N - 1)) * lda + min(ti * 32 + tx, N - 1)];
+            vb[q] = A[int64_t(min(ti * 32 + y, N - 1)) * lda + min(tj * 32 + tx, N - 1)];
         }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) T[ty + 8 * q][tx] = va[q];
         __syncthreads();
-        for (int y = ty; y < 32; y += 8) {
-            const int r = ti * 32 + y, c = tj * 32 + tx;
-            if (r < N && c < N) mx = fmax(mx, fabs(double(A[int64_t(r) * lda + c]) - double(T[tx][y])));
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int y = ty + 8 * q, r = ti * 32 + y, c = tj * 32 + tx;
+            const double d = fabs(double(vb[q]) - double(T[tx][y]));
+            mx = (r < N && c < N) ? fmax(mx, d) : mx;
         }
         __syncthreads();
     }
