@@ -21,13 +21,17 @@ Parts:
   50-digit arithmetic from the closed-form base integral of Section 4.2.
 * ``wq`` (O3): the weighted-quadrature rules (Alg. 1, Alg. 2, modified moments)
   and the row assembly of eqs. IK1e2 / IK1e2_bis with dense linear algebra.
-* ``solve``: dense FP64 solve of A alpha = beta (eq. sistlin).
 * ``direct`` (O4): right-hand side of the direct formulation, eq. final_b2
   with the rule of Section 5 (regular weighted outer rule, composite Gauss
   inner rule), F = b1/2 - b2/(2 pi) (eq. seconda_BIE), and the outward flux of
   a harmonic function for the convergence pin.
 * ``collocation`` (O5): collocation BEM with the same rules (Conclusions):
   the outer integral replaced by the value at the Greville abscissae.
+* ``open_arc``: the singular rule of Section 4.2 on an open interval (the
+  paper's own setting of its Table 1 tests).
+
+Solutions of A alpha = beta (eq. sistlin) in the tests use LAPACK's FP64
+solve (numpy) directly; there is no oracle solver of its own.
 
 Every function is FP64 and written for readability, not speed.
 """

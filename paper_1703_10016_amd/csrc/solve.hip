@@ -1015,6 +1015,10 @@ __global__ __launch_bounds__(256) void rowabs_kernel(int N, const InT *A, int64_
     if (lane == 0) rs[row] = s;
 }
 
+// Largest of two values that propagates NaN (fmax returns the other operand),
+// so that a non-finite correction, residual or entry reaches the host's checks.
+__device__ __forceinline__ double nan_max(double a, double b) { return (a > b || a != a) ? a : b; }
+
 // x += d (d FP32), and max-norms: red[0] = |d|_inf, red[1] = |x|_inf, red[2] = |r|_inf, red[3] = |beta|_inf
 __global__ __launch_bounds__(1024) void update_norms_kernel(int N, double *x, const float *d, const double *r,
                                                             const double *beta, int add, double *red)
@@ -1024,19 +1028,19 @@ __global__ __launch_bounds__(1024) void update_norms_kernel(int N, double *x, co
     for (int i = threadIdx.x; i < N; i += blockDim.x) {
         double xi = add ? x[i] + double(d[i]) : double(d[i]);
         x[i] = xi;
-        m[0] = fmax(m[0], fabs(double(d[i])));
-        m[1] = fmax(m[1], fabs(xi));
-        m[2] = fmax(m[2], fabs(r[i]));
-        m[3] = fmax(m[3], fabs(beta[i]));
+        m[0] = nan_max(m[0], fabs(double(d[i])));
+        m[1] = nan_max(m[1], fabs(xi));
+        m[2] = nan_max(m[2], fabs(r[i]));
+        m[3] = nan_max(m[3], fabs(beta[i]));
     }
     for (int q = 0; q < 4; ++q) {
-        for (int off = 32; off > 0; off >>= 1) m[q] = fmax(m[q], __shfl_xor(m[q], off));
+        for (int off = 32; off > 0; off >>= 1) m[q] = nan_max(m[q], __shfl_xor(m[q], off));
         if ((threadIdx.x & 63) == 0) s[q][threadIdx.x >> 6] = m[q];
     }
     __syncthreads();
     if (threadIdx.x < 4) {
         double v = 0.0;
-        for (int k = 0; k < int(blockDim.x >> 6); ++k) v = fmax(v, s[threadIdx.x][k]);
+        for (int k = 0; k < int(blockDim.x >> 6); ++k) v = nan_max(v, s[threadIdx.x][k]);
         red[threadIdx.x] = v;
     }
 }
@@ -1045,13 +1049,13 @@ __global__ __launch_bounds__(1024) void max_kernel(int N, const double *v, doubl
 {
     __shared__ double s[16];
     double m = 0.0;
-    for (int i = threadIdx.x; i < N; i += blockDim.x) m = fmax(m, fabs(v[i]));
-    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+    for (int i = threadIdx.x; i < N; i += blockDim.x) m = nan_max(m, fabs(v[i]));
+    for (int off = 32; off > 0; off >>= 1) m = nan_max(m, __shfl_xor(m, off));
     if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = m;
     __syncthreads();
     if (threadIdx.x == 0) {
         double v2 = 0.0;
-        for (int k = 0; k < int(blockDim.x >> 6); ++k) v2 = fmax(v2, s[k]);
+        for (int k = 0; k < int(blockDim.x >> 6); ++k) v2 = nan_max(v2, s[k]);
         *out = v2;
     }
 }
@@ -1093,14 +1097,14 @@ __global__ __launch_bounds__(256) void asym_kernel(int N, const InT *A, int64_t 
         for (int q = 0; q < 4; ++q) {
             const int y = ty + 8 * q, r = ti * 32 + y, c = tj * 32 + tx;
             const double d = fabs(double(vb[q]) - double(T[tx][y]));
-            mx = (r < N && c < N) ? fmax(mx, d) : mx;
+            mx = (r < N && c < N) ? nan_max(mx, d) : mx;
         }
         __syncthreads();
     }
-    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+    for (int off = 32; off > 0; off >>= 1) mx = nan_max(mx, __shfl_xor(mx, off));
     if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = mx;
     __syncthreads();
-    if (threadIdx.x == 0) out[blockIdx.x] = fmax(fmax(s[0], s[1]), fmax(s[2], s[3]));
+    if (threadIdx.x == 0) out[blockIdx.x] = nan_max(nan_max(s[0], s[1]), nan_max(s[2], s[3]));
 }
 
 // Register panel for the rows k0..N-1 (m = N - k0 <= 16384) of the block
@@ -1382,7 +1386,8 @@ int mixed_solve(int N, const void *d_A, int64_t lda, int a_prec, const double *d
                 }
             }
             res.iters = it + 1;
-            res.rel_update = red[1] > 0 ? red[0] / red[1] : 0.0;
+            // NaN in either norm stays NaN (and ends the loop below as no convergence)
+            res.rel_update = red[0] == 0.0 ? 0.0 : red[0] / red[1];
             res.backward_err = red[2] / (normA * red[1] + red[3]);   // of the iterate before this step
             if (res.rel_update <= tol) {
                 status = 0;

@@ -85,3 +85,33 @@ def test_batch_graph_replay(ctx):
             assert np.array_equal(o.cpu().numpy(), e), rep
     del g
     S.sgbem_batch_free(ctx.ctx, b)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batch_members_match_oracle(ctx, prec):
+    """Batch members against the oracle (eqs. IK1e2 / IK1e2_bis, Alg. 3), not
+    against the library's own single-curve path: full matrices for three
+    members of different degree, sampled rows (upper part from the row, lower
+    part through the mirror) for two members with N >= 700.  1e-12 in FP64,
+    2e-5 in FP32, max-norm relative."""
+    import torch
+    from oracle import wq
+    from paper_1703_10016_amd import sgbem as S
+    b, outs = _batch(ctx, prec)
+    S.sgbem_batch_assemble(ctx.ctx, b)
+    torch.cuda.synchronize()
+    tol = 1e-12 if prec == "fp64" else 2e-5
+    for k in (1, 2, 5):                   # (p, N) = (3, 64), (4, 100), (4, 300)
+        curve, p, N = CASES[k]
+        got = outs[k].double().cpu().numpy()
+        ref = wq.matrix(curve, p, N, 1)
+        assert np.abs(got - ref).max() < tol * np.abs(ref).max(), (k, p, N)
+    for k in (9, 10):                     # (2, 700), (3, 1000)
+        curve, p, N = CASES[k]
+        got = outs[k].double().cpu().numpy()
+        rows = [0, 1, N // 2 + 1, N - 1]
+        ref = wq.full_rows(curve, p, N, 1, rows)
+        for r, i in enumerate(rows):
+            assert np.abs(got[i, i:] - ref[r, i:]).max() < tol * np.abs(ref[r]).max(), (k, i)
+            assert np.array_equal(got[i, :i], got[:i, i])
+    S.sgbem_batch_free(ctx.ctx, b)

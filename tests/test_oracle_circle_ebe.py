@@ -154,3 +154,32 @@ def test_solution_converges_at_order_p_plus_1():
         errs.append(np.sqrt(np.mean((phi - ex) ** 2) / np.mean(ex ** 2)))
     rates = [math.log2(a / b) for a, b in zip(errs, errs[1:])]
     assert all(2.6 < q < 3.6 for q in rates), rates
+
+
+# ------------------------------------------------------------------ O2 right-hand side (eq. final_b1)
+@pytest.mark.parametrize("N,p,G", [(64, 2, 8), (32, 3, 10), (20, 4, 12)])
+def test_ebe_rhs_equals_circle_closed_form(N, p, G):
+    """beta_i = int B_i J g ds for g = x1^2 - x2^2 on the circle has the closed
+    form of O1; the G-point element rule reaches it to rounding for G >= 8.
+    A swapped piece index (p - a for a), a dropped element length or a shifted
+    element fails this (the closed form carries the phase (i + (p+1)/2)/N)."""
+    r = 0.5
+    beta = ebe.EBEProblem(synth.circle(r), p, N, G).rhs(synth.g_x2_minus_y2)
+    ref = circle.rhs_x2_minus_y2(r, N, p)
+    assert np.abs(beta - ref).max() < 1e-14 * np.abs(ref).max()
+
+
+def test_ebe_rhs_star_adaptive_quadrature():
+    """On a star (J not constant, g = exp(x1) cos(x2)) the element rule at G = 12
+    equals beta_i by adaptive quadrature over the p+1 elements of supp B_i."""
+    curve, p, N, G = synth.star(3), 3, 12, 12
+    beta = ebe.EBEProblem(curve, p, N, G).rhs(synth.g_exp_cos)
+
+    def integrand(i, s):
+        x, y, _, _, J = curves.evaluate(curve, np.array([s % 1.0]))
+        return float(bspline.periodic(p, N, i, s % 1.0)) * J[0] * float(synth.g_exp_cos(x[0], y[0]))
+
+    for i in (0, 5, N - 1):
+        ref = sum(integrate.quad(lambda s: integrand(i, s), (i + e) / N, (i + e + 1) / N,
+                                 epsabs=1e-15, epsrel=1e-13, limit=200)[0] for e in range(p + 1))
+        assert abs(beta[i] - ref) < 1e-13 * np.abs(beta).max(), (i, beta[i], ref)

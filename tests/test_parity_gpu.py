@@ -119,7 +119,8 @@ def test_full_size_ebe_sampled_entries(ellipse_full):
     assert np.abs(A[ii, jj] - ref).max() < 1e-12 * np.abs(A).max()
 
 
-@pytest.mark.parametrize("p,N,prec", [(2, 4096, "fp64"), (4, 4096, "fp64"), (3, 16384, "fp64"), (3, 16384, "fp32")])
+@pytest.mark.parametrize("p,N,prec", [(2, 4096, "fp64"), (4, 4096, "fp64"), (3, 16384, "fp64"), (3, 16384, "fp32"),
+                                      (2, 16384, "fp32"), (4, 16384, "fp32"), (3, 4096, "fp32")])
 def test_large_wq_sampled_rows(ctx, p, N, prec):
     """Star curves at the sizes of the large configurations (the launch that
     switches to the large-matrix tile instance from N = 4096): sampled rows
@@ -158,6 +159,16 @@ def test_fp32_error_bound(ctx, method):
     assert np.array_equal(A32, A32.T)
     err = relmax(A32, A64)
     assert err < 2e-6, err
+
+
+def test_fp32_ebe_matches_oracle(ctx):
+    """The FP32 plain form against the FP64 oracle of the same rule (not the
+    GPU's own FP64 matrix): FP32 kernel values and sums, FP64 node differences."""
+    curve, p, N, G = synth.star(11), 3, 300, 4
+    A32 = ctx.assemble(curve, p, N, "ebe", n_gauss=G, precision="fp32").cpu().numpy().astype(np.float64)
+    ref = ebe.matrix(curve, p, N, G)
+    assert np.array_equal(A32, A32.T)
+    assert relmax(A32, ref) < 2e-6
 
 
 # ------------------------------------------------------------------ right-hand side
@@ -225,6 +236,38 @@ def test_positive_definite_solve_without_interchanges(ctx, prec):
     assert info.pivoted == 0
     ref = np.linalg.solve(A.cpu().numpy().astype(np.float64), beta.cpu().numpy())
     assert np.linalg.norm(x.cpu().numpy() - ref) / np.linalg.norm(ref) < 1e-10
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("N", [4200, 8200])
+def test_positive_definite_large_keeps_factor_without_interchanges(ctx, N, prec):
+    """Beyond N = 4096 the factorisation without interchanges runs in 128-column
+    blocks of two 64-column halves; N = 4200 and 8200 leave ragged second halves
+    (40 and 8 columns).  On the ellipse (positive definite) that factor must be
+    kept (no silent fallback to partial pivoting) and the refined solution must
+    equal LAPACK's FP64 solve of the same stored matrix."""
+    c = synth.config_ellipse()
+    A = ctx.assemble(c.curve, c.p, N, "wq", precision=prec)
+    beta = ctx.rhs(c.curve, c.p, N, c.g)
+    x, info = ctx.solve(A, beta, tol=1e-12)
+    assert info.pivoted == 0, (info.iters, info.rel_update, info.backward_err)
+    ref = np.linalg.solve(A.cpu().numpy().astype(np.float64), beta.cpu().numpy())
+    assert np.linalg.norm(x.cpu().numpy() - ref) / np.linalg.norm(ref) < 1e-10
+
+
+@pytest.mark.parametrize("bad", [float("nan"), float("inf")], ids=["nan", "inf"])
+def test_non_finite_matrix_is_never_reported_converged(ctx, bad):
+    """A symmetric matrix with one non-finite pair of entries: the refinement's
+    norms propagate NaN, so the solve ends with an error status (no convergence
+    or a zero pivot), never with SGBEM_OK."""
+    import torch
+    from paper_1703_10016_amd import sgbem as S
+    N = 96
+    A = circle.matrix(0.5, N, 2)
+    A[5, 7] = A[7, 5] = bad
+    b = torch.from_numpy(circle.rhs_x2_minus_y2(0.5, N, 2)).cuda()
+    x, info = ctx.solve(torch.from_numpy(A).cuda(), b, check=False)
+    assert info.status in (S.SGBEM_E_NOCONV, S.SGBEM_E_SINGULAR), info.status
 
 
 @pytest.mark.parametrize("N", [300, 4200], ids=["64-column blocks", "128-column blocks"])

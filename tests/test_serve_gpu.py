@@ -169,3 +169,22 @@ def test_destroy_drops_requests_not_yet_admitted():
     t = time.time()
     S.sgbem_server_destroy(srv)
     assert time.time() - t < 10.0
+
+
+def test_served_solution_matches_oracle_solve():
+    """Served alpha against LAPACK's FP64 solve of the oracle's matrix and
+    right-hand side (eqs. IK1e2 / IK1e2_bis, eq. final_b1), not against the
+    library's own single-call path.  The served matrix is within 1e-12
+    (max-norm relative) of the oracle's and the refinement stops at 1e-12, so
+    the relative solution error is bounded by cond_2(A) times a small multiple
+    of 1e-12: the test allows 1e-10 + 4 cond_2(A) 1e-12."""
+    from oracle import wq
+    reqs = _requests([(3, 300), (2, 256)])
+    xs, comp, _ = _run_server(reqs, workers=2, budget_bytes=1 << 30, max_N=512, max_rules=8)
+    for (curve, p, N, _), x, c in zip(reqs, xs, [comp[0], comp[1]]):
+        assert c.status == 0, c.message
+        A = wq.matrix(curve, p, N, 1)
+        beta = wq.rhs(curve, p, N, 1, synth.g_exp_cos)
+        ref = np.linalg.solve(A, beta)
+        err = np.linalg.norm(x - ref) / np.linalg.norm(ref)
+        assert err < 1e-10 + 4 * np.linalg.cond(A) * 1e-12, (p, N, err, np.linalg.cond(A))
