@@ -28,7 +28,7 @@ from typing import Callable, List, Tuple
 import numpy as np
 
 __all__ = [
-    "PolarCurve", "BSplineCurve", "circle", "ellipse_bspline", "star",
+    "PolarCurve", "BSplineCurve", "circle", "ellipse_bspline", "ellipse_bspline_nonuniform", "star",
     "g_x2_minus_y2", "g_exp_cos", "Problem", "config_circle", "config_ellipse",
     "config_stars", "config_batch", "config_serving",
 ]
@@ -46,12 +46,16 @@ class PolarCurve:
 
 @dataclass(frozen=True)
 class BSplineCurve:
-    """Closed curve f(t) = sum_j ctrl[j] B_j(t) with periodic uniform knots on
-    n_ctrl elements of [0, 1); B_j is supported on [j/n, (j+degree+1)/n) mod 1.
-    ``ctrl`` has shape (n_ctrl, 2); the first ``degree`` points are not repeated."""
+    """Closed curve f(t) = sum_j ctrl[j] B_j(t) with periodic knots on n_ctrl
+    elements of [0, 1); B_j is supported on [tau_j, tau_{j+degree+1}) mod 1.
+    ``ctrl`` has shape (n_ctrl, 2); the first ``degree`` points are not repeated.
+    ``knots``: None for uniform knots tau_k = k / n_ctrl, else the n_ctrl + 1
+    breakpoints tau_0 = 0 < tau_1 < ... < tau_n = 1 of one period (extended
+    periodically, tau_{k+n} = tau_k + 1)."""
     degree: int
     ctrl: np.ndarray
     kind: str = "bspline"
+    knots: np.ndarray = None
 
 
 def circle(r: float = 0.5) -> PolarCurve:
@@ -67,6 +71,20 @@ def ellipse_bspline(a: float = 1.0, b: float = 0.5, n_ctrl: int = 32) -> BSpline
     scale = 3.0 / (2.0 + math.cos(2.0 * math.pi / n_ctrl))
     ctrl = scale * np.stack([a * np.cos(th), b * np.sin(th)], axis=1)
     return BSplineCurve(degree=3, ctrl=np.ascontiguousarray(ctrl))
+
+
+def ellipse_bspline_nonuniform(idx: int = 0, n_ctrl: int = 32, jitter: float = 0.35) -> BSplineCurve:
+    """The control polygon of ``ellipse_bspline`` on non-uniform periodic knots
+    tau_k = (k + jitter (u_k - 1/2)) / n_ctrl, u_k ~ U(0, 1) from PCG64 seeded
+    with [1703, 30000 + idx], tau_0 = 0 and tau_n = 1 (element lengths between
+    (1 - jitter) / n and (1 + jitter) / n).  The control polygon is convex, so
+    the curve is a simple closed convex curve near the ellipse."""
+    rng = np.random.default_rng([1703, 30000 + int(idx)])
+    u = rng.uniform(0.0, 1.0, n_ctrl)
+    u[0] = 0.5
+    tau = (np.arange(n_ctrl + 1) + jitter * (np.append(u, 0.5) - 0.5)) / n_ctrl
+    base = ellipse_bspline(n_ctrl=n_ctrl)
+    return BSplineCurve(degree=3, ctrl=base.ctrl, knots=np.ascontiguousarray(tau))
 
 
 def star(idx: int, n_modes: int = 6) -> PolarCurve:

@@ -79,3 +79,51 @@ def test_ellipse_bspline_interpolates_at_knots():
     tm = (np.arange(32) + 0.5) / 32
     x, y, *_ = curves.evaluate(c, tm)
     assert np.abs(np.hypot(x, 2 * y) - 1).max() < 5e-6
+
+
+def _scipy_periodic(curve):
+    """scipy's BSpline on the extended knot vector tau_{-d} .. tau_{n+d} with
+    coefficients Q_{(i - d) mod n}: the closed curve on [0, 1)."""
+    d, Q, tau = curve.degree, np.asarray(curve.ctrl), np.asarray(curve.knots)
+    n = Q.shape[0]
+    text = np.concatenate([tau[n - d:n] - 1.0, tau, tau[1:d + 1] + 1.0])
+    return BSpline(text, np.array([Q[(i - d) % n] for i in range(n + d)]), d)
+
+
+@pytest.mark.parametrize("curve", [
+    synth.ellipse_bspline_nonuniform(0),
+    synth.ellipse_bspline_nonuniform(5, n_ctrl=9, jitter=0.6),
+    synth.BSplineCurve(degree=2, ctrl=np.random.default_rng(4).normal(size=(7, 2)),
+                       knots=np.array([0.0, 0.05, 0.3, 0.35, 0.6, 0.8, 0.93, 1.0])),
+    synth.BSplineCurve(degree=5, ctrl=np.random.default_rng(6).normal(size=(11, 2)),
+                       knots=np.sort(np.concatenate([[0.0, 1.0], np.random.default_rng(7).uniform(0, 1, 10)]))),
+])
+def test_periodic_knots_match_scipy(curve):
+    t = np.concatenate([np.linspace(0, 1, 777, endpoint=False), np.asarray(curve.knots[:-1])])
+    S = _scipy_periodic(curve)
+    ref, dref = S(t), S.derivative()(t)
+    x, y, dx, dy, J = curves.evaluate(curve, t)
+    sc = np.abs(ref).max()
+    assert np.abs(x - ref[:, 0]).max() < 1e-14 * sc and np.abs(y - ref[:, 1]).max() < 1e-14 * sc
+    dsc = np.abs(dref).max()
+    assert np.abs(dx - dref[:, 0]).max() < 1e-13 * dsc and np.abs(dy - dref[:, 1]).max() < 1e-13 * dsc
+    assert np.allclose(J, np.hypot(dref[:, 0], dref[:, 1]), rtol=1e-12, atol=0)
+
+
+def test_uniform_knot_vector_reduces_to_the_uniform_curve():
+    import dataclasses
+    u = synth.ellipse_bspline()
+    uk = dataclasses.replace(u, knots=np.arange(33) / 32)
+    t = np.random.default_rng(2).uniform(0, 1, 400)
+    for a, b in zip(curves.evaluate(u, t), curves.evaluate(uk, t)):
+        assert np.abs(a - b).max() < 1e-13 * max(1.0, np.abs(a).max())
+
+
+def test_nonuniform_ellipse_is_closed_and_convex():
+    c = synth.ellipse_bspline_nonuniform(0)
+    t = np.linspace(0, 1, 2001)
+    x, y, dx, dy, J = curves.evaluate(c, np.mod(t, 1.0))
+    assert J.min() > 0.1
+    # turning direction never changes sign (convex, counter-clockwise)
+    cross = dx[:-1] * dy[1:] - dy[:-1] * dx[1:]
+    assert (cross > 0).all()
