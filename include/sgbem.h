@@ -210,6 +210,29 @@ sgbem_status sgbem_assemble(sgbem_ctx ctx, const sgbem_curve *curve, sgbem_rules
                             void *d_A, int64_t lda);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the fast
+ * form of sgbem_assemble (method SGBEM_WQ, same kernels, same results) with
+ * no allocation of any kind.  The node geometry (f and J on the 2 n_ref N
+ * nodes), which sgbem_assemble keeps in a buffer of the context, goes to a
+ * fixed device array of the library instead: SGBEM_NOALLOC_MAX_NODES nodes
+ * (3 doubles each, 1.5 MiB), one array per device, held until the process
+ * ends; its address is looked up when the first context on the device is
+ * created.  Every call on one device shares that array: calls that overlap
+ * on one device (two streams, or two host threads) race, and the caller
+ * must order them.  Nothing in it needs clearing between calls (every node
+ * is written before it is read).  The curve must travel inline (polar, or
+ * B-spline with at most 64 control points).  Kernel timing
+ * (sgbem_ctx_set_timing) does not apply.  Asynchronous, launches only.
+ * Errors: E_INVAL (2 n_ref N > SGBEM_NOALLOC_MAX_NODES, or the arguments of
+ *      sgbem_assemble), E_UNSUPPORTED (a curve that does not travel inline, a
+ *      (p, n_ref) without a compiled kernel), E_DEVICE.
+ */
+#define SGBEM_NOALLOC_MAX_NODES 65536
+sgbem_status sgbem_assemble_noalloc(sgbem_ctx ctx, const sgbem_curve *curve, sgbem_rules rules,
+                                    int32_t precision, void *d_A, int64_t lda);
+
+/*
  * Right-hand side beta_i = int B_i J g(f) ds (eq. final_b1), FP64:
  *  WQ:  sum_n w_n^(i) J(eta_n) g_n (Section 5);   EBE: G-point Gauss per element.
  * d_g: device [count] FP64 samples of g at the sgbem_rhs_points of the same

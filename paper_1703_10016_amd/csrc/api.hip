@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -41,8 +42,17 @@ bool assemble_supported(int method, int, int p, int P)
 
 using namespace sgbem;
 
+// Node geometry of sgbem_assemble_noalloc (X, Y, J of up to
+// SGBEM_NOALLOC_MAX_NODES nodes): a fixed array, one copy per device, held
+// until the process ends.  Host code never uses this name as an address: it
+// passes the device address that scratch_address() looked up.
+static __device__ __align__(256) double scratch[3 * SGBEM_NOALLOC_MAX_NODES];
+
 namespace {
 thread_local std::string g_err;
+
+std::mutex g_scratch_mu;
+std::vector<double *> g_scratch_addr;   // device address of `scratch`, per device (nullptr: not looked up)
 }  // namespace
 
 namespace sgbem {
@@ -194,7 +204,7 @@ sgbem_status inline_curve(const sgbem_curve *cv, CurveDev &d)
     d.kind = cv->kind;
     d.inline_data = 1;
     if (cv->kind == SGBEM_CURVE_BSPLINE) {
-        if (cv->n_ctrl > 64) return set_err(SGBEM_E_UNSUPPORTED, "batched curves need at most 64 control points");
+        if (cv->n_ctrl > 64) return set_err(SGBEM_E_UNSUPPORTED, "a curve that travels inline has at most 64 control points");
         d.degree = cv->degree;
         d.n_ctrl = cv->n_ctrl;
         std::memcpy(d.inl, cv->ctrl_xy, size_t(cv->n_ctrl) * 2 * sizeof(double));
@@ -222,6 +232,26 @@ bool valid_batch(sgbem_ctx c, sgbem_batch b)
     for (auto *x : c->batches)
         if (x == b) return true;
     return false;
+}
+
+// With `device` current: the device address of that device's copy of
+// `scratch`, looked up once per device and kept.
+sgbem_status scratch_address(int device, double *&out)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    try {
+        if (int(g_scratch_addr.size()) <= device) g_scratch_addr.resize(size_t(device) + 1, nullptr);
+    } catch (...) {
+        return set_err(SGBEM_E_NOMEM, "host allocation failed");
+    }
+    if (!g_scratch_addr[device]) {
+        void *p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return set_err(SGBEM_E_DEVICE, "hipGetSymbolAddress returned no address for the fixed geometry array");
+        g_scratch_addr[device] = static_cast<double *>(p);
+    }
+    out = g_scratch_addr[device];
+    return SGBEM_OK;
 }
 
 // Upload the curve's arrays and return the device description.
@@ -277,6 +307,24 @@ GridDesc wq_grid(sgbem_rules r)
     g.P = 0;
     g.npts = int(r->npts);
     return g;
+}
+
+// Tile-kernel arguments of the fast form: node geometry X, Y, J on the grid of
+// r, the rule tables and the support coefficients (output fields left to the caller).
+void wq_tile_args(sgbem_rules r, const double *X, const double *Y, const double *J, TileArgs &ta)
+{
+    ta.npts = int(r->npts);
+    ta.X = X;
+    ta.Y = Y;
+    ta.J = J;
+    ta.inv_s2 = r->d_inv_s2;
+    ta.ws = r->d_ws;
+    ta.inv_s2f = r->d_inv_s2f;
+    ta.wsf = r->d_wsf;
+    for (int q = 0; q < r->Q; ++q) {
+        ta.coefA[q] = r->w0[q];
+        ta.coefB[q] = r->bvals[q];
+    }
 }
 
 GridDesc gauss_grid(int N, int G)
@@ -374,9 +422,16 @@ sgbem_status sgbem_ctx_create(int32_t device, void *hip_stream, sgbem_ctx *out)
     int n = 0;
     HIPCHK(hipGetDeviceCount(&n));
     if (device < 0 || device >= n) return set_err(SGBEM_E_INVAL, "no such HIP device");
+    double *scr = nullptr;
+    {
+        DeviceGuard g(device);
+        sgbem_status st = scratch_address(device, scr);
+        if (st) return st;
+    }
     auto *c = new (std::nothrow) sgbem_ctx_s;
     if (!c) return set_err(SGBEM_E_NOMEM, "host allocation failed");
     c->device = device;
+    c->noalloc_scratch = scr;
     c->stream = static_cast<hipStream_t>(hip_stream);
     *out = c;
     return SGBEM_OK;
@@ -563,18 +618,7 @@ sgbem_status sgbem_assemble(sgbem_ctx c, const sgbem_curve *curve, sgbem_rules r
         const GridDesc grid = wq_grid(r);
         double *X, *Y, *J;
         if ((st = geometry(c, cd, grid, c->geo, X, Y, J))) return st;
-        ta.npts = grid.npts;
-        ta.X = X;
-        ta.Y = Y;
-        ta.J = J;
-        ta.inv_s2 = r->d_inv_s2;
-        ta.ws = r->d_ws;
-        ta.inv_s2f = r->d_inv_s2f;
-        ta.wsf = r->d_wsf;
-        for (int q = 0; q < r->Q; ++q) {
-            ta.coefA[q] = r->w0[q];
-            ta.coefB[q] = r->bvals[q];
-        }
+        wq_tile_args(r, X, Y, J, ta);
         KernelEvents ke;
         const KernelEvents *kev;
         if ((st = timing_events(c, ke, kev))) return st;
@@ -617,6 +661,37 @@ sgbem_status sgbem_assemble(sgbem_ctx c, const sgbem_curve *curve, sgbem_rules r
     if ((st = timing_events(c, ke, kev))) return st;
     HIPCHK(launch_assemble(1, precision, p, P, ta, c->stream, kev));
     HIPCHK(launch_band(precision, N, p, na.L, ta.scale, d_A, lda, c->stream));
+    return SGBEM_OK;
+}
+
+sgbem_status sgbem_assemble_noalloc(sgbem_ctx c, const sgbem_curve *curve, sgbem_rules r, int32_t precision,
+                                    void *d_A, int64_t lda)
+{
+    if (!c || !r || !d_A) return set_err(SGBEM_E_INVAL, "NULL argument");
+    if (!valid_rules(c, r)) return set_err(SGBEM_E_INVAL, "rules handle does not belong to this context");
+    if (precision != SGBEM_FP64 && precision != SGBEM_FP32) return set_err(SGBEM_E_INVAL, "unknown precision");
+    if (lda < r->N) return set_err(SGBEM_E_INVAL, "lda < N");
+    if (r->npts > SGBEM_NOALLOC_MAX_NODES)
+        return set_err(SGBEM_E_INVAL, "2 n_ref N exceeds SGBEM_NOALLOC_MAX_NODES (the fixed geometry array)");
+    const int p = r->p, P = 2 * r->R;
+    if (!assemble_supported(SGBEM_WQ, precision, p, P))
+        return set_err(SGBEM_E_UNSUPPORTED, "no kernel compiled for this (p, n_ref)");
+    if (!c->noalloc_scratch) return set_err(SGBEM_E_DEVICE, "the fixed geometry array has no device address");
+    CurveDev cd;
+    sgbem_status st = inline_curve(curve, cd);
+    if (st) return st;
+    DeviceGuard g(c->device);
+    const GridDesc grid = wq_grid(r);
+    double *X = c->noalloc_scratch, *Y = X + grid.npts, *J = Y + grid.npts;
+    HIPCHK(launch_geometry(cd, grid, X, Y, J, c->stream));
+    TileArgs ta;
+    std::memset(&ta, 0, sizeof ta);
+    ta.N = r->N;
+    ta.scale = -1.0 / (2.0 * kPi);
+    ta.out = d_A;
+    ta.lda = lda;
+    wq_tile_args(r, X, Y, J, ta);
+    HIPCHK(launch_assemble(0, precision, p, P, ta, c->stream, nullptr));
     return SGBEM_OK;
 }
 

@@ -76,6 +76,8 @@ struct sgbem_batch_s {
 struct sgbem_ctx_s {
     int device = 0;
     hipStream_t stream = nullptr;
+    // device address of the fixed geometry array of sgbem_assemble_noalloc on this device
+    double *noalloc_scratch = nullptr;
     sgbem::DevBuf geo, geo16, nearL, params, solve_ws, dl;
     std::vector<sgbem_rules_s *> rules;
     std::vector<sgbem_batch_s *> batches;

@@ -20,6 +20,7 @@ SGBEM_E_NOCONV, SGBEM_E_DEVICE, SGBEM_E_UNSUPPORTED = -4, -5, -6
 SGBEM_CURVE_BSPLINE, SGBEM_CURVE_POLAR = 0, 1
 SGBEM_WQ, SGBEM_EBE = 0, 1
 SGBEM_FP64, SGBEM_FP32 = 0, 1
+SGBEM_NOALLOC_MAX_NODES = 65536
 
 _NAMES = {0: "OK", -1: "E_INVAL", -2: "E_NOMEM", -3: "E_SINGULAR", -4: "E_NOCONV", -5: "E_DEVICE",
           -6: "E_UNSUPPORTED"}
@@ -94,6 +95,7 @@ def lib():
             "sgbem_nearfield_host": [dp, dp, dp, dp],
             "sgbem_rhs_points": [vp, cp, vp, i32, i32, vp, i64, ctypes.POINTER(i64)],
             "sgbem_assemble": [vp, cp, vp, i32, i32, i32, vp, i64],
+            "sgbem_assemble_noalloc": [vp, cp, vp, i32, vp, i64],
             "sgbem_rhs": [vp, cp, vp, i32, i32, vp, vp],
             "sgbem_solve": [vp, i32, vp, i64, i32, vp, vp, dbl, i32, ctypes.POINTER(sgbem_solve_info)],
             "sgbem_batch_create": [vp, i32, cp, ctypes.POINTER(vp), i32, ctypes.POINTER(vp), ctypes.POINTER(i64),
@@ -139,7 +141,7 @@ def exported_symbols():
             "sgbem_batch_tune", "sgbem_batch_free", "sgbem_node_points_host", "sgbem_server_footprint",
             "sgbem_server_create", "sgbem_server_submit", "sgbem_server_poll", "sgbem_server_clock",
             "sgbem_server_stats", "sgbem_server_destroy", "sgbem_rhs_direct",
-            "sgbem_assemble_collocation", "sgbem_collocation_rhs"]
+            "sgbem_assemble_collocation", "sgbem_collocation_rhs", "sgbem_assemble_noalloc"]
 
 
 # ------------------------------------------------------------------ curve marshalling
@@ -242,6 +244,11 @@ def sgbem_assemble(ctx, curve, rules, method, n_gauss, precision, d_A_ptr, lda):
     c = _as_curve(curve)
     _check(lib().sgbem_assemble(ctx, c.ref(), rules, int(method), int(n_gauss), int(precision),
                                 ctypes.c_void_p(d_A_ptr), int(lda)))
+
+
+def sgbem_assemble_noalloc(ctx, curve, rules, precision, d_A_ptr, lda):
+    c = _as_curve(curve)
+    _check(lib().sgbem_assemble_noalloc(ctx, c.ref(), rules, int(precision), ctypes.c_void_p(d_A_ptr), int(lda)))
 
 
 def sgbem_rhs(ctx, curve, rules, method, n_gauss, d_g_ptr, d_beta_ptr):
