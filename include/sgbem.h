@@ -62,10 +62,15 @@ typedef enum { SGBEM_FP64 = 0, SGBEM_FP32 = 1 } sgbem_precision;
  * call: up to 64 control points (or any polar curve) travel inline in the
  * kernel arguments; larger control nets are copied to device memory owned by
  * the context.
- *  BSPLINE: f(t) = sum_j ctrl[j] M_d(n t - j mod n) with periodic uniform knots
- *           (the closed-curve representation of Section 3, whose last d control
- *           points repeat the first ones; here they are not repeated):
- *           degree d in [1, 7], n_ctrl > d, ctrl_xy = [n_ctrl][2].
+ *  BSPLINE: f(t) = sum_j ctrl[j] B_j(t), the closed-curve representation of
+ *           Section 3 (whose last d control points repeat the first ones; here
+ *           they are not repeated) on the periodic extension of the knots of
+ *           one period, tau_{k + n} = tau_k + 1, B_j of degree d supported on
+ *           [tau_j, tau_{j+d+1}) mod 1:
+ *           degree d in [1, 7], n_ctrl > d, ctrl_xy = [n_ctrl][2];
+ *           knots = NULL for uniform knots tau_k = k / n_ctrl, else [n_ctrl + 1]
+ *           breakpoints 0 = tau_0 < tau_1 < ... < tau_n = 1 (strictly
+ *           increasing: simple knots, so the curve is C^(d-1)).
  *  POLAR:   f(t) = r(theta) (cos theta, sin theta), theta = 2 pi t,
  *           r(theta) = r0 (1 + sum_{k=1..n_modes} a[k-1] cos(k theta + phi[k-1])),
  *           r0 > 0, 0 <= n_modes <= 64, r must stay positive.
@@ -76,6 +81,7 @@ typedef struct {
     int32_t degree;
     int32_t n_ctrl;
     const double *ctrl_xy;
+    const double *knots;
     double r0;
     int32_t n_modes;
     const double *a;
@@ -94,9 +100,38 @@ typedef struct {
 /* ---------------------------------------------------------------- context */
 
 /* Create a context on HIP device `device`; `hip_stream` is a hipStream_t (NULL:
- * the null stream).  Allocates nothing on the device until first use.
- * Errors: E_INVAL (bad device), E_DEVICE. */
-sgbem_status sgbem_ctx_create(int32_t device, void *hip_stream, sgbem_ctx *out);
+ * the null stream).  Allocates nothing on the device until first use; from
+ * then on the device memory the context holds (rule tables of its
+ * sgbem_weights handles, workspaces of the calls, batch descriptions) stays
+ * within `hbm_budget_bytes` (0: no limit): a call whose allocation would
+ * exceed it returns E_NOMEM before allocating or freeing anything, and the
+ * context keeps what it held.  sgbem_memory_need gives the bytes each call
+ * needs.  Errors: E_INVAL (bad device), E_DEVICE. */
+sgbem_status sgbem_ctx_create(int32_t device, void *hip_stream, uint64_t hbm_budget_bytes, sgbem_ctx *out);
+
+/* Device bytes the context holds now and its budget (0: no limit). */
+sgbem_status sgbem_ctx_memory(sgbem_ctx ctx, int64_t *held_bytes, int64_t *budget_bytes);
+
+/* Host-only: the device bytes a context allocates for one call of the kind
+ * `what` (each buffer rounded up to 4096 bytes; the workspaces are grow-only
+ * buffers of the context, reused by later calls of the same or smaller size):
+ *  SGBEM_MEM_RULES:        one sgbem_weights handle of (p, N, n_ref): 72 M + O(1)
+ *                          bytes, M = n_ref N;
+ *  SGBEM_MEM_ASSEMBLE_WQ:  node geometry of sgbem_assemble (SGBEM_WQ), sgbem_rhs
+ *                          (SGBEM_WQ) and sgbem_assemble_collocation: 48 M bytes;
+ *  SGBEM_MEM_ASSEMBLE_EBE: sgbem_assemble with SGBEM_EBE and n_gauss points:
+ *                          geometry on the Gauss and the 16-point near grids, the
+ *                          near-pair matrices and the cached near-pair table;
+ *  SGBEM_MEM_RHS_DIRECT:   sgbem_rhs_direct with n_gauss points: node geometry and
+ *                          the double-layer sweep's workspace;
+ *  SGBEM_MEM_SOLVE:        sgbem_solve of order N: 4 N^2 + O(N) bytes.
+ * n_ctrl: control points of the B-spline curve of the call (0 for a polar
+ * curve); beyond 64 they are copied to the device, 24 n_ctrl + 8 bytes more.
+ * Errors: E_INVAL. */
+typedef enum { SGBEM_MEM_RULES = 0, SGBEM_MEM_ASSEMBLE_WQ = 1, SGBEM_MEM_ASSEMBLE_EBE = 2,
+               SGBEM_MEM_RHS_DIRECT = 3, SGBEM_MEM_SOLVE = 4 } sgbem_memory_kind;
+sgbem_status sgbem_memory_need(int32_t what, int32_t p, int32_t N, int32_t n_ref, int32_t n_gauss, int32_t n_ctrl,
+                               int64_t *bytes);
 
 /* Synchronise the stream, free every device buffer the context owns. */
 sgbem_status sgbem_ctx_destroy(sgbem_ctx ctx);
@@ -415,7 +450,9 @@ sgbem_status sgbem_server_create(const sgbem_server_config *config, sgbem_server
 
 /* Queue a request.  Rejected with E_NOMEM when its footprint exceeds the
  * arena (it could never be admitted), E_INVAL / E_UNSUPPORTED for bad
- * arguments; a rejected request produces no completion. */
+ * arguments (E_UNSUPPORTED: a B-spline curve of more than 64 control points,
+ * which would need device memory of its own); a rejected request produces no
+ * completion. */
 sgbem_status sgbem_server_submit(sgbem_server s, const sgbem_request *req);
 
 /* Move up to cap completions into out (oldest first), waiting up to

@@ -63,18 +63,55 @@ sgbem_status set_err(sgbem_status st, const std::string &m)
     return st;
 }
 
+size_t buf_bytes(size_t bytes)
+{
+    const size_t nb = bytes < 4096 ? 4096 : bytes;
+    return (nb + 4095) & ~size_t(4095);
+}
+
+sgbem_status budget_check(sgbem_ctx c, size_t bytes, size_t releasing)
+{
+    if (c->budget == 0) return SGBEM_OK;
+    const uint64_t after = c->held - releasing + bytes;
+    if (after <= c->budget) return SGBEM_OK;
+    char m[200];
+    std::snprintf(m, sizeof m, "context HBM budget: %llu bytes needed, %llu held of %llu",
+                  (unsigned long long)bytes, (unsigned long long)c->held, (unsigned long long)c->budget);
+    return set_err(SGBEM_E_NOMEM, m);
+}
+
+sgbem_status ctx_malloc(sgbem_ctx c, void **p, size_t bytes)
+{
+    *p = nullptr;
+    sgbem_status st = budget_check(c, bytes, 0);
+    if (st) return st;
+    HIPCHK(hipMalloc(p, bytes));
+    c->held += bytes;
+    return SGBEM_OK;
+}
+
+void ctx_free(sgbem_ctx c, void *p, size_t bytes)
+{
+    if (!p) return;
+    (void)hipFree(p);
+    c->held -= bytes;
+}
+
 sgbem_status ensure(sgbem_ctx c, DevBuf &b, size_t bytes)
 {
     if (b.bytes >= bytes) return SGBEM_OK;
+    const size_t nb = buf_bytes(bytes);
+    sgbem_status st = budget_check(c, nb, b.bytes);
+    if (st) return st;
     if (b.ptr) {
         HIPCHK(hipStreamSynchronize(c->stream));
-        HIPCHK(hipFree(b.ptr));
+        ctx_free(c, b.ptr, b.bytes);
         b.ptr = nullptr;
         b.bytes = 0;
     }
-    size_t nb = bytes < 4096 ? 4096 : bytes;
-    nb = (nb + 4095) & ~size_t(4095);
-    HIPCHK(hipMalloc(&b.ptr, nb));
+    void *q = nullptr;
+    if ((st = ctx_malloc(c, &q, nb))) return st;
+    b.ptr = q;
     b.bytes = nb;
     return SGBEM_OK;
 }
@@ -178,6 +215,13 @@ sgbem_status check_curve(const sgbem_curve *c)
         if (c->degree < 1 || c->degree > 7) return set_err(SGBEM_E_INVAL, "B-spline curve degree must be in [1, 7]");
         if (c->n_ctrl <= c->degree) return set_err(SGBEM_E_INVAL, "B-spline curve needs n_ctrl > degree");
         if (!c->ctrl_xy) return set_err(SGBEM_E_INVAL, "B-spline curve without control points");
+        if (c->knots) {
+            const double *k = c->knots;
+            if (k[0] != 0.0 || k[c->n_ctrl] != 1.0)
+                return set_err(SGBEM_E_INVAL, "B-spline knots must run from 0 to 1 over one period");
+            for (int i = 0; i < c->n_ctrl; ++i)
+                if (!(k[i + 1] > k[i])) return set_err(SGBEM_E_INVAL, "B-spline knots must be strictly increasing");
+        }
     } else if (c->kind == SGBEM_CURVE_POLAR) {
         if (!(c->r0 > 0.0)) return set_err(SGBEM_E_INVAL, "polar curve needs r0 > 0");
         if (c->n_modes < 0 || c->n_modes > 64) return set_err(SGBEM_E_INVAL, "polar curve n_modes must be in [0, 64]");
@@ -208,6 +252,10 @@ sgbem_status inline_curve(const sgbem_curve *cv, CurveDev &d)
         d.degree = cv->degree;
         d.n_ctrl = cv->n_ctrl;
         std::memcpy(d.inl, cv->ctrl_xy, size_t(cv->n_ctrl) * 2 * sizeof(double));
+        if (cv->knots) {
+            d.nonuniform = 1;
+            std::memcpy(d.inl + 128, cv->knots, size_t(cv->n_ctrl + 1) * sizeof(double));
+        }
     } else {
         d.r0 = cv->r0;
         d.n_modes = cv->n_modes;
@@ -261,13 +309,7 @@ sgbem_status upload_curve(sgbem_ctx c, const sgbem_curve *cv, CurveDev &d)
     if (st) return st;
     std::memset(&d, 0, sizeof d);
     d.kind = cv->kind;
-    if (cv->kind == SGBEM_CURVE_BSPLINE && cv->n_ctrl <= 64) {
-        d.degree = cv->degree;
-        d.n_ctrl = cv->n_ctrl;
-        d.inline_data = 1;
-        std::memcpy(d.inl, cv->ctrl_xy, size_t(cv->n_ctrl) * 2 * sizeof(double));
-        return SGBEM_OK;
-    }
+    if (cv->kind == SGBEM_CURVE_BSPLINE && cv->n_ctrl <= 64) return inline_curve(cv, d);
     if (cv->kind == SGBEM_CURVE_POLAR) {
         d.r0 = cv->r0;
         d.n_modes = cv->n_modes;
@@ -279,12 +321,20 @@ sgbem_status upload_curve(sgbem_ctx c, const sgbem_curve *cv, CurveDev &d)
         return SGBEM_OK;
     }
     {
+        // control points, then the knots of a non-uniform curve
         d.degree = cv->degree;
         d.n_ctrl = cv->n_ctrl;
-        const size_t bytes = size_t(cv->n_ctrl) * 2 * sizeof(double);
-        if ((st = ensure(c, c->params, bytes))) return st;
-        HIPCHK(hipMemcpyAsync(c->params.ptr, cv->ctrl_xy, bytes, hipMemcpyHostToDevice, c->stream));
+        const size_t bc = size_t(cv->n_ctrl) * 2 * sizeof(double);
+        const size_t bk = cv->knots ? size_t(cv->n_ctrl + 1) * sizeof(double) : 0;
+        if ((st = ensure(c, c->params, bc + bk))) return st;
+        HIPCHK(hipMemcpyAsync(c->params.ptr, cv->ctrl_xy, bc, hipMemcpyHostToDevice, c->stream));
         d.ctrl = static_cast<const double *>(c->params.ptr);
+        if (cv->knots) {
+            double *kd = static_cast<double *>(c->params.ptr) + 2 * size_t(cv->n_ctrl);
+            HIPCHK(hipMemcpyAsync(kd, cv->knots, bk, hipMemcpyHostToDevice, c->stream));
+            d.knots = kd;
+            d.nonuniform = 1;
+        }
     }
     return SGBEM_OK;
 }
@@ -347,11 +397,14 @@ sgbem_status cached_table(sgbem_ctx c, int key, const std::vector<double> &host,
         dev = it->second;
         return SGBEM_OK;
     }
-    double *d = nullptr;
-    HIPCHK(hipMalloc(&d, host.size() * sizeof(double)));
+    void *dv = nullptr;
+    const size_t nb = buf_bytes(host.size() * sizeof(double));
+    sgbem_status st = ctx_malloc(c, &dv, nb);
+    if (st) return st;
+    double *d = static_cast<double *>(dv);
     hipError_t e = hipMemcpy(d, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
-        (void)hipFree(d);
+        ctx_free(c, d, nb);
         return set_err(SGBEM_E_DEVICE, std::string("table upload: ") + hipGetErrorString(e));
     }
     c->tables[key] = d;
@@ -415,7 +468,7 @@ const char *sgbem_version(void)
     return "libsgbem 1.0 (gfx950)";
 }
 
-sgbem_status sgbem_ctx_create(int32_t device, void *hip_stream, sgbem_ctx *out)
+sgbem_status sgbem_ctx_create(int32_t device, void *hip_stream, uint64_t hbm_budget_bytes, sgbem_ctx *out)
 {
     if (!out) return set_err(SGBEM_E_INVAL, "out is NULL");
     *out = nullptr;
@@ -432,8 +485,63 @@ sgbem_status sgbem_ctx_create(int32_t device, void *hip_stream, sgbem_ctx *out)
     if (!c) return set_err(SGBEM_E_NOMEM, "host allocation failed");
     c->device = device;
     c->noalloc_scratch = scr;
+    c->budget = hbm_budget_bytes;
     c->stream = static_cast<hipStream_t>(hip_stream);
     *out = c;
+    return SGBEM_OK;
+}
+
+sgbem_status sgbem_ctx_memory(sgbem_ctx c, int64_t *held_bytes, int64_t *budget_bytes)
+{
+    if (!c) return set_err(SGBEM_E_INVAL, "ctx is NULL");
+    if (held_bytes) *held_bytes = int64_t(c->held);
+    if (budget_bytes) *budget_bytes = int64_t(c->budget);
+    return SGBEM_OK;
+}
+
+sgbem_status sgbem_memory_need(int32_t what, int32_t p, int32_t N, int32_t n_ref, int32_t n_gauss, int32_t n_ctrl,
+                               int64_t *bytes)
+{
+    if (!bytes) return set_err(SGBEM_E_INVAL, "bytes is NULL");
+    *bytes = 0;
+    if (N < 1 || N > (1 << 24) || n_ctrl < 0) return set_err(SGBEM_E_INVAL, "bad N or n_ctrl");
+    const bool need_rules = what == SGBEM_MEM_RULES || what == SGBEM_MEM_ASSEMBLE_WQ || what == SGBEM_MEM_RHS_DIRECT;
+    if (need_rules && (n_ref < 1 || n_ref > 4)) return set_err(SGBEM_E_INVAL, "n_ref must be in [1, 4]");
+    if (what != SGBEM_MEM_SOLVE && (p < 1 || p > 6)) return set_err(SGBEM_E_INVAL, "p must be in [1, 6]");
+    const size_t n = size_t(N), M = size_t(n_ref) * n;
+    // control points beyond the inline storage (and the knots of a non-uniform curve)
+    const size_t params = n_ctrl > 64 ? buf_bytes(size_t(3 * n_ctrl + 1) * sizeof(double)) : 0;
+    size_t b = 0;
+    switch (what) {
+    case SGBEM_MEM_RULES:
+        b = buf_bytes(rules_block_bytes(int64_t(2 * M)));
+        break;
+    case SGBEM_MEM_ASSEMBLE_WQ:
+        b = buf_bytes(3 * 2 * M * sizeof(double)) + params;
+        break;
+    case SGBEM_MEM_ASSEMBLE_EBE: {
+        if (n_gauss < 1 || n_gauss > 8) return set_err(SGBEM_E_INVAL, "n_gauss must be in [1, 8]");
+        const size_t G = size_t(n_gauss), q = size_t(p + 1);
+        b = buf_bytes(3 * n * G * sizeof(double)) + buf_bytes(3 * n * 16 * sizeof(double)) +
+            buf_bytes(n * 2 * q * q * sizeof(double)) + buf_bytes((544 + q * 16) * sizeof(double)) +
+            buf_bytes(G * q * sizeof(double)) + params;
+        break;
+    }
+    case SGBEM_MEM_RHS_DIRECT: {
+        if (n_gauss < 2 || n_gauss > 8 || (n_gauss & 1)) return set_err(SGBEM_E_INVAL, "n_gauss must be 2, 4, 6 or 8");
+        const int nn = int(2 * M), np = int(n) * n_gauss;
+        const size_t nchunk = size_t(dl_chunks(nn, np));
+        b = buf_bytes(3 * size_t(nn) * sizeof(double)) +
+            buf_bytes(sizeof(double) * (5 * size_t(np) + nchunk * size_t(nn) + 2 * size_t(nn))) + params;
+        break;
+    }
+    case SGBEM_MEM_SOLVE:
+        b = buf_bytes(solve_workspace_bytes(N));
+        break;
+    default:
+        return set_err(SGBEM_E_INVAL, "unknown memory kind");
+    }
+    *bytes = int64_t(b);
     return SGBEM_OK;
 }
 
@@ -453,7 +561,7 @@ sgbem_status sgbem_ctx_destroy(sgbem_ctx c)
     (void)hipStreamSynchronize(c->stream);
     for (DevBuf *b : {&c->geo, &c->geo16, &c->nearL, &c->params, &c->solve_ws, &c->dl})
         if (b->ptr) (void)hipFree(b->ptr);
-    for (auto &kv : c->tables) (void)hipFree(kv.second);
+    for (auto &kv : c->tables) (void)hipFree(kv.second);   // (the context goes: no accounting)
     for (auto *r : c->rules) free_rules(r);
     for (auto *b : c->batches) {
         (void)hipFree(b->mem);
@@ -530,6 +638,8 @@ sgbem_status sgbem_node_points_host(const sgbem_curve *curve, int32_t N, int32_t
     d.n_modes = curve->n_modes;
     d.r0 = curve->r0;
     d.ctrl = curve->ctrl_xy;
+    d.knots = curve->knots;
+    d.nonuniform = curve->kind == SGBEM_CURVE_BSPLINE && curve->knots ? 1 : 0;
     d.a = curve->a;
     d.phi = curve->phi;
     const int64_t npts = int64_t(2) * n_ref * N;
@@ -546,11 +656,29 @@ sgbem_status sgbem_weights(sgbem_ctx c, int32_t p, int32_t N, int32_t n_ref, sgb
 {
     if (!c || !out) return set_err(SGBEM_E_INVAL, "ctx or out is NULL");
     *out = nullptr;
+    if (p < 1 || p > 6 || n_ref < 1 || n_ref > 4 || N < 2 * (p + 1) || int64_t(2) * n_ref * N > (int64_t(1) << 24))
+        return set_err(SGBEM_E_INVAL, "need p in [1, 6], n_ref in [1, 4], N >= 2 (p + 1), 2 n_ref N <= 2^24");
     DeviceGuard g(c->device);
-    sgbem_rules r = nullptr;
-    sgbem_status st = make_rules(p, N, n_ref, nullptr, c->stream, r);
+    // the block within the context's budget, before the host work
+    const size_t nb = buf_bytes(rules_block_bytes(int64_t(2) * n_ref * N));
+    void *block = nullptr;
+    sgbem_status st = ctx_malloc(c, &block, nb);
     if (st) return st;
-    c->rules.push_back(r);
+    sgbem_rules r = nullptr;
+    if ((st = make_rules(p, N, n_ref, block, c->stream, r))) {
+        ctx_free(c, block, nb);
+        return st;
+    }
+    r->owned = true;
+    r->block_bytes = nb;
+    try {
+        c->rules.push_back(r);
+    } catch (...) {
+        ctx_free(c, block, nb);
+        r->owned = false;
+        free_rules(r);
+        return set_err(SGBEM_E_NOMEM, "host allocation failed");
+    }
     *out = r;
     return SGBEM_OK;
 }
@@ -567,6 +695,7 @@ sgbem_status sgbem_rules_free(sgbem_ctx c, sgbem_rules r)
             c->rules.erase(c->rules.begin() + i);
             break;
         }
+    if (r->owned) c->held -= r->block_bytes;
     free_rules(r);
     return SGBEM_OK;
 }
@@ -874,11 +1003,16 @@ sgbem_status sgbem_batch_create(sgbem_ctx c, int32_t n, const sgbem_curve *curve
     const size_t total_bytes = o_geo + al(sizeof(double) * 3 * size_t(gsum));
     auto *bt = new (std::nothrow) sgbem_batch_s;
     if (!bt) return set_err(SGBEM_E_NOMEM, "host allocation failed");
-    hipError_t e = hipMalloc(&bt->mem, total_bytes);
-    if (e != hipSuccess) {
-        delete bt;
-        return set_err(e == hipErrorOutOfMemory ? SGBEM_E_NOMEM : SGBEM_E_DEVICE, "batch allocation failed");
+    const size_t mem_bytes = buf_bytes(total_bytes);
+    {
+        const sgbem_status sa = ctx_malloc(c, &bt->mem, mem_bytes);
+        if (sa) {
+            delete bt;
+            return sa;
+        }
     }
+    bt->mem_bytes = mem_bytes;
+    hipError_t e = hipSuccess;
     char *base = static_cast<char *>(bt->mem);
     bt->d.curves = reinterpret_cast<CurveDev *>(base + o_curves);
     bt->d.npts = reinterpret_cast<int *>(base + o_npts);
@@ -905,7 +1039,7 @@ sgbem_status sgbem_batch_create(sgbem_ctx c, int32_t n, const sgbem_curve *curve
     for (int k = 0; k < kNumBatchConfigs; ++k) ups.push_back({bt->d.prefix[k], pre[k].data(), sizeof(int) * (n + 1)});
     for (const Up &u : ups) {
         if ((e = hipMemcpy(u.dst, u.src, u.bytes, hipMemcpyHostToDevice)) != hipSuccess) {
-            (void)hipFree(bt->mem);
+            ctx_free(c, bt->mem, bt->mem_bytes);
             delete bt;
             return set_err(SGBEM_E_DEVICE, std::string("batch upload: ") + hipGetErrorString(e));
         }
@@ -983,7 +1117,7 @@ sgbem_status sgbem_batch_free(sgbem_ctx c, sgbem_batch b)
             c->batches.erase(c->batches.begin() + i);
             break;
         }
-    (void)hipFree(b->mem);
+    ctx_free(c, b->mem, b->mem_bytes);
     delete b;
     return SGBEM_OK;
 }

@@ -28,7 +28,7 @@ sgbem_status set_err(sgbem_status st, const std::string &m);
                                     std::string(#call) + ": " + hipGetErrorString(e_));    \
     } while (0)
 
-// Grow-only device buffer owned by a context.
+// Grow-only device buffer owned by a context (bytes: its allocated size).
 struct DevBuf {
     void *ptr = nullptr;
     size_t bytes = 0;
@@ -61,6 +61,7 @@ struct sgbem_rules_s {
     double *d_inv_s2 = nullptr, *d_ws = nullptr, *d_w0 = nullptr;
     float *d_inv_s2f = nullptr, *d_wsf = nullptr;
     void *block = nullptr;
+    size_t block_bytes = 0;   // allocated size of an owned block
     bool owned = false;
     bool shared = false;
 };
@@ -71,6 +72,7 @@ struct sgbem_batch_s {
     int cfg = 0, grid = 0;
     sgbem::BatchDev d{};
     void *mem = nullptr;     // one device allocation holding the whole description
+    size_t mem_bytes = 0;
 };
 
 struct sgbem_ctx_s {
@@ -78,6 +80,9 @@ struct sgbem_ctx_s {
     hipStream_t stream = nullptr;
     // device address of the fixed geometry array of sgbem_assemble_noalloc on this device
     double *noalloc_scratch = nullptr;
+    // device bytes held by the context (buffers, tables, owned rule blocks,
+    // batches) and the limit set at creation (0: none)
+    uint64_t held = 0, budget = 0;
     sgbem::DevBuf geo, geo16, nearL, params, solve_ws, dl;
     std::vector<sgbem_rules_s *> rules;
     std::vector<sgbem_batch_s *> batches;
@@ -96,8 +101,21 @@ struct sgbem_ctx_s {
 namespace sgbem {
 
 // Grow b to at least `bytes` (synchronises the context's stream before a
-// reallocation).
+// reallocation).  Sizes are rounded up to 4096 bytes; E_NOMEM, with b and
+// everything else the context holds unchanged, when the grown buffer would
+// exceed the context's budget.
 sgbem_status ensure(sgbem_ctx c, DevBuf &b, size_t bytes);
+
+// Allocation size of a context buffer of `bytes` (at least 4096, a multiple of 4096).
+size_t buf_bytes(size_t bytes);
+
+// E_NOMEM when allocating `bytes` while releasing `releasing` would take the
+// context beyond its budget.
+sgbem_status budget_check(sgbem_ctx c, size_t bytes, size_t releasing);
+
+// hipMalloc / hipFree with the context's accounting (ctx_malloc checks the budget first).
+sgbem_status ctx_malloc(sgbem_ctx c, void **p, size_t bytes);
+void ctx_free(sgbem_ctx c, void *p, size_t bytes);
 
 // Bytes of the device block of a rule set with npts nodes.
 size_t rules_block_bytes(int64_t npts);

@@ -1,9 +1,10 @@
 // Curve geometry at one parameter value, shared by the single and batched
 // geometry kernels and the host-side node points: f, f' and J = |f'| (eq. J).
 //  polar:   f = r(theta) (cos theta, sin theta), theta = 2 pi t, closed-form derivative;
-//  B-spline (periodic uniform knots, Section 3): de Boor's algorithm on the span
-//           containing n_ctrl t, and on the derivative curve with control points
-//           n_ctrl (Q_j - Q_{j-1}) at degree d-1.
+//  B-spline (periodic knots, Section 3): de Boor's algorithm on the span
+//           containing t, and on the derivative curve with control points
+//           d (Q_j - Q_{j-1}) / (tau_{j+d} - tau_j) at degree d-1 (uniform
+//           knots tau_k = k / n_ctrl: n_ctrl (Q_j - Q_{j-1})).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -63,6 +64,60 @@ __host__ __device__ __forceinline__ void eval_curve_d(const CurveDev &c, double 
         y = r * sn;
         dx = 6.283185307179586476925286766559 * (dr * cs - r * sn);
         dy = 6.283185307179586476925286766559 * (dr * sn + r * cs);
+    } else if (c.nonuniform) {
+        // breakpoints tau_0 = 0 < ... < tau_n = 1 of one period, tau_{k+n} = tau_k + 1;
+        // B_j supported on [tau_j, tau_{j+d+1})
+        const int d = c.degree, nc = c.n_ctrl;
+        const double *tk = c.inline_data ? c.inl + 128 : c.knots;
+        int lo = 0, hi = nc - 1;      // the span l with tau_l <= t < tau_{l+1}
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (tk[mid] <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        const int l = lo;
+        // tau_k for k in [l - d, l + d]
+        double tau[16];
+        for (int i = 0; i <= 2 * d; ++i) {
+            const int k = l - d + i;
+            const int kk = k < 0 ? k + nc : (k >= nc ? k - nc : k);
+            tau[i] = tk[kk] + (k < 0 ? -1.0 : (k >= nc ? 1.0 : 0.0));
+        }
+        double px[8], py[8];
+        for (int i = 0; i <= d; ++i) {
+            int j = l - d + i;
+            j = ((j % nc) + nc) % nc;
+            px[i] = cq[2 * j];
+            py[i] = cq[2 * j + 1];
+        }
+        // derivative control points d (Q_j - Q_{j-1}) / (tau_{j+d} - tau_j), j = l-d+1 .. l
+        double qx[8], qy[8];
+        for (int i = 1; i <= d; ++i) {
+            const double s = d / (tau[i + d] - tau[i]);
+            qx[i - 1] = s * (px[i] - px[i - 1]);
+            qy[i - 1] = s * (py[i] - py[i - 1]);
+        }
+        // de Boor, local index i <-> knot tau_{l-d+i} = tau[i]
+        for (int r = 1; r <= d; ++r) {
+            for (int i = d; i >= r; --i) {
+                const double al = (t - tau[i]) / (tau[i + d + 1 - r] - tau[i]);
+                px[i] = (1.0 - al) * px[i - 1] + al * px[i];
+                py[i] = (1.0 - al) * py[i - 1] + al * py[i];
+            }
+        }
+        x = px[d];
+        y = py[d];
+        // degree d-1 on the same knots: local index i <-> knot tau_{l-d+1+i} = tau[i + 1]
+        const int dd = d - 1;
+        for (int r = 1; r <= dd; ++r) {
+            for (int i = dd; i >= r; --i) {
+                const double al = (t - tau[i + 1]) / (tau[i + 1 + dd + 1 - r] - tau[i + 1]);
+                qx[i] = (1.0 - al) * qx[i - 1] + al * qx[i];
+                qy[i] = (1.0 - al) * qy[i - 1] + al * qy[i];
+            }
+        }
+        dx = qx[dd];
+        dy = qy[dd];
     } else {
         const int d = c.degree, nc = c.n_ctrl;
         const double u = t * nc;

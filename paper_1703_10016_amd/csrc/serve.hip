@@ -8,7 +8,10 @@
 // and a free range of the request arena big enough for the request's
 // footprint; a request that does not fit waits (and so do the ones behind it)
 // until completions return memory.  Device memory is allocated only at
-// creation: the request arena, and the rule arena that backs the rule cache.
+// creation: the request arena, the rule arena that backs the rule cache, and
+// each slot's node-geometry buffer sized for the largest N; served curves
+// travel inline in the kernel arguments (polar, or at most 64 control points),
+// so a request allocates nothing.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -99,7 +102,7 @@ Layout layout(int N, int prec)
 
 struct Req {
     sgbem_request r{};
-    std::vector<double> ctrl, a, phi, g;
+    std::vector<double> ctrl, knots, a, phi, g;
     Layout lay;
     int64_t off = -1;
     double t_admit = 0.0;
@@ -435,7 +438,7 @@ sgbem_status sgbem_server_create(const sgbem_server_config *cfg, sgbem_server *o
             st = SGBEM_E_DEVICE;
             set_err(st, std::string("stream: ") + hipGetErrorString(e));
         }
-        if (st == SGBEM_OK) st = sgbem_ctx_create(cfg->device, w.stream, &w.ctx);
+        if (st == SGBEM_OK) st = sgbem_ctx_create(cfg->device, w.stream, 0, &w.ctx);
         // geometry buffer for the largest request, so that no slot reallocates while serving
         if (st == SGBEM_OK) st = ensure(w.ctx, w.ctx->geo, size_t(cfg->max_N) * 2 * 3 * sizeof(double));
         if (st != SGBEM_OK) {
@@ -474,6 +477,8 @@ sgbem_status sgbem_server_submit(sgbem_server s, const sgbem_request *req)
     if (!(req->arrival_s == req->arrival_s)) return set_err(SGBEM_E_INVAL, "arrival_s is NaN");
     sgbem_status st = check_curve(&req->curve);
     if (st) return st;
+    if (req->curve.kind == SGBEM_CURVE_BSPLINE && req->curve.n_ctrl > 64)
+        return set_err(SGBEM_E_UNSUPPORTED, "served curves travel inline: at most 64 control points");
     const Layout lay = layout(N, s->cfg.precision);
     if (int64_t(lay.total) > s->cfg.budget_bytes) {
         std::lock_guard<std::mutex> lk(s->mu);
@@ -489,6 +494,10 @@ sgbem_status sgbem_server_submit(sgbem_server s, const sgbem_request *req)
         if (cv.kind == SGBEM_CURVE_BSPLINE) {
             q->ctrl.assign(cv.ctrl_xy, cv.ctrl_xy + size_t(cv.n_ctrl) * 2);
             q->r.curve.ctrl_xy = q->ctrl.data();
+            if (cv.knots) {
+                q->knots.assign(cv.knots, cv.knots + size_t(cv.n_ctrl) + 1);
+                q->r.curve.knots = q->knots.data();
+            }
         } else if (cv.n_modes > 0) {
             q->a.assign(cv.a, cv.a + cv.n_modes);
             q->phi.assign(cv.phi, cv.phi + cv.n_modes);

@@ -11,12 +11,12 @@ _PREC = {"fp64": S.SGBEM_FP64, "fp32": S.SGBEM_FP32}
 
 
 class Context:
-    def __init__(self, device: int = 0, stream=None):
+    def __init__(self, device: int = 0, stream=None, hbm_budget_bytes: int = 0):
         import torch
         self.torch = torch
         self.device = torch.device("cuda", device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        self.ctx = S.sgbem_ctx_create(device, self.stream.cuda_stream)
+        self.ctx = S.sgbem_ctx_create(device, self.stream.cuda_stream, hbm_budget_bytes)
         self._rules = {}
 
     def close(self):

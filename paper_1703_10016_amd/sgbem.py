@@ -34,7 +34,8 @@ class SgbemError(RuntimeError):
 
 class sgbem_curve(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("degree", ctypes.c_int32), ("n_ctrl", ctypes.c_int32),
-                ("ctrl_xy", ctypes.POINTER(ctypes.c_double)), ("r0", ctypes.c_double),
+                ("ctrl_xy", ctypes.POINTER(ctypes.c_double)), ("knots", ctypes.POINTER(ctypes.c_double)),
+                ("r0", ctypes.c_double),
                 ("n_modes", ctypes.c_int32), ("a", ctypes.POINTER(ctypes.c_double)),
                 ("phi", ctypes.POINTER(ctypes.c_double))]
 
@@ -84,7 +85,9 @@ def lib():
         dp = ctypes.POINTER(ctypes.c_double)
         cp = ctypes.POINTER(sgbem_curve)
         sig = {
-            "sgbem_ctx_create": [i32, vp, ctypes.POINTER(vp)],
+            "sgbem_ctx_create": [i32, vp, ctypes.c_uint64, ctypes.POINTER(vp)],
+            "sgbem_ctx_memory": [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)],
+            "sgbem_memory_need": [i32, i32, i32, i32, i32, i32, ctypes.POINTER(i64)],
             "sgbem_ctx_destroy": [vp],
             "sgbem_ctx_set_stream": [vp, vp],
             "sgbem_ctx_set_timing": [vp, i32],
@@ -141,7 +144,8 @@ def exported_symbols():
             "sgbem_batch_tune", "sgbem_batch_free", "sgbem_node_points_host", "sgbem_server_footprint",
             "sgbem_server_create", "sgbem_server_submit", "sgbem_server_poll", "sgbem_server_clock",
             "sgbem_server_stats", "sgbem_server_destroy", "sgbem_rhs_direct",
-            "sgbem_assemble_collocation", "sgbem_collocation_rhs", "sgbem_assemble_noalloc"]
+            "sgbem_assemble_collocation", "sgbem_collocation_rhs", "sgbem_assemble_noalloc",
+            "sgbem_ctx_memory", "sgbem_memory_need"]
 
 
 # ------------------------------------------------------------------ curve marshalling
@@ -168,6 +172,13 @@ class Curve:
             c.n_ctrl = q.shape[0]
             self._keep.append(q)
             c.ctrl_xy = q.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            kn = getattr(curve, "knots", None)
+            if kn is not None:
+                kn = np.ascontiguousarray(kn, dtype=np.float64)
+                if kn.shape != (q.shape[0] + 1,):
+                    raise ValueError("knots must hold n_ctrl + 1 breakpoints")
+                self._keep.append(kn)
+                c.knots = kn.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         else:
             raise ValueError("curve must have kind 'polar' or 'bspline'")
         self.c = c
@@ -181,10 +192,26 @@ def _as_curve(curve):
 
 
 # ------------------------------------------------------------------ ABI functions
-def sgbem_ctx_create(device=0, stream=None):
+def sgbem_ctx_create(device=0, stream=None, hbm_budget_bytes=0):
     h = ctypes.c_void_p()
-    _check(lib().sgbem_ctx_create(int(device), ctypes.c_void_p(stream or 0), ctypes.byref(h)))
+    _check(lib().sgbem_ctx_create(int(device), ctypes.c_void_p(stream or 0), int(hbm_budget_bytes), ctypes.byref(h)))
     return h
+
+
+def sgbem_ctx_memory(ctx):
+    """(bytes held, budget) of a context."""
+    held, budget = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().sgbem_ctx_memory(ctx, ctypes.byref(held), ctypes.byref(budget)))
+    return held.value, budget.value
+
+
+SGBEM_MEM_RULES, SGBEM_MEM_ASSEMBLE_WQ, SGBEM_MEM_ASSEMBLE_EBE, SGBEM_MEM_RHS_DIRECT, SGBEM_MEM_SOLVE = 0, 1, 2, 3, 4
+
+
+def sgbem_memory_need(what, p=1, N=1, n_ref=1, n_gauss=0, n_ctrl=0):
+    b = ctypes.c_int64()
+    _check(lib().sgbem_memory_need(int(what), int(p), int(N), int(n_ref), int(n_gauss), int(n_ctrl), ctypes.byref(b)))
+    return b.value
 
 
 def sgbem_ctx_destroy(ctx):

@@ -84,14 +84,16 @@ def test_python_binding_has_no_compute_fallback():
     assert "oracle" not in src and "scipy" not in src
 
 
-@pytest.mark.parametrize("which", ["circle", "ellipse", "star"])
+@pytest.mark.parametrize("which", ["circle", "ellipse", "star", "ellipse-nonuniform", "nonuniform-80"])
 def test_node_points_host_match_oracle_curve(which):
     """The host node points f(n / 2 n_ref N) agree with the oracle's curve
     evaluation (de Boor / polar form, Section 3) to rounding."""
     import synth
     from oracle import curves
     S = _lib()
-    curve = {"circle": synth.circle(0.5), "ellipse": synth.ellipse_bspline(), "star": synth.star(7)}[which]
+    curve = {"circle": synth.circle(0.5), "ellipse": synth.ellipse_bspline(), "star": synth.star(7),
+             "ellipse-nonuniform": synth.ellipse_bspline_nonuniform(0),
+             "nonuniform-80": synth.ellipse_bspline_nonuniform(3, n_ctrl=80, jitter=0.6)}[which]
     for N, R in [(37, 1), (64, 2)]:
         xy = S.sgbem_node_points_host(curve, N, R)
         t = np.arange(2 * R * N) / (2 * R * N)
@@ -122,3 +124,70 @@ def test_server_rejects_bad_config_before_touching_the_device(kw):
     with pytest.raises(S.SgbemError) as e:
         S.sgbem_server_create(**kw)
     assert e.value.status == S.SGBEM_E_INVAL
+
+
+def test_node_points_host_nonuniform_knots_with_derivative_at_breakpoints():
+    """Node points on a knot vector with clustered knots, where many nodes fall
+    on or next to breakpoints (the span search's boundary cases)."""
+    import synth
+    from oracle import curves
+    S = _lib()
+    tau = np.array([0.0, 0.125, 0.25, 0.26, 0.27, 0.5, 0.625, 0.75, 0.875, 1.0])
+    ctrl = np.stack([np.cos(2 * np.pi * np.arange(9) / 9), 0.6 * np.sin(2 * np.pi * np.arange(9) / 9)], 1)
+    for d in (1, 2, 3, 5):
+        curve = synth.BSplineCurve(degree=d, ctrl=ctrl, knots=tau)
+        xy = S.sgbem_node_points_host(curve, 16, 2)
+        x, y = curves.evaluate(curve, np.arange(64) / 64)[:2]
+        assert np.abs(xy[:, 0] - x).max() < 1e-14 and np.abs(xy[:, 1] - y).max() < 1e-14
+
+
+@pytest.mark.parametrize("knots", [np.array([0.0, 0.3, 0.3, 0.6, 1.0]), np.array([0.1, 0.3, 0.5, 0.7, 1.0]),
+                                   np.array([0.0, 0.3, 0.5, 0.7, 0.99]), np.array([0.0, 0.5, 0.4, 0.7, 1.0])])
+def test_bad_knot_vectors_are_rejected(knots):
+    """Knots of one period must run from 0 to 1 and increase strictly."""
+    import synth
+    S = _lib()
+    ctrl = np.stack([np.cos(np.arange(4)), np.sin(np.arange(4))], 1)
+    with pytest.raises(S.SgbemError) as e:
+        S.sgbem_node_points_host(synth.BSplineCurve(degree=2, ctrl=ctrl, knots=knots), 8, 1)
+    assert e.value.status == S.SGBEM_E_INVAL
+
+
+def _al256(b):
+    return (b + 255) // 256 * 256
+
+
+def _buf(b):
+    return max(4096, (b + 4095) // 4096 * 4096)
+
+
+def test_memory_need_formulas():
+    """Device bytes per call kind, as the header states them: rule block
+    72 M (+ alignment), node geometry 48 M, solve workspace 4 N^2 + O(N), each
+    buffer rounded up to 4096 bytes, control nets beyond 64 points added."""
+    S = _lib()
+    for p, N, R in [(3, 1024, 1), (2, 16384, 1), (4, 700, 2), (6, 14, 4)]:
+        M = R * N
+        n = 2 * M
+        rules = _al256(8 * n) + _al256(16 * n) + _al256(512) + _al256(4 * n) + _al256(8 * n)
+        assert S.sgbem_memory_need(S.SGBEM_MEM_RULES, p, N, R) == _buf(rules)
+        assert abs(_buf(rules) - 72 * M) <= 4096 + 5 * 256
+        assert S.sgbem_memory_need(S.SGBEM_MEM_ASSEMBLE_WQ, p, N, R) == _buf(48 * M)
+        assert S.sgbem_memory_need(S.SGBEM_MEM_ASSEMBLE_WQ, p, N, R, n_ctrl=64) == _buf(48 * M)
+        assert S.sgbem_memory_need(S.SGBEM_MEM_ASSEMBLE_WQ, p, N, R, n_ctrl=100) == _buf(48 * M) + _buf(8 * 301)
+    for N in (16, 1000, 4099, 16384):
+        sv = S.sgbem_memory_need(S.SGBEM_MEM_SOLVE, 1, N)
+        assert 4 * N * N <= sv <= 4 * N * N + 1024 * N + 65536 and sv % 4096 == 0
+    p, N, G = 3, 200, 5
+    ebe = S.sgbem_memory_need(S.SGBEM_MEM_ASSEMBLE_EBE, p, N, 1, G)
+    assert ebe == _buf(24 * N * G) + _buf(24 * N * 16) + _buf(16 * N * (p + 1) ** 2) + _buf(8 * (544 + 16 * (p + 1))) \
+        + _buf(8 * G * (p + 1))
+    d = S.sgbem_memory_need(S.SGBEM_MEM_RHS_DIRECT, p, N, 1, 4)
+    assert d >= _buf(48 * N) + _buf(8 * (5 * N * 4 + 2 * 2 * N))
+    for bad in [dict(what=9), dict(what=0, N=0), dict(what=0, n_ref=5), dict(what=1, p=0), dict(what=2, n_gauss=0),
+                dict(what=3, n_gauss=3), dict(what=1, n_ctrl=-1)]:
+        kw = dict(p=3, N=64, n_ref=1, n_gauss=4, n_ctrl=0)
+        kw.update(bad)
+        with pytest.raises(S.SgbemError) as e:
+            S.sgbem_memory_need(kw.pop("what"), **kw)
+        assert e.value.status == S.SGBEM_E_INVAL
