@@ -23,14 +23,18 @@ constexpr int NB = 64;            // widest panel (register panels); longer pane
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 struct WS {
-    float *LU;
+    float *LU;       // the FP32 factor (column-major, ld N) or the Gauss-Jordan inverse (row-major, ld Np)
     int *piv, *perm, *info;
     double *r;
     float *v, *v2;
     double *red;     // reduction outputs
     float *DI;       // inverted diagonal blocks
     float *DI2;      // off-diagonal blocks of the inverses of pairs of diagonal blocks
+    float *GR, *GC, *GP;   // Gauss-Jordan panels: row blocks [2][nt][64][64], column blocks [2][nt][64][64], pivot inverses [2][64][64]
 };
+
+// Order padded to whole 64 x 64 tiles (the Gauss-Jordan inverse works on tiles).
+int padded64(int N) { return (N + 63) / 64 * 64; }
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -38,8 +42,9 @@ WS carve(void *base, int N)
 {
     char *p = static_cast<char *>(base);
     WS w;
+    const size_t Np = size_t(padded64(N));
     w.LU = reinterpret_cast<float *>(p);
-    p += align_up(size_t(N) * N * sizeof(float));
+    p += align_up(Np * Np * sizeof(float));
     w.piv = reinterpret_cast<int *>(p);
     p += align_up(size_t(N) * sizeof(int));
     w.perm = reinterpret_cast<int *>(p);
@@ -57,6 +62,13 @@ WS carve(void *base, int N)
     w.DI = reinterpret_cast<float *>(p);
     p += align_up(size_t(N + 63) / 64 * 2 * 4096 * sizeof(float));
     w.DI2 = reinterpret_cast<float *>(p);
+    p += align_up(std::max<size_t>(size_t(N + 63) / 64 / 2, 1) * 2 * 4096 * sizeof(float));
+    const size_t nt = Np / 64;
+    w.GR = reinterpret_cast<float *>(p);
+    p += align_up(2 * nt * 4096 * sizeof(float));
+    w.GC = reinterpret_cast<float *>(p);
+    p += align_up(2 * nt * 4096 * sizeof(float));
+    w.GP = reinterpret_cast<float *>(p);
     return w;
 }
 
@@ -965,6 +977,308 @@ __global__ void permute_kernel(int N, const int *perm, const double *src, float 
     if (i < N) dst[i] = float(src[perm[i]]);
 }
 
+// ---------------------------------------------------------------- Gauss-Jordan inverse (no interchanges)
+// For an exactly symmetric A of moderate order the FP32 factor used by the
+// refinement is the explicit inverse X, formed by block Gauss-Jordan
+// elimination without interchanges on 64 x 64 tiles of the matrix padded
+// with the identity to Np = 64 nt rows.  Sweep of pivot block k (P = A_kk^-1):
+//   A_kk <- P,  A_kj <- P A_kj,  A_ik <- -A_ik P,  A_ij <- A_ij - A_ik P A_kj,
+// with the old A_ik and A_kj on the right-hand sides; after the nt sweeps the
+// matrix holds X = A^-1.  One launch per sweep, one workgroup per tile: the
+// old row and column blocks of the sweep come from copies made by the
+// previous launch (the tiles of row and column k are rewritten in the same
+// launch), and the workgroup that updates the next pivot tile also inverts it.
+// Every product runs on v_mfma_f32_16x16x4_f32.  A refinement step then needs
+// one matrix-vector product with X instead of two triangular solves.
+constexpr int kGJMaxN = 4096;
+typedef float Tile64[64][65];
+
+// acc[a][b][v] = (X Y)[wr + 16 a + 4 (lane >> 4) + v][wc + 16 b + (lane & 15)]:
+// this wavefront's 32 x 32 quadrant of the product of two 64 x 64 LDS tiles.
+__device__ __forceinline__ void mm64_acc(const float (*X)[65], const float (*Y)[65], floatx4 acc[2][2], int wr, int wc,
+                                         int lane)
+{
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int k = 0; k < 64; k += 4) {
+        const int kk = k + (lane >> 4);
+        float av[2], bv[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) av[a] = X[wr + 16 * a + (lane & 15)][kk];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) bv[b] = Y[kk][wc + 16 * b + (lane & 15)];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+}
+
+// In-place inverse of the 64 x 64 LDS tile T by four Gauss-Jordan sweeps of
+// 16 x 16 pivot blocks (the same sweep as above, one level down).  Per sweep:
+// wavefront 0 inverts the pivot block (lane 4 r + g holds entries (r, 4 g .. 4 g + 3),
+// one scalar sweep per pivot, the pivot row and column reaching the lanes by
+// shuffles) into S; then Uh = S T_q (the pivot block's rows, their own columns
+// replaced by S) and, with V = T_{:q} (old), T <- T - V Uh outside the pivot
+// rows and columns, -V Uh in the pivot columns, Uh in the pivot rows.  *bad
+// (LDS, zeroed by the caller) is set on a zero or non-finite pivot.
+__device__ void invert64_lds(Tile64 &T, float (*S)[17], Tile64 &Uh, int *bad, int tid)
+{
+    const int wave = tid >> 6, lane = tid & 63;
+    const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
+    for (int q = 0; q < 64; q += 16) {
+        if (wave == 0) {
+            const int r = lane >> 2, g = lane & 3;
+            float e[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) e[c] = T[q + r][q + 4 * g + c];
+            int badl = 0;
+#pragma unroll
+            for (int p = 0; p < 16; ++p) {
+                const int pc = p & 3, pg = p >> 2;
+                const float d = __shfl(e[pc], 4 * p + pg);     // T[p][p]
+                const float f = __shfl(e[pc], 4 * r + pg);     // T[r][p]
+                float rp[4];                                   // T[p][4 g + c]
+#pragma unroll
+                for (int c = 0; c < 4; ++c) rp[c] = __shfl(e[c], 4 * p + g);
+                const bool ok = fabsf(d) > 0.0f && fabsf(d) <= 3.402823466e38f;
+                badl |= ok ? 0 : 1;
+                const float ip = ok ? 1.0f / d : 0.0f;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const int j = 4 * g + c;
+                    if (j == p) e[c] = (r == p) ? ip : -f * ip;
+                    else e[c] = (r == p) ? rp[c] * ip : e[c] - f * (rp[c] * ip);
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) S[r][4 * g + c] = e[c];
+            if (badl) *bad = 1;
+        }
+        __syncthreads();
+        {
+            // Uh = S T[q .. q+15][:], wavefront w: columns 16 w .. 16 w + 15
+            floatx4 u = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+            const int c0 = 16 * wave;
+#pragma unroll
+            for (int k = 0; k < 16; k += 4) {
+                const int kk = k + (lane >> 4);
+                u = __builtin_amdgcn_mfma_f32_16x16x4f32(S[lane & 15][kk], T[q + kk][c0 + (lane & 15)], u, 0, 0, 0);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int m = 4 * (lane >> 4) + v, j = c0 + (lane & 15);
+                Uh[m][j] = (j >= q && j < q + 16) ? S[m][j - q] : u[v];
+            }
+        }
+        // the old pivot columns of this wavefront's rows and its quadrant, read before any write
+        float va[2][4], told[2][2][4];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) va[a][ks] = T[wr + 16 * a + (lane & 15)][q + 4 * ks + (lane >> 4)];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) told[a][b][v] = T[wr + 16 * a + 4 * (lane >> 4) + v][wc + 16 * b + (lane & 15)];
+        __syncthreads();
+        floatx4 acc[2][2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) acc[a][b] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            const int kk = 4 * ks + (lane >> 4);
+            float bv[2];
+#pragma unroll
+            for (int b = 0; b < 2; ++b) bv[b] = Uh[kk][wc + 16 * b + (lane & 15)];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(va[a][ks], bv[b], acc[a][b], 0, 0, 0);
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = wr + 16 * a + 4 * (lane >> 4) + v, j = wc + 16 * b + (lane & 15);
+                    const bool iq = i >= q && i < q + 16, jq = j >= q && j < q + 16;
+                    T[i][j] = iq ? Uh[i - q][j] : (jq ? -acc[a][b][v] : told[a][b][v] - acc[a][b][v]);
+                }
+        __syncthreads();
+    }
+}
+
+// Sweep k of the Gauss-Jordan inverse (k = -1: load A, FP64 or FP32 row-major,
+// into the padded FP32 matrix W, row-major with ld Np).  Workgroup b owns tile
+// (b / nt, b % nt).  Rin / Cin / Pin: the old row block k, column block k and
+// the inverse of the pivot tile, made by the previous launch; the tiles of
+// row and column k + 1 after this sweep go to Rout / Cout and the inverse of
+// the new pivot tile to Pout (a zero or non-finite pivot sets *info).
+template <typename InT>
+__global__ __launch_bounds__(256) void gj_step_kernel(int N, int Np, int k, const InT *A, int64_t lda, float *W,
+                                                      const float *Rin, const float *Cin, const float *Pin, float *Rout,
+                                                      float *Cout, float *Pout, int *info)
+{
+    __shared__ Tile64 T, L, R, P;
+    __shared__ float S[16][17];
+    __shared__ int bad;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
+    const int nt = Np / 64;
+    const int bi = blockIdx.x / nt, bj = blockIdx.x - (blockIdx.x / nt) * nt;
+    float *Wt = W + int64_t(bi) * 64 * Np + bj * 64;
+    const bool ri = bi == k, cj = bj == k;
+    if (k < 0) {
+        float tv[16];
+#pragma unroll
+        for (int it = 0; it < 16; ++it) {
+            const int e = tid + 256 * it, r = bi * 64 + (e >> 6), c = bj * 64 + (e & 63);
+            const bool in = r < N && c < N;
+            tv[it] = float(A[int64_t(min(r, N - 1)) * lda + min(c, N - 1)]) * (in ? 1.0f : 0.0f) +
+                     ((!in && r == c) ? 1.0f : 0.0f);
+        }
+#pragma unroll
+        for (int it = 0; it < 16; ++it) {
+            const int e = tid + 256 * it;
+            T[e >> 6][e & 63] = tv[it];
+        }
+    } else {
+        float tv[16], pv[16], lv[16], rv[16];
+#pragma unroll
+        for (int it = 0; it < 16; ++it) {
+            const int e = tid + 256 * it;
+            tv[it] = Wt[int64_t(e >> 6) * Np + (e & 63)];
+            pv[it] = Pin[e];
+            lv[it] = Cin[int64_t(bi) * 4096 + e];
+            rv[it] = Rin[int64_t(bj) * 4096 + e];
+        }
+#pragma unroll
+        for (int it = 0; it < 16; ++it) {
+            const int e = tid + 256 * it;
+            T[e >> 6][e & 63] = tv[it];
+            P[e >> 6][e & 63] = pv[it];
+            L[e >> 6][e & 63] = lv[it];
+            R[e >> 6][e & 63] = rv[it];
+        }
+    }
+    __syncthreads();
+    if (k >= 0) {
+        floatx4 acc[2][2];
+        if (ri && cj) {
+#pragma unroll
+            for (int it = 0; it < 16; ++it) {
+                const int e = tid + 256 * it;
+                T[e >> 6][e & 63] = P[e >> 6][e & 63];
+            }
+        } else if (ri || cj) {
+            // row k: P A_kj;  column k: -A_ik P
+            if (ri) mm64_acc(P, T, acc, wr, wc, lane);
+            else mm64_acc(T, P, acc, wr, wc, lane);
+            __syncthreads();
+            const float sg = ri ? 1.0f : -1.0f;
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        T[wr + 16 * a + 4 * (lane >> 4) + v][wc + 16 * b + (lane & 15)] = sg * acc[a][b][v];
+        } else {
+            // A_ij - A_ik (P A_kj): first P A_kj into R, then the product with A_ik
+            mm64_acc(P, R, acc, wr, wc, lane);
+            __syncthreads();
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) R[wr + 16 * a + 4 * (lane >> 4) + v][wc + 16 * b + (lane & 15)] = acc[a][b][v];
+            __syncthreads();
+            mm64_acc(L, R, acc, wr, wc, lane);
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) T[wr + 16 * a + 4 * (lane >> 4) + v][wc + 16 * b + (lane & 15)] -= acc[a][b][v];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int it = 0; it < 16; ++it) {
+        const int e = tid + 256 * it;
+        Wt[int64_t(e >> 6) * Np + (e & 63)] = T[e >> 6][e & 63];
+    }
+    if (k + 1 < nt) {
+        if (bi == k + 1)
+#pragma unroll
+            for (int it = 0; it < 16; ++it) {
+                const int e = tid + 256 * it;
+                Rout[int64_t(bj) * 4096 + e] = T[e >> 6][e & 63];
+            }
+        if (bj == k + 1)
+#pragma unroll
+            for (int it = 0; it < 16; ++it) {
+                const int e = tid + 256 * it;
+                Cout[int64_t(bi) * 4096 + e] = T[e >> 6][e & 63];
+            }
+        if (bi == k + 1 && bj == k + 1) {
+            if (tid == 0) bad = 0;
+            __syncthreads();
+            invert64_lds(T, S, L, &bad, tid);
+#pragma unroll
+            for (int it = 0; it < 16; ++it) {
+                const int e = tid + 256 * it;
+                Pout[e] = T[e >> 6][e & 63];
+            }
+            if (tid == 0 && bad && *info == 0) *info = 64 * (k + 1) + 1;
+        }
+    }
+}
+
+// v = X r: X the Gauss-Jordan inverse (row-major, ld Np; zero beyond column N
+// in rows below N), r FP64; one wavefront per row, four columns per lane and
+// step, two steps of loads in flight.
+__global__ __launch_bounds__(256) void inv_apply_kernel(int N, int Np, const float *X, const double *r, float *v)
+{
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (row >= N) return;
+    const float *x = X + int64_t(row) * Np;
+    float p4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int j0 = 4 * lane; j0 < Np; j0 += 512) {
+        const int j1 = j0 + 256;
+        const float4 a0 = *reinterpret_cast<const float4 *>(x + j0);
+        const float4 a1 = j1 < Np ? *reinterpret_cast<const float4 *>(x + j1) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        float rv[8];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            rv[q] = float(r[min(j0 + q, N - 1)]) * (j0 + q < N ? 1.0f : 0.0f);
+            rv[4 + q] = float(r[min(j1 + q, N - 1)]) * (j1 + q < N ? 1.0f : 0.0f);
+        }
+        p4[0] += a0.x * rv[0];
+        p4[1] += a0.y * rv[1];
+        p4[2] += a0.z * rv[2];
+        p4[3] += a0.w * rv[3];
+        p4[0] += a1.x * rv[4];
+        p4[1] += a1.y * rv[5];
+        p4[2] += a1.z * rv[6];
+        p4[3] += a1.w * rv[7];
+    }
+    float s = (p4[0] + p4[1]) + (p4[2] + p4[3]);
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (lane == 0) v[row] = s;
+}
+
 // ---------------------------------------------------------------- refinement pieces
 // r = beta - A x (FP64), one wavefront per row; A row-major as stored.
 template <typename InT>
@@ -1138,11 +1452,12 @@ int launch_panel(int N, float *LU, int k0, int KE, int *piv, int *info, hipStrea
 
 size_t solve_workspace_bytes(int N)
 {
-    const size_t nblk = size_t(N + 63) / 64;
-    return align_up(size_t(N) * N * sizeof(float)) + 2 * align_up(size_t(N) * sizeof(int)) + align_up(16) +
+    const size_t nblk = size_t(N + 63) / 64, Np = size_t(padded64(N));
+    return align_up(Np * Np * sizeof(float)) + 2 * align_up(size_t(N) * sizeof(int)) + align_up(16) +
            align_up(size_t(N) * sizeof(double)) + 2 * align_up(size_t(N) * sizeof(float)) + align_up(64 * sizeof(double)) +
            align_up(size_t(N) * sizeof(double)) + align_up(nblk * 2 * 4096 * sizeof(float)) +
-           align_up(std::max<size_t>(nblk / 2, 1) * 2 * 4096 * sizeof(float));
+           align_up(std::max<size_t>(nblk / 2, 1) * 2 * 4096 * sizeof(float)) +
+           2 * align_up(2 * nblk * 4096 * sizeof(float)) + align_up(2 * 4096 * sizeof(float));
 }
 
 bool lu_without_pivoting_supported(int N) { return N <= 16384; }
@@ -1287,6 +1602,31 @@ hipError_t lu_solve_f32(int N, const float *LU, const float *diag_inv, const flo
     return hipGetLastError();
 }
 
+namespace {
+// The Gauss-Jordan inverse of A (FP64 or FP32, row-major, lda) into w.LU
+// (row-major, ld Np): one loading launch, then one launch per sweep.
+hipError_t gj_inverse(int N, const void *A, int64_t lda, int a_prec, const WS &w, hipStream_t s)
+{
+    const int Np = padded64(N), nt = Np / 64;
+    float *GR[2] = {w.GR, w.GR + int64_t(nt) * 4096}, *GC[2] = {w.GC, w.GC + int64_t(nt) * 4096};
+    float *GP[2] = {w.GP, w.GP + 4096};
+    hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(64), 0, s, w.info);
+    if (a_prec == 0)
+        hipLaunchKernelGGL(gj_step_kernel<double>, dim3(nt * nt), dim3(256), 0, s, N, Np, -1, static_cast<const double *>(A),
+                           lda, w.LU, GR[1], GC[1], GP[1], GR[0], GC[0], GP[0], w.info);
+    else
+        hipLaunchKernelGGL(gj_step_kernel<float>, dim3(nt * nt), dim3(256), 0, s, N, Np, -1, static_cast<const float *>(A),
+                           lda, w.LU, GR[1], GC[1], GP[1], GR[0], GC[0], GP[0], w.info);
+    for (int k = 0; k < nt; ++k) {
+        const int in = k & 1, out = in ^ 1;
+        hipLaunchKernelGGL(gj_step_kernel<float>, dim3(nt * nt), dim3(256), 0, s, N, Np, k,
+                           static_cast<const float *>(w.LU), int64_t(Np), w.LU, GR[in], GC[in], GP[in], GR[out],
+                           GC[out], GP[out], w.info);
+    }
+    return hipGetLastError();
+}
+}  // namespace
+
 int mixed_solve(int N, const void *d_A, int64_t lda, int a_prec, const double *d_beta, double *d_x, double tol,
                 int max_iter, void *ws_base, hipStream_t s, SolveResult &res, std::string &msg)
 {
@@ -1319,15 +1659,32 @@ int mixed_solve(int N, const void *d_A, int64_t lda, int a_prec, const double *d
     // means a refactorisation with partial pivoting, as for any other matrix.
     bool pivot = !(na[0] == 0.0 && lu_without_pivoting_supported(N));
     for (;;) {
-        dim3 tg((N + 31) / 32, (N + 31) / 32);
-        if (a_prec == 0)
-            hipLaunchKernelGGL(to_colmajor_kernel<double>, tg, dim3(256), 0, s, N, static_cast<const double *>(d_A), lda, w.LU);
-        else
-            hipLaunchKernelGGL(to_colmajor_kernel<float>, tg, dim3(256), 0, s, N, static_cast<const float *>(d_A), lda, w.LU);
-        if ((e = lu_factor_f32(N, w.LU, w.piv, w.info, w.DI, pivot, s)) != hipSuccess)
-            return fail(-5, "LU factorisation launch", e);
-        if ((N + 63) / 64 >= 2)     // at least one pair of diagonal blocks
-            hipLaunchKernelGGL(pair_inverse_kernel, dim3(2 * ((N + 63) / 64 / 2)), dim3(256), 0, s, N, w.LU, w.DI, w.DI2);
+        // Without interchanges and up to kGJMaxN the explicit inverse (one
+        // matrix-vector product per refinement step); otherwise the LU factor.
+        const bool gj = !pivot && N <= kGJMaxN;
+        if (gj) {
+            if ((e = gj_inverse(N, d_A, lda, a_prec, w, s)) != hipSuccess) return fail(-5, "Gauss-Jordan launch", e);
+        } else {
+            dim3 tg((N + 31) / 32, (N + 31) / 32);
+            if (a_prec == 0)
+                hipLaunchKernelGGL(to_colmajor_kernel<double>, tg, dim3(256), 0, s, N, static_cast<const double *>(d_A), lda, w.LU);
+            else
+                hipLaunchKernelGGL(to_colmajor_kernel<float>, tg, dim3(256), 0, s, N, static_cast<const float *>(d_A), lda, w.LU);
+            if ((e = lu_factor_f32(N, w.LU, w.piv, w.info, w.DI, pivot, s)) != hipSuccess)
+                return fail(-5, "LU factorisation launch", e);
+            if ((N + 63) / 64 >= 2)     // at least one pair of diagonal blocks
+                hipLaunchKernelGGL(pair_inverse_kernel, dim3(2 * ((N + 63) / 64 / 2)), dim3(256), 0, s, N, w.LU, w.DI, w.DI2);
+        }
+        const int Np = padded64(N);
+        // d = (LU)^-1 P rhs, or X rhs
+        auto apply = [&](const double *rhs) {
+            if (gj) {
+                hipLaunchKernelGGL(inv_apply_kernel, dim3((N + 3) / 4), dim3(256), 0, s, N, Np, w.LU, rhs, w.v);
+            } else {
+                hipLaunchKernelGGL(permute_kernel, dim3((N + 255) / 256), dim3(256), 0, s, N, w.perm, rhs, w.v);
+                (void)lu_solve_f32(N, w.LU, w.DI, w.DI2, w.v, w.v2, s);
+            }
+        };
         // the permutation from the interchange sequence (host, O(N)); none without
         // pivoting, and then no wait here either: the zero-pivot flag is read with
         // the first synchronisation the refinement makes anyway
@@ -1345,7 +1702,7 @@ int mixed_solve(int N, const void *d_A, int64_t lda, int a_prec, const double *d
         for (int i = 0; i < N; ++i) perm[i] = i;
         if (pivot)
             for (int j = 0; j < N; ++j) std::swap(perm[j], perm[piv[j]]);
-        if ((e = hipMemcpyAsync(w.perm, perm.data(), N * sizeof(int), hipMemcpyHostToDevice, s)) != hipSuccess)
+        if (!gj && (e = hipMemcpyAsync(w.perm, perm.data(), N * sizeof(int), hipMemcpyHostToDevice, s)) != hipSuccess)
             return fail(-5, "permutation upload", e);
 
         auto residual = [&]() {
@@ -1353,9 +1710,8 @@ int mixed_solve(int N, const void *d_A, int64_t lda, int a_prec, const double *d
             else launch_residual<float>(N, d_A, lda, d_x, d_beta, w.r, s);
         };
         double red[4];
-        // x0 = LU \ beta
-        hipLaunchKernelGGL(permute_kernel, dim3((N + 255) / 256), dim3(256), 0, s, N, w.perm, d_beta, w.v);
-        (void)lu_solve_f32(N, w.LU, w.DI, w.DI2, w.v, w.v2, s);
+        // x0 = LU \ beta (or X beta)
+        apply(d_beta);
         hipLaunchKernelGGL(update_norms_kernel, dim3(1), dim3(1024), 0, s, N, d_x, w.v, d_beta, d_beta, 0, w.red);
         res.iters = 0;
         res.rel_update = 1.0;
@@ -1371,8 +1727,7 @@ int mixed_solve(int N, const void *d_A, int64_t lda, int a_prec, const double *d
         bool stalled = false, zero_pivot = false;
         for (int it = 0; it < max_iter; ++it) {
             residual();
-            hipLaunchKernelGGL(permute_kernel, dim3((N + 255) / 256), dim3(256), 0, s, N, w.perm, w.r, w.v);
-            (void)lu_solve_f32(N, w.LU, w.DI, w.DI2, w.v, w.v2, s);
+            apply(w.r);
             hipLaunchKernelGGL(update_norms_kernel, dim3(1), dim3(1024), 0, s, N, d_x, w.v, w.r, d_beta, 1, w.red);
             if ((e = hipMemcpyAsync(red, w.red, sizeof red, hipMemcpyDeviceToHost, s)) != hipSuccess ||
                 (!info_read && (e = hipMemcpyAsync(&info, w.info, sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess) ||

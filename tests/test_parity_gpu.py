@@ -186,8 +186,8 @@ def test_rhs_matches_oracle(ctx, method, R, G):
 
 
 # ------------------------------------------------------------------ solve
-SOLVE_SIZES = [(100, "fp64"), (256, "fp64"), (200, "fp32"), (1000, "fp64"), (2500, "fp64"), (4500, "fp32"),
-               (9000, "fp64")]
+SOLVE_SIZES = [(20, "fp64"), (65, "fp32"), (100, "fp64"), (256, "fp64"), (200, "fp32"), (1000, "fp64"),
+               (2500, "fp64"), (4096, "fp64"), (4500, "fp32"), (9000, "fp64")]
 
 
 def skew_perturbed(A, seed):
