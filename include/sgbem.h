@@ -124,7 +124,8 @@ sgbem_status sgbem_ctx_memory(sgbem_ctx ctx, int64_t *held_bytes, int64_t *budge
  *                          near-pair matrices and the cached near-pair table;
  *  SGBEM_MEM_RHS_DIRECT:   sgbem_rhs_direct with n_gauss points: node geometry and
  *                          the double-layer sweep's workspace;
- *  SGBEM_MEM_SOLVE:        sgbem_solve of order N: 4 N^2 + O(N) bytes.
+ *  SGBEM_MEM_SOLVE:        sgbem_solve of order N: 4 N_p^2 + about 1.8 N_p KB,
+ *                          N_p = N rounded up to a multiple of 64.
  * n_ctrl: control points of the B-spline curve of the call (0 for a polar
  * curve); beyond 64 they are copied to the device, 24 n_ctrl + 8 bytes more.
  * Errors: E_INVAL. */
@@ -368,7 +369,9 @@ sgbem_status sgbem_batch_free(sgbem_ctx ctx, sgbem_batch batch);
  *  d_A:     device, row-major, lda, FP64 or FP32 per a_prec; not modified.
  *  d_beta:  device [N] FP64.    d_x: device [N] FP64 (output).
  *  info:    host, may be NULL; written before return (the call synchronises).
- * Workspace (4 N^2 + O(N) bytes) is allocated in the context and kept.
+ * Workspace (4 N^2 + O(N) bytes, sgbem_memory_need) is allocated in the
+ * context and kept, as is a small pinned host buffer the kernels write the
+ * refinement's results to.
  * Errors: E_INVAL, E_NOMEM, E_SINGULAR (zero pivot), E_NOCONV (x holds the
  *      last iterate), E_DEVICE.
  */

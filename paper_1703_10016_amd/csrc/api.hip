@@ -97,6 +97,15 @@ void ctx_free(sgbem_ctx c, void *p, size_t bytes)
     c->held -= bytes;
 }
 
+sgbem_status ensure_hbuf(sgbem_ctx c)
+{
+    if (c->hbuf) return SGBEM_OK;
+    void *p = nullptr;
+    HIPCHK(hipHostMalloc(&p, kSolveHostDoubles * sizeof(double), hipHostMallocCoherent));
+    c->hbuf = static_cast<double *>(p);
+    return SGBEM_OK;
+}
+
 sgbem_status ensure(sgbem_ctx c, DevBuf &b, size_t bytes)
 {
     if (b.bytes >= bytes) return SGBEM_OK;
@@ -568,6 +577,7 @@ sgbem_status sgbem_ctx_destroy(sgbem_ctx c)
         delete b;
     }
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+    if (c->hbuf) (void)hipHostFree(c->hbuf);
     delete c;
     return SGBEM_OK;
 }
@@ -1133,9 +1143,11 @@ sgbem_status sgbem_solve(sgbem_ctx c, int32_t N, const void *d_A, int64_t lda, i
     const size_t bytes = solve_workspace_bytes(N);
     sgbem_status st = ensure(c, c->solve_ws, bytes);
     if (st) return st;
+    if ((st = ensure_hbuf(c))) return st;
     SolveResult res;
     std::string msg;
-    const int rc = mixed_solve(N, d_A, lda, a_prec, d_beta, d_x, tol, max_iter, c->solve_ws.ptr, c->stream, res, msg);
+    const int rc = mixed_solve(N, d_A, lda, a_prec, d_beta, d_x, tol, max_iter, c->solve_ws.ptr, c->hbuf, c->stream,
+                               res, msg);
     if (info) {
         info->iters = res.iters;
         info->status = rc;

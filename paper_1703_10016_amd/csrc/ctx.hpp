@@ -83,6 +83,8 @@ struct sgbem_ctx_s {
     // device bytes held by the context (buffers, tables, owned rule blocks,
     // batches) and the limit set at creation (0: none)
     uint64_t held = 0, budget = 0;
+    // pinned host buffer the solve's kernels write their results to (made on first use)
+    double *hbuf = nullptr;
     sgbem::DevBuf geo, geo16, nearL, params, solve_ws, dl;
     std::vector<sgbem_rules_s *> rules;
     std::vector<sgbem_batch_s *> batches;
@@ -105,6 +107,9 @@ namespace sgbem {
 // everything else the context holds unchanged, when the grown buffer would
 // exceed the context's budget.
 sgbem_status ensure(sgbem_ctx c, DevBuf &b, size_t bytes);
+
+// The context's pinned host buffer for the solve (hipHostMalloc on first use).
+sgbem_status ensure_hbuf(sgbem_ctx c);
 
 // Allocation size of a context buffer of `bytes` (at least 4096, a multiple of 4096).
 size_t buf_bytes(size_t bytes);

@@ -315,7 +315,8 @@ sgbem_completion run(sgbem_server s, Worker &w, Req *q)
         }
         if (st == SGBEM_OK) {
             SolveResult res;
-            st = sgbem_status(mixed_solve(N, dA, N, prec, dbeta, dx, s->cfg.tol, s->cfg.max_iter, dws, w.stream, res, msg));
+            st = sgbem_status(mixed_solve(N, dA, N, prec, dbeta, dx, s->cfg.tol, s->cfg.max_iter, dws, w.ctx->hbuf,
+                                          w.stream, res, msg));
             c.iters = res.iters;
             c.backward_err = res.backward_err;
             if (st == SGBEM_OK || st == SGBEM_E_NOCONV) {
@@ -439,8 +440,10 @@ sgbem_status sgbem_server_create(const sgbem_server_config *cfg, sgbem_server *o
             set_err(st, std::string("stream: ") + hipGetErrorString(e));
         }
         if (st == SGBEM_OK) st = sgbem_ctx_create(cfg->device, w.stream, 0, &w.ctx);
-        // geometry buffer for the largest request, so that no slot reallocates while serving
+        // geometry buffer for the largest request, so that no slot reallocates while serving,
+        // and the solve's pinned host buffer
         if (st == SGBEM_OK) st = ensure(w.ctx, w.ctx->geo, size_t(cfg->max_N) * 2 * 3 * sizeof(double));
+        if (st == SGBEM_OK) st = ensure_hbuf(w.ctx);
         if (st != SGBEM_OK) {
             const std::string m = sgbem_last_error();
             teardown(s);

@@ -36,6 +36,17 @@ struct WS {
 // Order padded to whole 64 x 64 tiles (the Gauss-Jordan inverse works on tiles).
 int padded64(int N) { return (N + 63) / 64 * 64; }
 
+// Control block of the batched refinement (doubles, written by the device):
+//  [0] max |A_ij - A_ji|   [1] ||A||_inf   [2] previous ||d|| / ||x||   [3] stop reason
+//  (0 running, 1 converged, 2 stalled, 3 not finite, 4 zero pivot, 5 not symmetric)
+//  [4] steps taken   [5] last ||d|| / ||x||   [6] last backward error
+enum { CTL_ASYM = 0, CTL_NORMA = 1, CTL_PREV = 2, CTL_STOP = 3, CTL_ITERS = 4, CTL_REL = 5, CTL_BWD = 6, CTL_SIZE = 8 };
+
+// True when a batched refinement has stopped (or the matrix is not symmetric):
+// the remaining kernels of the batch return at once.
+__device__ __forceinline__ bool ctl_stopped(const double *ctl) { return ctl && (ctl[CTL_STOP] != 0.0 || ctl[CTL_ASYM] != 0.0); }
+
+
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 WS carve(void *base, int N)
@@ -1017,46 +1028,56 @@ __device__ __forceinline__ void mm64_acc(const float (*X)[65], const float (*Y)[
     }
 }
 
+// Inverse of the 16 x 16 block B = T[q .. q+15][q .. q+15] by wavefront 0 into S:
+// lane r (r < 16) holds row r in registers; per pivot the pivot row reaches
+// every lane by readlane (scalar registers, no LDS) and each entry takes one
+// FMA: with t = -B_rp / B_pp off the pivot row and t = 1 / B_pp - 1 on it,
+// B_rc + t B_pc is the swept entry for c != p; column p becomes -B_rp / B_pp,
+// and 1 / B_pp on the pivot.  Returns 1 on a zero or non-finite pivot.
+__device__ __forceinline__ int invert16_wave(const float (*T)[65], int q, float (*S)[17], int lane)
+{
+    const int r = lane & 15;
+    float e[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) e[c] = T[q + r][q + c];
+    int bad = 0;
+#pragma unroll
+    for (int p = 0; p < 16; ++p) {
+        float rp[16];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) rp[c] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(e[c]), p));
+        const float d = rp[p];
+        const bool ok = fabsf(d) > 0.0f && fabsf(d) <= 3.402823466e38f;
+        bad |= ok ? 0 : 1;
+        const float ip = ok ? __builtin_amdgcn_rcpf(d) : 0.0f;
+        const float f = e[p];
+        const float t = (r == p) ? ip - 1.0f : -f * ip;
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+            if (c != p) e[c] = fmaf(t, rp[c], e[c]);
+        e[p] = (r == p) ? ip : t;
+    }
+    if (lane < 16)
+#pragma unroll
+        for (int c = 0; c < 16; ++c) S[r][c] = e[c];
+    return bad;
+}
+
 // In-place inverse of the 64 x 64 LDS tile T by four Gauss-Jordan sweeps of
 // 16 x 16 pivot blocks (the same sweep as above, one level down).  Per sweep:
-// wavefront 0 inverts the pivot block (lane 4 r + g holds entries (r, 4 g .. 4 g + 3),
-// one scalar sweep per pivot, the pivot row and column reaching the lanes by
-// shuffles) into S; then Uh = S T_q (the pivot block's rows, their own columns
-// replaced by S) and, with V = T_{:q} (old), T <- T - V Uh outside the pivot
-// rows and columns, -V Uh in the pivot columns, Uh in the pivot rows.  *bad
-// (LDS, zeroed by the caller) is set on a zero or non-finite pivot.
-__device__ void invert64_lds(Tile64 &T, float (*S)[17], Tile64 &Uh, int *bad, int tid)
+// wavefront 0 inverts the pivot block into S; then Uh = S T_q (the pivot
+// block's rows, their own columns replaced by S) and, with V = T_{:q} (old),
+// T <- T - V Uh outside the pivot rows and columns, -V Uh in the pivot
+// columns, Uh in the pivot rows.  *bad (LDS, zeroed by the caller) is set on a
+// zero or non-finite pivot.
+__device__ __forceinline__ void invert64_lds(Tile64 &T, float (*S)[17], Tile64 &Uh, int *bad, int tid)
 {
     const int wave = tid >> 6, lane = tid & 63;
     const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
+#pragma unroll
     for (int q = 0; q < 64; q += 16) {
         if (wave == 0) {
-            const int r = lane >> 2, g = lane & 3;
-            float e[4];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) e[c] = T[q + r][q + 4 * g + c];
-            int badl = 0;
-#pragma unroll
-            for (int p = 0; p < 16; ++p) {
-                const int pc = p & 3, pg = p >> 2;
-                const float d = __shfl(e[pc], 4 * p + pg);     // T[p][p]
-                const float f = __shfl(e[pc], 4 * r + pg);     // T[r][p]
-                float rp[4];                                   // T[p][4 g + c]
-#pragma unroll
-                for (int c = 0; c < 4; ++c) rp[c] = __shfl(e[c], 4 * p + g);
-                const bool ok = fabsf(d) > 0.0f && fabsf(d) <= 3.402823466e38f;
-                badl |= ok ? 0 : 1;
-                const float ip = ok ? 1.0f / d : 0.0f;
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    const int j = 4 * g + c;
-                    if (j == p) e[c] = (r == p) ? ip : -f * ip;
-                    else e[c] = (r == p) ? rp[c] * ip : e[c] - f * (rp[c] * ip);
-                }
-            }
-#pragma unroll
-            for (int c = 0; c < 4; ++c) S[r][4 * g + c] = e[c];
-            if (badl) *bad = 1;
+            if (invert16_wave(T, q, S, lane) && lane == 0) *bad = 1;
         }
         __syncthreads();
         {
@@ -1127,9 +1148,10 @@ __device__ void invert64_lds(Tile64 &T, float (*S)[17], Tile64 &Uh, int *bad, in
 template <typename InT>
 __global__ __launch_bounds__(256) void gj_step_kernel(int N, int Np, int k, const InT *A, int64_t lda, float *W,
                                                       const float *Rin, const float *Cin, const float *Pin, float *Rout,
-                                                      float *Cout, float *Pout, int *info)
+                                                      float *Cout, float *Pout, int *info, const double *ctl)
 {
     __shared__ Tile64 T, L, R, P;
+    if (ctl[CTL_ASYM] != 0.0) return;   // not symmetric: this inverse will not be used
     __shared__ float S[16][17];
     __shared__ int bad;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -1249,10 +1271,11 @@ __global__ __launch_bounds__(256) void gj_step_kernel(int N, int Np, int k, cons
 // v = X r: X the Gauss-Jordan inverse (row-major, ld Np; zero beyond column N
 // in rows below N), r FP64; one wavefront per row, four columns per lane and
 // step, two steps of loads in flight.
-__global__ __launch_bounds__(256) void inv_apply_kernel(int N, int Np, const float *X, const double *r, float *v)
+__global__ __launch_bounds__(256) void inv_apply_kernel(int N, int Np, const float *X, const double *r, float *v,
+                                                        const double *ctl)
 {
     const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-    if (row >= N) return;
+    if (row >= N || ctl_stopped(ctl)) return;
     const float *x = X + int64_t(row) * Np;
     float p4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     for (int j0 = 4 * lane; j0 < Np; j0 += 512) {
@@ -1283,11 +1306,11 @@ __global__ __launch_bounds__(256) void inv_apply_kernel(int N, int Np, const flo
 // r = beta - A x (FP64), one wavefront per row; A row-major as stored.
 template <typename InT>
 __global__ __launch_bounds__(256) void residual_kernel(int N, const InT *A, int64_t lda, const double *x,
-                                                       const double *beta, double *r)
+                                                       const double *beta, double *r, const double *ctl)
 {
     const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    if (row >= N) return;
+    if (row >= N || ctl_stopped(ctl)) return;
     const InT *a = A + int64_t(row) * lda;
     // eight loads of the row (and of x) in flight per lane, four partial sums
     double p4[4] = {0.0, 0.0, 0.0, 0.0};
@@ -1333,11 +1356,23 @@ __global__ __launch_bounds__(256) void rowabs_kernel(int N, const InT *A, int64_
 // so that a non-finite correction, residual or entry reaches the host's checks.
 __device__ __forceinline__ double nan_max(double a, double b) { return (a > b || a != a) ? a : b; }
 
-// x += d (d FP32), and max-norms: red[0] = |d|_inf, red[1] = |x|_inf, red[2] = |r|_inf, red[3] = |beta|_inf
+// x += d (d FP32), and max-norms: red[0] = |d|_inf, red[1] = |x|_inf, red[2] = |r|_inf, red[3] = |beta|_inf.
+// With a control block (batched refinement): nothing once stopped; otherwise
+// the step's decision, taken as the host would: converged when
+// ||d|| <= tol ||x||, or when the corrections stop shrinking
+// (||d|| > ||d_prev|| / 2) with the backward error at the FP64 level; stalled
+// when they stop shrinking above it; not finite on NaN or overflow; a zero
+// pivot (info) or an asymmetric matrix ends the attempt before the first step.
 __global__ __launch_bounds__(1024) void update_norms_kernel(int N, double *x, const float *d, const double *r,
-                                                            const double *beta, int add, double *red)
+                                                            const double *beta, int add, double *red, double *ctl,
+                                                            const int *info, double tol)
 {
     __shared__ double s[4][16];
+    if (ctl_stopped(ctl)) return;
+    if (ctl && *info != 0) {
+        if (threadIdx.x == 0) ctl[CTL_STOP] = 4.0;
+        return;
+    }
     double m[4] = {0, 0, 0, 0};
     for (int i = threadIdx.x; i < N; i += blockDim.x) {
         double xi = add ? x[i] + double(d[i]) : double(d[i]);
@@ -1356,6 +1391,62 @@ __global__ __launch_bounds__(1024) void update_norms_kernel(int N, double *x, co
         double v = 0.0;
         for (int k = 0; k < int(blockDim.x >> 6); ++k) v = nan_max(v, s[threadIdx.x][k]);
         red[threadIdx.x] = v;
+        if (ctl) s[threadIdx.x][0] = v;
+    }
+    if (ctl) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const double dn = s[0][0], xn = s[1][0], rn = s[2][0], bn = s[3][0];
+            const double rel = dn == 0.0 ? 0.0 : dn / xn;
+            const double bwd = rn / (ctl[CTL_NORMA] * xn + bn);   // of the iterate before this step
+            double stop = 0.0;
+            if (rel <= tol) stop = 1.0;
+            else if (rel > 0.5 * ctl[CTL_PREV]) stop = bwd <= 64 * 1.1102230246251565e-16 ? 1.0 : 2.0;
+            else if (!(rel < 1e300)) stop = 3.0;
+            ctl[CTL_ITERS] += 1.0;
+            ctl[CTL_REL] = rel;
+            ctl[CTL_BWD] = bwd;
+            ctl[CTL_PREV] = rel;
+            ctl[CTL_STOP] = stop;
+        }
+    }
+}
+
+// End of a refinement batch, written straight to the caller's pinned host
+// buffer: out[0 .. CTL_SIZE) = the control block, then |r|_inf, |x|_inf,
+// |beta|_inf of the final iterate (its backward error) and the zero-pivot flag.
+__global__ __launch_bounds__(1024) void final_norms_kernel(int N, const double *r, const double *x, const double *beta,
+                                                           const double *ctl, const int *info, double *out)
+{
+    __shared__ double s[3][16];
+    double m[3] = {0.0, 0.0, 0.0};
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        m[0] = nan_max(m[0], fabs(r[i]));
+        m[1] = nan_max(m[1], fabs(x[i]));
+        m[2] = nan_max(m[2], fabs(beta[i]));
+    }
+    for (int q = 0; q < 3; ++q) {
+        for (int off = 32; off > 0; off >>= 1) m[q] = nan_max(m[q], __shfl_xor(m[q], off));
+        if ((threadIdx.x & 63) == 0) s[q][threadIdx.x >> 6] = m[q];
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        double v = 0.0;
+        for (int k = 0; k < int(blockDim.x >> 6); ++k) v = nan_max(v, s[threadIdx.x][k]);
+        out[CTL_SIZE + threadIdx.x] = v;
+    }
+    if (threadIdx.x < CTL_SIZE) out[threadIdx.x] = ctl[threadIdx.x];
+    if (threadIdx.x == 0) out[CTL_SIZE + 3] = double(*info);
+}
+
+__global__ void ctl_init_kernel(double *ctl)
+{
+    if (threadIdx.x == 0) {
+        ctl[CTL_PREV] = 1e300;
+        ctl[CTL_STOP] = 0.0;
+        ctl[CTL_ITERS] = 0.0;
+        ctl[CTL_REL] = 1.0;
+        ctl[CTL_BWD] = 1.0;
     }
 }
 
@@ -1375,10 +1466,11 @@ __global__ __launch_bounds__(1024) void max_kernel(int N, const double *v, doubl
 }
 
 template <typename InT>
-void launch_residual(int N, const void *A, int64_t lda, const double *x, const double *beta, double *r, hipStream_t s)
+void launch_residual(int N, const void *A, int64_t lda, const double *x, const double *beta, double *r, hipStream_t s,
+                     const double *ctl = nullptr)
 {
     hipLaunchKernelGGL(residual_kernel<InT>, dim3((N + 3) / 4), dim3(256), 0, s, N, static_cast<const InT *>(A), lda,
-                       x, beta, r);
+                       x, beta, r, ctl);
 }
 
 // Exact symmetry test of A (row-major, leading dimension lda): each workgroup
@@ -1605,7 +1697,7 @@ hipError_t lu_solve_f32(int N, const float *LU, const float *diag_inv, const flo
 namespace {
 // The Gauss-Jordan inverse of A (FP64 or FP32, row-major, lda) into w.LU
 // (row-major, ld Np): one loading launch, then one launch per sweep.
-hipError_t gj_inverse(int N, const void *A, int64_t lda, int a_prec, const WS &w, hipStream_t s)
+hipError_t gj_inverse(int N, const void *A, int64_t lda, int a_prec, const WS &w, const double *ctl, hipStream_t s)
 {
     const int Np = padded64(N), nt = Np / 64;
     float *GR[2] = {w.GR, w.GR + int64_t(nt) * 4096}, *GC[2] = {w.GC, w.GC + int64_t(nt) * 4096};
@@ -1613,24 +1705,25 @@ hipError_t gj_inverse(int N, const void *A, int64_t lda, int a_prec, const WS &w
     hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(64), 0, s, w.info);
     if (a_prec == 0)
         hipLaunchKernelGGL(gj_step_kernel<double>, dim3(nt * nt), dim3(256), 0, s, N, Np, -1, static_cast<const double *>(A),
-                           lda, w.LU, GR[1], GC[1], GP[1], GR[0], GC[0], GP[0], w.info);
+                           lda, w.LU, GR[1], GC[1], GP[1], GR[0], GC[0], GP[0], w.info, ctl);
     else
         hipLaunchKernelGGL(gj_step_kernel<float>, dim3(nt * nt), dim3(256), 0, s, N, Np, -1, static_cast<const float *>(A),
-                           lda, w.LU, GR[1], GC[1], GP[1], GR[0], GC[0], GP[0], w.info);
+                           lda, w.LU, GR[1], GC[1], GP[1], GR[0], GC[0], GP[0], w.info, ctl);
     for (int k = 0; k < nt; ++k) {
         const int in = k & 1, out = in ^ 1;
         hipLaunchKernelGGL(gj_step_kernel<float>, dim3(nt * nt), dim3(256), 0, s, N, Np, k,
                            static_cast<const float *>(w.LU), int64_t(Np), w.LU, GR[in], GC[in], GP[in], GR[out],
-                           GC[out], GP[out], w.info);
+                           GC[out], GP[out], w.info, ctl);
     }
     return hipGetLastError();
 }
 }  // namespace
 
 int mixed_solve(int N, const void *d_A, int64_t lda, int a_prec, const double *d_beta, double *d_x, double tol,
-                int max_iter, void *ws_base, hipStream_t s, SolveResult &res, std::string &msg)
+                int max_iter, void *ws_base, double *hbuf, hipStream_t s, SolveResult &res, std::string &msg)
 {
     WS w = carve(ws_base, N);
+    double *ctl = w.red + 40;
     auto fail = [&](int st, const char *m, hipError_t e) {
         msg = std::string(m) + (e != hipSuccess ? std::string(": ") + hipGetErrorString(e) : std::string());
         return st;
@@ -1638,33 +1731,102 @@ int mixed_solve(int N, const void *d_A, int64_t lda, int a_prec, const double *d
     // ||A||_inf for the backward error (one read of A) and the exact symmetry test
     const int ngrid = std::min(N, 1024);
     if (a_prec == 0) {
-        hipLaunchKernelGGL(rowabs_kernel<double>, dim3((N + 3) / 4), dim3(256), 0, s, N, static_cast<const double *>(d_A), lda, w.red + 8);
+        hipLaunchKernelGGL(rowabs_kernel<double>, dim3((N + 3) / 4), dim3(256), 0, s, N, static_cast<const double *>(d_A), lda, w.red + 64);
         hipLaunchKernelGGL(asym_kernel<double>, dim3(ngrid), dim3(256), 0, s, N, static_cast<const double *>(d_A), lda, w.r);
     } else {
-        hipLaunchKernelGGL(rowabs_kernel<float>, dim3((N + 3) / 4), dim3(256), 0, s, N, static_cast<const float *>(d_A), lda, w.red + 8);
+        hipLaunchKernelGGL(rowabs_kernel<float>, dim3((N + 3) / 4), dim3(256), 0, s, N, static_cast<const float *>(d_A), lda, w.red + 64);
         hipLaunchKernelGGL(asym_kernel<float>, dim3(ngrid), dim3(256), 0, s, N, static_cast<const float *>(d_A), lda, w.r);
     }
-    hipLaunchKernelGGL(max_kernel, dim3(1), dim3(1024), 0, s, N, w.red + 8, w.red + 4);
-    hipLaunchKernelGGL(max_kernel, dim3(1), dim3(1024), 0, s, ngrid, w.r, w.red + 3);
-    double na[2];   // max |A_ij - A_ji|, ||A||_inf
+    hipLaunchKernelGGL(max_kernel, dim3(1), dim3(1024), 0, s, N, w.red + 64, ctl + CTL_NORMA);
+    hipLaunchKernelGGL(max_kernel, dim3(1), dim3(1024), 0, s, ngrid, w.r, ctl + CTL_ASYM);
+    if (!hbuf) return fail(-1, "the solve needs a pinned host buffer", hipSuccess);
     hipError_t e;
-    if ((e = hipMemcpyAsync(na, w.red + 3, sizeof na, hipMemcpyDeviceToHost, s)) != hipSuccess ||
-        (e = hipStreamSynchronize(s)) != hipSuccess)
-        return fail(-5, "matrix norm", e);
-    const double normA = na[1];
+    double normA = 0.0;
+    bool na_known = false;
     // A symmetric matrix (the Galerkin matrix is) is first factored without
     // interchanges: stable for a positive definite matrix, the setting of the
     // method.  The FP64-refined solution is accepted only if the refinement
     // converges; a zero pivot or a refinement that stalls short of the target
     // means a refactorisation with partial pivoting, as for any other matrix.
-    bool pivot = !(na[0] == 0.0 && lu_without_pivoting_supported(N));
+    // Up to kGJMaxN the symmetry test is not waited for: the explicit inverse
+    // starts at once and its kernels return at once for an asymmetric matrix,
+    // whose first synchronisation then sends it to partial pivoting.
+    bool pivot;
+    if (N <= kGJMaxN) {
+        pivot = false;
+    } else {
+        double na[2];
+        if ((e = hipMemcpyAsync(na, ctl, sizeof na, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+            (e = hipStreamSynchronize(s)) != hipSuccess)
+            return fail(-5, "matrix norm", e);
+        normA = na[1];
+        na_known = true;
+        pivot = !(na[0] == 0.0 && lu_without_pivoting_supported(N));
+    }
     for (;;) {
         // Without interchanges and up to kGJMaxN the explicit inverse (one
         // matrix-vector product per refinement step); otherwise the LU factor.
         const bool gj = !pivot && N <= kGJMaxN;
         if (gj) {
-            if ((e = gj_inverse(N, d_A, lda, a_prec, w, s)) != hipSuccess) return fail(-5, "Gauss-Jordan launch", e);
-        } else {
+            // Refinement in batches of up to four steps with the decisions on the
+            // device (update_norms_kernel) and one synchronisation per batch,
+            // whose last kernel writes the control block, the backward-error
+            // norms of the final iterate and the zero-pivot flag to hbuf.
+            const int Np = padded64(N);
+            if ((e = gj_inverse(N, d_A, lda, a_prec, w, ctl, s)) != hipSuccess) return fail(-5, "Gauss-Jordan launch", e);
+            hipLaunchKernelGGL(ctl_init_kernel, dim3(1), dim3(64), 0, s, ctl);
+            hipLaunchKernelGGL(inv_apply_kernel, dim3((N + 3) / 4), dim3(256), 0, s, N, Np, w.LU, d_beta, w.v, ctl);
+            hipLaunchKernelGGL(update_norms_kernel, dim3(1), dim3(1024), 0, s, N, d_x, w.v, d_beta, d_beta, 0, w.red,
+                               static_cast<double *>(nullptr), w.info, tol);
+            int launched = 0;
+            volatile double *hb = hbuf;
+            for (;;) {
+                const int nb = std::min(4, max_iter - launched);
+                for (int b = 0; b < nb; ++b) {
+                    if (a_prec == 0) launch_residual<double>(N, d_A, lda, d_x, d_beta, w.r, s, ctl);
+                    else launch_residual<float>(N, d_A, lda, d_x, d_beta, w.r, s, ctl);
+                    hipLaunchKernelGGL(inv_apply_kernel, dim3((N + 3) / 4), dim3(256), 0, s, N, Np, w.LU, w.r, w.v, ctl);
+                    hipLaunchKernelGGL(update_norms_kernel, dim3(1), dim3(1024), 0, s, N, d_x, w.v, w.r, d_beta, 1,
+                                       w.red, ctl, w.info, tol);
+                }
+                launched += nb;
+                if (a_prec == 0) launch_residual<double>(N, d_A, lda, d_x, d_beta, w.r, s);
+                else launch_residual<float>(N, d_A, lda, d_x, d_beta, w.r, s);
+                hipLaunchKernelGGL(final_norms_kernel, dim3(1), dim3(1024), 0, s, N, w.r, d_x, d_beta, ctl, w.info, hbuf);
+                if ((e = hipGetLastError()) != hipSuccess || (e = hipStreamSynchronize(s)) != hipSuccess)
+                    return fail(-5, "refinement", e);
+                if (hb[CTL_ASYM] != 0.0 || hb[CTL_STOP] != 0.0 || launched >= max_iter) break;
+            }
+            normA = hb[CTL_NORMA];
+            na_known = true;
+            if (hb[CTL_ASYM] != 0.0) {   // not symmetric: partial pivoting from the start
+                pivot = true;
+                continue;
+            }
+            const double stop = hb[CTL_STOP];
+            res.pivoted = false;
+            res.iters = int(hb[CTL_ITERS]);
+            res.rel_update = hb[CTL_REL];
+            res.backward_err = hb[CTL_BWD];
+            // a zero pivot, a stalled or non-finite refinement, or no convergence
+            // within max_iter steps: refactor with partial pivoting
+            if (hb[CTL_SIZE + 3] != 0.0 || (stop != 1.0 && max_iter > 0)) {
+                pivot = true;
+                continue;
+            }
+            res.backward_err = hb[CTL_SIZE] / (normA * hb[CTL_SIZE + 1] + hb[CTL_SIZE + 2]);
+            if (stop != 1.0) return fail(-4, "iterative refinement did not reach the tolerance", hipSuccess);
+            return 0;
+        }
+        if (!na_known) {    // (every way here has read the norm; kept for safety)
+            double na[2];
+            if ((e = hipMemcpyAsync(na, ctl, sizeof na, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+                (e = hipStreamSynchronize(s)) != hipSuccess)
+                return fail(-5, "matrix norm", e);
+            normA = na[1];
+            na_known = true;
+        }
+        {
             dim3 tg((N + 31) / 32, (N + 31) / 32);
             if (a_prec == 0)
                 hipLaunchKernelGGL(to_colmajor_kernel<double>, tg, dim3(256), 0, s, N, static_cast<const double *>(d_A), lda, w.LU);
@@ -1675,15 +1837,10 @@ int mixed_solve(int N, const void *d_A, int64_t lda, int a_prec, const double *d
             if ((N + 63) / 64 >= 2)     // at least one pair of diagonal blocks
                 hipLaunchKernelGGL(pair_inverse_kernel, dim3(2 * ((N + 63) / 64 / 2)), dim3(256), 0, s, N, w.LU, w.DI, w.DI2);
         }
-        const int Np = padded64(N);
-        // d = (LU)^-1 P rhs, or X rhs
+        // d = (LU)^-1 P rhs
         auto apply = [&](const double *rhs) {
-            if (gj) {
-                hipLaunchKernelGGL(inv_apply_kernel, dim3((N + 3) / 4), dim3(256), 0, s, N, Np, w.LU, rhs, w.v);
-            } else {
-                hipLaunchKernelGGL(permute_kernel, dim3((N + 255) / 256), dim3(256), 0, s, N, w.perm, rhs, w.v);
-                (void)lu_solve_f32(N, w.LU, w.DI, w.DI2, w.v, w.v2, s);
-            }
+            hipLaunchKernelGGL(permute_kernel, dim3((N + 255) / 256), dim3(256), 0, s, N, w.perm, rhs, w.v);
+            (void)lu_solve_f32(N, w.LU, w.DI, w.DI2, w.v, w.v2, s);
         };
         // the permutation from the interchange sequence (host, O(N)); none without
         // pivoting, and then no wait here either: the zero-pivot flag is read with
@@ -1702,7 +1859,7 @@ int mixed_solve(int N, const void *d_A, int64_t lda, int a_prec, const double *d
         for (int i = 0; i < N; ++i) perm[i] = i;
         if (pivot)
             for (int j = 0; j < N; ++j) std::swap(perm[j], perm[piv[j]]);
-        if (!gj && (e = hipMemcpyAsync(w.perm, perm.data(), N * sizeof(int), hipMemcpyHostToDevice, s)) != hipSuccess)
+        if ((e = hipMemcpyAsync(w.perm, perm.data(), N * sizeof(int), hipMemcpyHostToDevice, s)) != hipSuccess)
             return fail(-5, "permutation upload", e);
 
         auto residual = [&]() {
@@ -1712,7 +1869,8 @@ int mixed_solve(int N, const void *d_A, int64_t lda, int a_prec, const double *d
         double red[4];
         // x0 = LU \ beta (or X beta)
         apply(d_beta);
-        hipLaunchKernelGGL(update_norms_kernel, dim3(1), dim3(1024), 0, s, N, d_x, w.v, d_beta, d_beta, 0, w.red);
+        hipLaunchKernelGGL(update_norms_kernel, dim3(1), dim3(1024), 0, s, N, d_x, w.v, d_beta, d_beta, 0, w.red,
+                           static_cast<double *>(nullptr), w.info, 0.0);
         res.iters = 0;
         res.rel_update = 1.0;
         res.backward_err = 1.0;
@@ -1728,7 +1886,8 @@ int mixed_solve(int N, const void *d_A, int64_t lda, int a_prec, const double *d
         for (int it = 0; it < max_iter; ++it) {
             residual();
             apply(w.r);
-            hipLaunchKernelGGL(update_norms_kernel, dim3(1), dim3(1024), 0, s, N, d_x, w.v, w.r, d_beta, 1, w.red);
+            hipLaunchKernelGGL(update_norms_kernel, dim3(1), dim3(1024), 0, s, N, d_x, w.v, w.r, d_beta, 1, w.red,
+                               static_cast<double *>(nullptr), w.info, 0.0);
             if ((e = hipMemcpyAsync(red, w.red, sizeof red, hipMemcpyDeviceToHost, s)) != hipSuccess ||
                 (!info_read && (e = hipMemcpyAsync(&info, w.info, sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess) ||
                 (e = hipStreamSynchronize(s)) != hipSuccess)

@@ -19,8 +19,11 @@ struct SolveResult {
 size_t solve_workspace_bytes(int N);
 
 // Returns an sgbem_status value; synchronises `stream` before returning.
+// hbuf: pinned host memory of kSolveHostDoubles doubles (hipHostMalloc), which
+// the last kernel of each refinement batch writes.
+constexpr int kSolveHostDoubles = 16;
 int mixed_solve(int N, const void *d_A, int64_t lda, int a_prec, const double *d_beta, double *d_x, double tol,
-                int max_iter, void *ws, hipStream_t stream, SolveResult &res, std::string &msg);
+                int max_iter, void *ws, double *hbuf, hipStream_t stream, SolveResult &res, std::string &msg);
 
 // Pieces, also used on their own by the tests and the serving loop.
 // FP32 LU in place (column-major, ld = N), with partial pivoting or (pivot
