@@ -14,7 +14,8 @@ Also measured in the same run (reported beside the headline value):
    error is not larger than the fast form's (errors of the coefficient vector
    against an element-by-element G = 8 solution), and the speedup;
  * latency of a solve request (assemble + right-hand side + mixed-precision
-   solve), p50 / p99 over repeated requests;
+   solve: FP32 explicit inverse by Gauss-Jordan, FP64 refinement), p50 / p99
+   over repeated requests;
  * the fused kernel's duration from HIP events on its stream -> roofline;
  * FP32 and FP64 throughput at N = 16384 (a star curve, one assembly each);
  * the direct formulation's right-hand side (double-layer sweep, eq. final_b2)
@@ -23,7 +24,11 @@ Also measured in the same run (reported beside the headline value):
  * a batch of 256 star curves (N in [128, 2048], p in {2, 3}, FP32) in one
    autotuned persistent launch replayed from a HIP graph, against 256
    sequential single-curve launches;
- * the CPU oracle (element-by-element, FP64, C + OpenMP) on a sample of rows.
+ * the CPU oracle (element-by-element, FP64, C + OpenMP) on a sample of rows,
+   and the oracle's G = 24 solution as a second reference of the equal-error
+   comparison;
+ * a serving sweep (Poisson arrivals at 10 .. 1000 req/s, about 10 s of
+   arrivals per rate, 100 to 2000 requests).
 """
 from __future__ import annotations
 
@@ -74,20 +79,31 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def serve_sweep(S, rates, n_req, workers, one_at_a_time=True):
-    """Open-loop serving: for each rate, n_req star requests with Poisson
-    arrivals (N log-uniform in [256, 8192], p in {2, 3, 4}) go to one server;
-    each is assembled (fast form, FP64), its right-hand side formed and solved
-    (FP32 LU + FP64 refinement).  Latency runs from the request's arrival to
+def requests_for_rate(rate, n_req, seconds):
+    """Requests sent at one arrival rate: n_req if given, else the rate times an
+    arrival window of `seconds`, between 100 and 2000 (at least 1000 completions
+    from 100 req/s up, so that p99 is a percentile and not the largest sample)."""
+    if n_req > 0:
+        return n_req
+    return int(min(2000, max(100, round(rate * seconds))))
+
+
+def serve_sweep(S, rates, n_req, workers, seconds=10.0, one_at_a_time=True):
+    """Open-loop serving: for each rate, star requests with Poisson arrivals
+    (N log-uniform in [256, 8192], p in {2, 3, 4}) go to one server; each is
+    assembled (fast form, FP64), its right-hand side formed and solved (FP32
+    factor + FP64 refinement).  Latency runs from the request's arrival to
     alpha in host memory; solves/s is completions over the span from the
     first arrival to the last completion."""
     import synth
     budget = 24 << 30
-    out = {"workers": workers, "budget_bytes": budget, "requests_per_rate": n_req, "matrix_precision": "fp64"}
+    out = {"workers": workers, "budget_bytes": budget,
+           "requests_per_rate": {str(r): requests_for_rate(r, n_req, seconds) for r in rates},
+           "matrix_precision": "fp64"}
     out["rates"] = []
     rows_by_workers = {}
     for w in ([workers, 1] if one_at_a_time else [workers]):
-        out_w = _serve_rates(S, rates if w == workers else rates[-1:], n_req, w, budget)
+        out_w = _serve_rates(S, rates if w == workers else rates[-1:], n_req, w, budget, seconds)
         rows_by_workers[w] = out_w
     out["rates"] = rows_by_workers[workers]
     if one_at_a_time:
@@ -101,7 +117,7 @@ def serve_sweep(S, rates, n_req, workers, one_at_a_time=True):
     return out
 
 
-def _serve_rates(S, rates, n_req, workers, budget):
+def _serve_rates(S, rates, n_req, workers, budget, seconds):
     import synth
     rows = []
     srv = S.sgbem_server_create(workers=workers, budget_bytes=budget, precision=S.SGBEM_FP64, max_N=8192,
@@ -115,7 +131,7 @@ def _serve_rates(S, rates, n_req, workers, budget):
             S.sgbem_server_submit(srv, cv, p, N, synth.g_exp_cos(xy[:, 0], xy[:, 1]), xw[i], 0.0, i)
         _serve_drain(S, srv, len(warm))
         for rate in rates:
-            arrivals, probs = synth.config_serving(rate, n_req)
+            arrivals, probs = synth.config_serving(rate, requests_for_rate(rate, n_req, seconds))
             gs = []
             for pb in probs:   # the client's boundary data at the fast form's node points
                 xy = S.sgbem_node_points_host(pb.curve, pb.N, 1)
@@ -138,7 +154,7 @@ def _serve_rates(S, rates, n_req, workers, budget):
                    "peak_in_flight": after["peak_in_flight"], "peak_bytes": after["peak_bytes"],
                    "rules_misses": after["rules_misses"] - before["rules_misses"]}
             rows.append(row)
-            log(f"[bench] serving ({workers} slot{'s' if workers > 1 else ''}) rate {rate:g}/s x {n_req}: "
+            log(f"[bench] serving ({workers} slot{'s' if workers > 1 else ''}) rate {rate:g}/s x {len(probs)}: "
                 f"p50 {row['p50_ms']:.2f} ms p99 {row['p99_ms']:.2f} ms, "
                 f"{row['solves_per_s']:.1f} solves/s, queue {row['mean_queue_ms']:.1f} ms, "
                 f"{len(ok)}/{len(comp)} ok")
@@ -171,7 +187,9 @@ def main():
     ap.add_argument("--no-scale", action="store_true", help="skip the N = 16384 points")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-curve batch")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop sweep")
-    ap.add_argument("--serve-requests", type=int, default=100, help="requests per arrival rate (2000: full sweep)")
+    ap.add_argument("--serve-requests", type=int, default=0,
+                    help="requests per arrival rate (0: the rate times --serve-seconds, within [100, 2000])")
+    ap.add_argument("--serve-seconds", type=float, default=10.0, help="arrival window per rate when --serve-requests is 0")
     ap.add_argument("--serve-rates", type=str, default="10,30,100,300,1000", help="arrival rates, req/s")
     ap.add_argument("--serve-workers", type=int, default=8)
     ap.add_argument("--solves", type=int, default=60)
@@ -397,8 +415,9 @@ def main():
                            "tflops": fl / (kms * 1e-3) / 1e12, "frac_of_vector_peak": fl / (kms * 1e-3) / pk}
             log(f"[bench] star N={Nb} WQ {prec}: {kms:.3f} ms -> {Nb*Nb/(kms*1e-3):.3e} entries/s, "
                 f"{fl/(kms*1e-3)/1e12:.2f} TFLOP/s")
-            # FP32 LU with partial pivoting + FP64 refinement to 1e-10 on this matrix; the LU is
-            # (2/3) N^3 flop, reported against the FP32 MFMA peak over the whole solve's wall time
+            # FP32 LU (without interchanges for this symmetric matrix unless that attempt fails) +
+            # FP64 refinement to 1e-10; the LU is (2/3) N^3 flop, reported against the FP32 MFMA
+            # peak over the whole solve's wall time
             bb = ctx.rhs(star, p, Nb, g, method="wq", n_ref=R)
             ctx.solve(Ab, bb, tol=1e-10, max_iter=30)                  # warm: workspace, code objects
             sms = []
@@ -409,12 +428,13 @@ def main():
                 torch.cuda.synchronize()
                 sms.append((time.perf_counter() - t0) * 1e3)
             lu_fl = 2.0 / 3.0 * Nb ** 3
-            scale[prec].update({"solve_ms": min(sms), "solve_iters": sinfo.iters,
+            scale[prec].update({"solve_ms": min(sms), "solve_iters": sinfo.iters, "solve_pivoted": int(sinfo.pivoted),
                                 "solve_backward_err": sinfo.backward_err,
                                 "lu_tflops_over_solve": lu_fl / (min(sms) * 1e-3) / 1e12,
                                 "lu_frac_of_fp32_peak": lu_fl / (min(sms) * 1e-3) / PEAK_FP32})
             log(f"[bench] star N={Nb} solve ({prec} matrix): {min(sms):.1f} ms, {sinfo.iters} refinement steps, "
-                f"backward err {sinfo.backward_err:.1e}; LU {lu_fl/(min(sms)*1e-3)/1e12:.1f} TFLOP/s over the solve")
+                f"pivoted {sinfo.pivoted}, backward err {sinfo.backward_err:.1e}; "
+                f"LU {lu_fl/(min(sms)*1e-3)/1e12:.1f} TFLOP/s over the solve")
             del Ab, bb, xb
         torch.cuda.empty_cache()
 
@@ -526,7 +546,7 @@ def main():
     serving = None
     if not args.no_serving:
         serving = serve_sweep(S, [float(r) for r in args.serve_rates.split(",")], args.serve_requests,
-                              args.serve_workers)
+                              args.serve_workers, args.serve_seconds)
 
     # ---------------------------------------------------------------- CPU oracle
     cpu = None
@@ -551,6 +571,28 @@ def main():
                "sample": f"element-by-element oracle (FP64, G={G_eq}, 16x16 near rule) on {nrows} rows of the "
                          f"N={N} ellipse matrix taken cyclically ({nrows*N} entries, {dt:.1f} s)"}
         log(f"[bench] CPU oracle: {cpu['value']:.3e} entries/s on {cpu['cores']} threads ({dt:.1f} s)")
+        # The survey's reference for the equal-error comparison: alpha from the oracle's plain
+        # form at G = 24 (FP64, upper triangle, mirrored), solved by LAPACK on the host.
+        t0 = time.perf_counter()
+        P24 = oebe.EBEProblem(curve, p, N, 24)
+        iu, ju = np.triu_indices(N)
+        v24 = P24.entries(iu, ju, nthreads)
+        A24 = np.zeros((N, N))
+        A24[iu, ju] = v24
+        A24[ju, iu] = v24
+        a24 = np.linalg.solve(A24, P24.rhs(g))
+        err24 = lambda a: float(np.linalg.norm(a - a24) / np.linalg.norm(a24))
+        for row in front["wq"]:
+            row["solution_err_oracle_g24"] = err24(sol_wq[row["n_ref"]])
+        for row in front["ebe"]:
+            row["solution_err_oracle_g24"] = err24(sol_ebe[row["n_gauss"]])
+        t_m = matched("solution_err_oracle_g24", front["wq"][R - 1]["solution_err_oracle_g24"])
+        speedup_interp["solution_err_oracle_g24"] = t_m / front["wq"][R - 1]["us_per_step"] if t_m else None
+        cpu["reference_g24_s"] = time.perf_counter() - t0
+        log(f"[bench] equal error against the oracle's G=24 solution ({cpu['reference_g24_s']:.1f} s on the host): WQ " +
+            " ".join(f"n_ref={row['n_ref']}:{row['solution_err_oracle_g24']:.2e}" for row in front["wq"]) + "; EBE " +
+            " ".join(f"G={row['n_gauss']}:{row['solution_err_oracle_g24']:.2e}" for row in front["ebe"]) +
+            f" -> log-interpolated speedup {speedup_interp['solution_err_oracle_g24']}")
 
     out = {
         "metric": "Galerkin entries/sec, WQ row vs element-by-element at equal err; p99 solve latency",
@@ -569,7 +611,8 @@ def main():
                                "B-splines p=3, N=1024; weighted-quadrature row assembly n_ref=1, FP64",
                    "p": p, "N": N, "n_ref": R, "step": "geometry + fused WQ assembly, HIP graph replay"},
         "equal_error": {"wq_solution_err": err_wq, "ebe_solution_err": err_ebe, "ebe_gauss_order": G_eq,
-                        "reference": "element-by-element G=8 solution (FP64)",
+                        "reference": "element-by-element G=8 solution (FP64, this GPU); solution_err_oracle_g24: "
+                                     "against the CPU oracle's element-by-element G=24 solution",
                         "interior_points": "16 points inside the ellipse, error of u_h against g",
                         "front": front, "speedup_log_interpolated": speedup_interp},
         "ebe": {"entries_per_s": ebe_rate, "ms_per_step": ms_ebe, "n_gauss": G_eq},
