@@ -29,6 +29,10 @@ Parts:
   the outer integral replaced by the value at the Greville abscissae.
 * ``open_arc``: the singular rule of Section 4.2 on an open interval (the
   paper's own setting of its Table 1 tests).
+* ``wq_knots`` (O6): the weighted-quadrature rules and the row assembly on
+  non-uniform periodic knots (Section 3): Algorithm 1 per test function,
+  Algorithm 2 per source with the full table of singular weights, modified
+  moments from the local pieces of the Cox-de Boor recurrence.
 
 Solutions of A alpha = beta (eq. sistlin) in the tests use LAPACK's FP64
 solve (numpy) directly; there is no oracle solver of its own.
