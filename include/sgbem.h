@@ -15,8 +15,9 @@
  *   find phi_h = sum_j alpha_j B_j with
  *   A alpha = beta,  A_ij = -(1/2pi) int int B_i(s) J(s) ln|f(s)-f(t)| B_j(t) J(t) dt ds
  *   (eqs. Gmatrix, final_1),  beta_i = int B_i(s) J(s) g(f(s)) ds (eq. final_b1),
- * with B_i the cyclic B-splines of degree p on N uniform elements of the
- * parameter interval [0, 1) (Section 3), f the curve and J = |f'| (eq. J).
+ * with B_i the cyclic B-splines of degree p on N elements of the parameter
+ * interval [0, 1) (Section 3; uniform, or non-uniform periodic knots given to
+ * sgbem_weights), f the curve and J = |f'| (eq. J).
  *
  * Conventions for every call:
  *  - every function returns an sgbem_status; no C++ exception crosses the ABI;
@@ -28,7 +29,8 @@
  *    stated otherwise; a context must be used from one host thread at a time
  *    (a server, sgbem_server_*, may be called from any thread);
  *  - matrices are row-major: entry (i, j) at ptr[i * lda + j], lda >= N;
- *  - basis index convention: B_i is supported on [i/N, (i+p+1)/N) mod 1.
+ *  - basis index convention: B_i is supported on [tau_i, tau_{i+p+1}) mod 1
+ *    (tau_k = k / N for uniform knots).
  */
 #ifndef SGBEM_H
 #define SGBEM_H
@@ -125,12 +127,14 @@ sgbem_status sgbem_ctx_memory(sgbem_ctx ctx, int64_t *held_bytes, int64_t *budge
  *  SGBEM_MEM_RHS_DIRECT:   sgbem_rhs_direct with n_gauss points: node geometry and
  *                          the double-layer sweep's workspace;
  *  SGBEM_MEM_SOLVE:        sgbem_solve of order N: 4 N_p^2 + about 1.8 N_p KB,
- *                          N_p = N rounded up to a multiple of 64.
+ *                          N_p = N rounded up to a multiple of 64;
+ *  SGBEM_MEM_RULES_KNOTS:  one sgbem_weights handle on non-uniform knots:
+ *                          32 M^2 + 16 N Q + 16 M bytes (the full singular table).
  * n_ctrl: control points of the B-spline curve of the call (0 for a polar
  * curve); beyond 64 they are copied to the device, 24 n_ctrl + 8 bytes more.
  * Errors: E_INVAL. */
 typedef enum { SGBEM_MEM_RULES = 0, SGBEM_MEM_ASSEMBLE_WQ = 1, SGBEM_MEM_ASSEMBLE_EBE = 2,
-               SGBEM_MEM_RHS_DIRECT = 3, SGBEM_MEM_SOLVE = 4 } sgbem_memory_kind;
+               SGBEM_MEM_RHS_DIRECT = 3, SGBEM_MEM_SOLVE = 4, SGBEM_MEM_RULES_KNOTS = 5 } sgbem_memory_kind;
 sgbem_status sgbem_memory_need(int32_t what, int32_t p, int32_t N, int32_t n_ref, int32_t n_gauss, int32_t n_ctrl,
                                int64_t *bytes);
 
@@ -163,23 +167,35 @@ const char *sgbem_version(void);
 
 /*
  * Build the quadrature rules of Section 4 for degree p, N elements and
- * refinement n_ref (the exactness space: cyclic B-splines of degree p on
- * M = n_ref N elements), and upload them to the device.  Synchronous.
+ * refinement n_ref (the exactness space: B-splines of degree p on the knots
+ * refined by splitting every element into n_ref equal parts, M = n_ref N
+ * elements), and upload them to the device.  Synchronous.
+ *  - knots: NULL for uniform periodic knots tau_k = k / N, else the N + 1
+ *    breakpoints 0 = tau_0 < tau_1 < ... < tau_N = 1 of one period (host,
+ *    read during the call), extended periodically (Section 3);
  *  - nodes (Section 4): all breakpoints and midpoints of the refined mesh,
- *    eta_n = n / (2M), n = 0..2M-1;
+ *    2M nodes (eta_n = n / (2M) for uniform knots);
  *  - regular rules (Alg. 1, eq. reg_exactness): minimum-norm weights on the
- *    2 n_ref (p+1) - 1 nodes inside supp B_i, exact for every Bbar_k meeting it;
+ *    2 n_ref (p+1) - 1 nodes inside supp B_i, exact for every refined
+ *    Bbar_k meeting it;
  *  - singular rules (Alg. 2, eqs. sing_exactness, mod_mom_gen): for each source
  *    eta_m, minimum-norm weights on all nodes exact for int Bbar_k(t) K2(eta_m,t) dt,
  *    K2(s,t) = ln|sin(pi (s-t)) / pi| (the kernel split of Section 3.1 made
  *    periodic), modified moments from the closed forms of Section 4.2.
  *    With uniform periodic knots the weights depend only on (m mod 2, n - m mod 2M),
- *    so two tables of length 2M are kept.
- * Limits: p in [1, 6], n_ref in [1, 4], N >= 2 (p + 1), 2 n_ref N <= 2^24.
- * Errors: E_INVAL, E_NOMEM, E_DEVICE, E_SINGULAR (rank-deficient collocation).
- * The handle is freed with sgbem_rules_free (or with its context).
+ *    so two tables of length 2M are kept; on non-uniform knots every test
+ *    function has its own regular rule and the singular weights form a full
+ *    2M x 2M table (32 M^2 bytes), built by host threads.
+ * Limits: p in [1, 6], n_ref in [1, 4], N >= 2 (p + 1), 2 n_ref N <= 2^24;
+ * non-uniform knots: 2 n_ref N <= 8192 (else E_UNSUPPORTED), and the rules
+ * serve the FP64 fast form (sgbem_assemble with SGBEM_WQ, n_ref in {1, 2}),
+ * sgbem_rhs with SGBEM_WQ and sgbem_rhs_points with SGBEM_WQ only (the other
+ * entry points return E_UNSUPPORTED for them).
+ * Errors: E_INVAL, E_NOMEM, E_DEVICE, E_SINGULAR (rank-deficient collocation),
+ * E_UNSUPPORTED.  The handle is freed with sgbem_rules_free (or with its context).
  */
-sgbem_status sgbem_weights(sgbem_ctx ctx, int32_t p, int32_t N, int32_t n_ref, sgbem_rules *out);
+sgbem_status sgbem_weights(sgbem_ctx ctx, int32_t p, int32_t N, int32_t n_ref, const double *knots,
+                           sgbem_rules *out);
 
 sgbem_status sgbem_rules_free(sgbem_ctx ctx, sgbem_rules rules);
 
@@ -191,6 +207,14 @@ sgbem_status sgbem_rules_free(sgbem_ctx ctx, sgbem_rules rules);
  * Any output pointer may be NULL.  Errors: E_INVAL, E_NOMEM, E_SINGULAR. */
 sgbem_status sgbem_weights_host(int32_t p, int32_t N, int32_t n_ref,
                                 double *w0, double *bvals, double *ws);
+
+/* Host-only view of the rules on non-uniform knots (same arguments as
+ * sgbem_weights with knots): W[N][Q] regular weights of B_i on the nodes
+ * 2 n_ref i + 1 + q (mod 2M), Bv[N][Q] B_i at those nodes, Ws[2M][2M] singular
+ * weights (row m: source eta_m), eta[2M] node parameters.  Any output may be
+ * NULL.  Errors: E_INVAL, E_NOMEM, E_SINGULAR, E_UNSUPPORTED. */
+sgbem_status sgbem_weights_host_knots(int32_t p, int32_t N, int32_t n_ref, const double *knots,
+                                      double *W, double *Bv, double *Ws, double *eta);
 
 /* Host-only reference matrices of the element-by-element near-pair rule
  * (Section 5, Remark): on unit elements with the 16 Gauss-Legendre points u_a

@@ -17,9 +17,9 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsgbem.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-HIP_UNITS = ["api.hip", "kernels.hip", "solve.hip", "batch.hip", "serve.hip", "dlayer.hip", "colloc.hip",
+HIP_UNITS = ["api.hip", "kernels.hip", "solve.hip", "batch.hip", "serve.hip", "dlayer.hip", "colloc.hip", "knots.hip",
              "asm_wq_f64.hip", "asm_wq_f32.hip", "asm_ebe_f64.hip", "asm_ebe_f32.hip"]
-CXX_UNITS = ["planner.cpp"]
+CXX_UNITS = ["planner.cpp", "planner_knots.cpp"]
 # the register-resident LU panel needs its 64 x 64 column loop fully unrolled
 UNIT_FLAGS = {"solve.hip": ["-mllvm", "-pragma-unroll-threshold=1000000"]}
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
@@ -47,7 +47,7 @@ def build(jobs: int = 8, verbose: bool = False) -> str:
     for u in CXX_UNITS:
         o = os.path.join(BUILD, u + ".o")
         objs.append(o)
-        cmds.append(["g++", "-O2", "-std=c++17", "-fPIC", "-Wall", "-c", os.path.join(CSRC, u), "-o", o])
+        cmds.append(["g++", "-O2", "-std=c++17", "-fPIC", "-pthread", "-Wall", "-c", os.path.join(CSRC, u), "-o", o])
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         for out in ex.map(_run, cmds):
             if verbose and out.strip():

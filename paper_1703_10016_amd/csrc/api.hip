@@ -20,6 +20,7 @@
 #include "curve_eval.hpp"
 #include "dlayer.hpp"
 #include "colloc.hpp"
+#include "knots.hpp"
 
 namespace sgbem {
 hipError_t launch_wq_f64(int p, int P, const TileArgs &a, hipStream_t s, const KernelEvents *ev);
@@ -133,6 +134,12 @@ size_t rules_block_bytes(int64_t npts)
 {
     const size_t n = size_t(npts);
     return align256(n * 8) + align256(2 * n * 8) + align256(64 * 8) + align256(n * 4) + align256(2 * n * 4);
+}
+
+size_t knot_rules_block_bytes(int N, int R, int p)
+{
+    const size_t Q = size_t(2 * R * (p + 1) - 1), nn = size_t(2) * R * N;
+    return 2 * align256(size_t(N) * Q * 8) + align256(nn * nn * 8) + align256(nn * 8);
 }
 
 void free_rules(sgbem_rules r)
@@ -365,6 +372,7 @@ GridDesc wq_grid(sgbem_rules r)
     g.N = r->N;
     g.P = 0;
     g.npts = int(r->npts);
+    g.tpar = r->knots ? r->d_eta : nullptr;   // non-uniform knots: the node parameters
     return g;
 }
 
@@ -514,7 +522,8 @@ sgbem_status sgbem_memory_need(int32_t what, int32_t p, int32_t N, int32_t n_ref
     if (!bytes) return set_err(SGBEM_E_INVAL, "bytes is NULL");
     *bytes = 0;
     if (N < 1 || N > (1 << 24) || n_ctrl < 0) return set_err(SGBEM_E_INVAL, "bad N or n_ctrl");
-    const bool need_rules = what == SGBEM_MEM_RULES || what == SGBEM_MEM_ASSEMBLE_WQ || what == SGBEM_MEM_RHS_DIRECT;
+    const bool need_rules = what == SGBEM_MEM_RULES || what == SGBEM_MEM_ASSEMBLE_WQ || what == SGBEM_MEM_RHS_DIRECT ||
+                            what == SGBEM_MEM_RULES_KNOTS;
     if (need_rules && (n_ref < 1 || n_ref > 4)) return set_err(SGBEM_E_INVAL, "n_ref must be in [1, 4]");
     if (what != SGBEM_MEM_SOLVE && (p < 1 || p > 6)) return set_err(SGBEM_E_INVAL, "p must be in [1, 6]");
     const size_t n = size_t(N), M = size_t(n_ref) * n;
@@ -546,6 +555,9 @@ sgbem_status sgbem_memory_need(int32_t what, int32_t p, int32_t N, int32_t n_ref
     }
     case SGBEM_MEM_SOLVE:
         b = buf_bytes(solve_workspace_bytes(N));
+        break;
+    case SGBEM_MEM_RULES_KNOTS:
+        b = buf_bytes(knot_rules_block_bytes(N, n_ref, p));
         break;
     default:
         return set_err(SGBEM_E_INVAL, "unknown memory kind");
@@ -662,34 +674,112 @@ sgbem_status sgbem_node_points_host(const sgbem_curve *curve, int32_t N, int32_t
     return SGBEM_OK;
 }
 
-sgbem_status sgbem_weights(sgbem_ctx c, int32_t p, int32_t N, int32_t n_ref, sgbem_rules *out)
+namespace {
+// Rules on non-uniform knots: built on the host, uploaded into one block of
+// the context (within its budget).
+sgbem_status make_knot_rules(sgbem_ctx c, int p, int N, int R, const double *knots, sgbem_rules &out)
+{
+    out = nullptr;
+    WQRulesKnots K;
+    try {
+        K = build_wq_rules_knots(p, N, R, knots);
+    } catch (const PlanError &e) {
+        return set_err(sgbem_status(e.status), e.msg);
+    } catch (const std::bad_alloc &) {
+        return set_err(SGBEM_E_NOMEM, "host allocation failed");
+    }
+    const size_t nb = buf_bytes(knot_rules_block_bytes(N, R, p));
+    void *block = nullptr;
+    sgbem_status st = ctx_malloc(c, &block, nb);
+    if (st) return st;
+    auto *r = new (std::nothrow) sgbem_rules_s;
+    if (!r) {
+        ctx_free(c, block, nb);
+        return set_err(SGBEM_E_NOMEM, "host allocation failed");
+    }
+    r->p = p;
+    r->N = N;
+    r->R = R;
+    r->Q = K.Q;
+    r->M = K.M;
+    r->npts = K.n_nodes;
+    r->knots = true;
+    r->block = block;
+    r->block_bytes = nb;
+    r->owned = true;
+    const size_t NQ = size_t(N) * K.Q, nn = size_t(K.n_nodes);
+    char *b = static_cast<char *>(block);
+    r->d_W = reinterpret_cast<double *>(b);
+    b += align256(NQ * 8);
+    r->d_Bv = reinterpret_cast<double *>(b);
+    b += align256(NQ * 8);
+    r->d_Wsg = reinterpret_cast<double *>(b);
+    b += align256(nn * nn * 8);
+    r->d_eta = reinterpret_cast<double *>(b);
+    hipError_t e = hipMemcpy(r->d_W, K.W.data(), NQ * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(r->d_Bv, K.Bv.data(), NQ * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(r->d_Wsg, K.Ws.data(), nn * nn * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(r->d_eta, K.eta.data(), nn * 8, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        ctx_free(c, block, nb);
+        delete r;
+        return set_err(SGBEM_E_DEVICE, std::string("rules upload: ") + hipGetErrorString(e));
+    }
+    out = r;
+    return SGBEM_OK;
+}
+}  // namespace
+
+sgbem_status sgbem_weights(sgbem_ctx c, int32_t p, int32_t N, int32_t n_ref, const double *knots, sgbem_rules *out)
 {
     if (!c || !out) return set_err(SGBEM_E_INVAL, "ctx or out is NULL");
     *out = nullptr;
     if (p < 1 || p > 6 || n_ref < 1 || n_ref > 4 || N < 2 * (p + 1) || int64_t(2) * n_ref * N > (int64_t(1) << 24))
         return set_err(SGBEM_E_INVAL, "need p in [1, 6], n_ref in [1, 4], N >= 2 (p + 1), 2 n_ref N <= 2^24");
     DeviceGuard g(c->device);
-    // the block within the context's budget, before the host work
-    const size_t nb = buf_bytes(rules_block_bytes(int64_t(2) * n_ref * N));
-    void *block = nullptr;
-    sgbem_status st = ctx_malloc(c, &block, nb);
-    if (st) return st;
     sgbem_rules r = nullptr;
-    if ((st = make_rules(p, N, n_ref, block, c->stream, r))) {
-        ctx_free(c, block, nb);
-        return st;
+    sgbem_status st;
+    if (knots) {
+        if ((st = make_knot_rules(c, p, N, n_ref, knots, r))) return st;
+    } else {
+        // the block within the context's budget, before the host work
+        const size_t nb = buf_bytes(rules_block_bytes(int64_t(2) * n_ref * N));
+        void *block = nullptr;
+        if ((st = ctx_malloc(c, &block, nb))) return st;
+        if ((st = make_rules(p, N, n_ref, block, c->stream, r))) {
+            ctx_free(c, block, nb);
+            return st;
+        }
+        r->owned = true;
+        r->block_bytes = nb;
     }
-    r->owned = true;
-    r->block_bytes = nb;
     try {
         c->rules.push_back(r);
     } catch (...) {
-        ctx_free(c, block, nb);
+        ctx_free(c, r->block, r->block_bytes);
         r->owned = false;
         free_rules(r);
         return set_err(SGBEM_E_NOMEM, "host allocation failed");
     }
     *out = r;
+    return SGBEM_OK;
+}
+
+sgbem_status sgbem_weights_host_knots(int32_t p, int32_t N, int32_t n_ref, const double *knots, double *W, double *Bv,
+                                      double *Ws, double *eta)
+{
+    if (!knots) return set_err(SGBEM_E_INVAL, "knots is NULL");
+    try {
+        const WQRulesKnots K = build_wq_rules_knots(p, N, n_ref, knots);
+        if (W) std::memcpy(W, K.W.data(), K.W.size() * sizeof(double));
+        if (Bv) std::memcpy(Bv, K.Bv.data(), K.Bv.size() * sizeof(double));
+        if (Ws) std::memcpy(Ws, K.Ws.data(), K.Ws.size() * sizeof(double));
+        if (eta) std::memcpy(eta, K.eta.data(), K.eta.size() * sizeof(double));
+    } catch (const PlanError &e) {
+        return set_err(sgbem_status(e.status), e.msg);
+    } catch (const std::bad_alloc &) {
+        return set_err(SGBEM_E_NOMEM, "host allocation failed");
+    }
     return SGBEM_OK;
 }
 
@@ -716,6 +806,7 @@ sgbem_status sgbem_rhs_points(sgbem_ctx c, const sgbem_curve *curve, sgbem_rules
     if (!c || !r || !count) return set_err(SGBEM_E_INVAL, "NULL argument");
     if (!valid_rules(c, r)) return set_err(SGBEM_E_INVAL, "rules handle does not belong to this context");
     if (method != SGBEM_WQ && method != SGBEM_EBE) return set_err(SGBEM_E_INVAL, "unknown method");
+    if (r->knots && method != SGBEM_WQ) return set_err(SGBEM_E_UNSUPPORTED, "rules on non-uniform knots: fast-form assembly and its right-hand side only");
     if (method == SGBEM_EBE && (n_gauss < 1 || n_gauss > 8)) return set_err(SGBEM_E_INVAL, "n_gauss must be in [1, 8]");
     DeviceGuard g(c->device);
     const GridDesc grid = method == SGBEM_WQ ? wq_grid(r) : gauss_grid(r->N, n_gauss);
@@ -741,6 +832,38 @@ sgbem_status sgbem_assemble(sgbem_ctx c, const sgbem_curve *curve, sgbem_rules r
     if (method == SGBEM_EBE && (n_gauss < 1 || n_gauss > 8)) return set_err(SGBEM_E_INVAL, "n_gauss must be in [1, 8]");
     const int p = r->p, N = r->N;
     const int P = method == SGBEM_WQ ? 2 * r->R : n_gauss;
+    if (r->knots) {
+        // non-uniform knots: per-row rules and the full singular table (FP64 fast form)
+        if (method != SGBEM_WQ || precision != SGBEM_FP64 || !assemble_knots_supported(p, P))
+            return set_err(SGBEM_E_UNSUPPORTED, "rules on non-uniform knots: FP64 fast form with n_ref in {1, 2} only");
+        DeviceGuard g(c->device);
+        CurveDev cd;
+        sgbem_status st = upload_curve(c, curve, cd);
+        if (st) return st;
+        const GridDesc grid = wq_grid(r);
+        double *X, *Y, *J;
+        if ((st = geometry(c, cd, grid, c->geo, X, Y, J))) return st;
+        KnotArgs ka;
+        ka.N = N;
+        ka.npts = grid.npts;
+        ka.P = P;
+        ka.Q = r->Q;
+        ka.X = X;
+        ka.Y = Y;
+        ka.J = J;
+        ka.eta = r->d_eta;
+        ka.W = r->d_W;
+        ka.Bv = r->d_Bv;
+        ka.Ws = r->d_Wsg;
+        ka.scale = -1.0 / (2.0 * kPi);
+        ka.out = static_cast<double *>(d_A);
+        ka.lda = lda;
+        KernelEvents ke;
+        const KernelEvents *kev;
+        if ((st = timing_events(c, ke, kev))) return st;
+        HIPCHK(launch_assemble_knots(p, ka, c->stream, kev));
+        return SGBEM_OK;
+    }
     if (!assemble_supported(method, precision, p, P)) return set_err(SGBEM_E_UNSUPPORTED, "no kernel compiled for this (p, P)");
     DeviceGuard g(c->device);
     CurveDev cd;
@@ -812,6 +935,7 @@ sgbem_status sgbem_assemble_noalloc(sgbem_ctx c, const sgbem_curve *curve, sgbem
     if (lda < r->N) return set_err(SGBEM_E_INVAL, "lda < N");
     if (r->npts > SGBEM_NOALLOC_MAX_NODES)
         return set_err(SGBEM_E_INVAL, "2 n_ref N exceeds SGBEM_NOALLOC_MAX_NODES (the fixed geometry array)");
+    if (r->knots) return set_err(SGBEM_E_UNSUPPORTED, "rules on non-uniform knots: fast-form assembly and its right-hand side only");
     const int p = r->p, P = 2 * r->R;
     if (!assemble_supported(SGBEM_WQ, precision, p, P))
         return set_err(SGBEM_E_UNSUPPORTED, "no kernel compiled for this (p, n_ref)");
@@ -850,9 +974,11 @@ sgbem_status sgbem_rhs(sgbem_ctx c, const sgbem_curve *curve, sgbem_rules r, int
         const GridDesc grid = wq_grid(r);
         double *X, *Y, *J;
         if ((st = geometry(c, cd, grid, c->geo, X, Y, J))) return st;
-        HIPCHK(launch_rhs(N, grid.npts, 2 * r->R, 1, r->Q, r->d_w0, 1.0, J, d_g, d_beta, c->stream));
+        if (r->knots) HIPCHK(launch_rhs_knots(N, grid.npts, 2 * r->R, r->Q, r->d_W, J, d_g, d_beta, c->stream));
+        else HIPCHK(launch_rhs(N, grid.npts, 2 * r->R, 1, r->Q, r->d_w0, 1.0, J, d_g, d_beta, c->stream));
         return SGBEM_OK;
     }
+    if (r->knots) return set_err(SGBEM_E_UNSUPPORTED, "rules on non-uniform knots: fast-form assembly and its right-hand side only");
     const int G = n_gauss;
     const GridDesc grid = gauss_grid(N, G);
     double *X, *Y, *J;
@@ -870,6 +996,7 @@ sgbem_status sgbem_rhs_direct(sgbem_ctx c, const sgbem_curve *curve, sgbem_rules
     if (!valid_rules(c, r)) return set_err(SGBEM_E_INVAL, "rules handle does not belong to this context");
     if (n_gauss < 2 || n_gauss > 8 || (n_gauss & 1))
         return set_err(SGBEM_E_INVAL, "n_gauss must be 2, 4, 6 or 8 (even: no Gauss point on a node)");
+    if (r->knots) return set_err(SGBEM_E_UNSUPPORTED, "rules on non-uniform knots: fast-form assembly and its right-hand side only");
     DeviceGuard g(c->device);
     CurveDev cd;
     sgbem_status st = upload_curve(c, curve, cd);
@@ -907,6 +1034,7 @@ sgbem_status sgbem_assemble_collocation(sgbem_ctx c, const sgbem_curve *curve, s
     if (!c || !r || !d_A) return set_err(SGBEM_E_INVAL, "NULL argument");
     if (!valid_rules(c, r)) return set_err(SGBEM_E_INVAL, "rules handle does not belong to this context");
     if (lda < r->N) return set_err(SGBEM_E_INVAL, "lda < N");
+    if (r->knots) return set_err(SGBEM_E_UNSUPPORTED, "rules on non-uniform knots: fast-form assembly and its right-hand side only");
     const int p = r->p, P = 2 * r->R;
     if (!colloc_supported(p, P)) return set_err(SGBEM_E_UNSUPPORTED, "collocation: n_ref in {1, 2} only");
     DeviceGuard g(c->device);
@@ -943,6 +1071,7 @@ sgbem_status sgbem_collocation_rhs(sgbem_ctx c, sgbem_rules r, const double *d_g
 {
     if (!c || !r || !d_g_nodes || !d_b) return set_err(SGBEM_E_INVAL, "NULL argument");
     if (!valid_rules(c, r)) return set_err(SGBEM_E_INVAL, "rules handle does not belong to this context");
+    if (r->knots) return set_err(SGBEM_E_UNSUPPORTED, "rules on non-uniform knots: fast-form assembly and its right-hand side only");
     DeviceGuard g(c->device);
     HIPCHK(launch_colloc_gather(r->N, int(r->npts), 2 * r->R, r->R * (r->p + 1), d_g_nodes, d_b, c->stream));
     return SGBEM_OK;
@@ -966,6 +1095,7 @@ sgbem_status sgbem_batch_create(sgbem_ctx c, int32_t n, const sgbem_curve *curve
     for (int b = 0; b < n; ++b) {
         sgbem_rules r = rules[b];
         if (!r || !valid_rules(c, r)) return set_err(SGBEM_E_INVAL, "batch: rules handle does not belong to this context");
+        if (r->knots) return set_err(SGBEM_E_UNSUPPORTED, "batch: rules on non-uniform knots are not batched");
         if (r->R != 1 || r->p < 2 || r->p > 4)
             return set_err(SGBEM_E_UNSUPPORTED, "batch: n_ref = 1 and p in {2, 3, 4} only");
         if (!d_A[b] || lda[b] < r->N) return set_err(SGBEM_E_INVAL, "batch: NULL matrix or lda < N");

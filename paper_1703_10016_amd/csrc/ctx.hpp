@@ -64,6 +64,10 @@ struct sgbem_rules_s {
     size_t block_bytes = 0;   // allocated size of an owned block
     bool owned = false;
     bool shared = false;
+    // rules on non-uniform knots (no translation invariance; FP64 fast form only):
+    // W[N][Q], Bv[N][Q], Ws[2M][2M], eta[2M] in the block
+    bool knots = false;
+    double *d_W = nullptr, *d_Bv = nullptr, *d_Wsg = nullptr, *d_eta = nullptr;
 };
 
 struct sgbem_batch_s {
@@ -124,6 +128,9 @@ void ctx_free(sgbem_ctx c, void *p, size_t bytes);
 
 // Bytes of the device block of a rule set with npts nodes.
 size_t rules_block_bytes(int64_t npts);
+
+// Bytes of the device block of rules on non-uniform knots.
+size_t knot_rules_block_bytes(int N, int R, int p);
 
 // Build the rules of (p, N, R) on the host and upload them on `stream`
 // (synchronised before return).  block: device memory of rules_block_bytes

@@ -18,7 +18,9 @@ __global__ void geometry_kernel(CurveDev c, GridDesc g, double *X, double *Y, do
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= g.npts) return;
     double t;
-    if (g.P == 0) {
+    if (g.tpar) {
+        t = g.tpar[n];
+    } else if (g.P == 0) {
         t = double(n) / double(g.npts);
     } else {
         const int e = n / g.P, q = n - e * g.P;

@@ -24,12 +24,13 @@ struct CurveDev {
 };
 
 // Point grid on [0, 1): n = e * P + q  ->  t = (e + off[q]) / N  (P <= 32),
-// or t = n / npts when P == 0.
+// or t = n / npts when P == 0, or t = tpar[n] (device table) when tpar is set.
 struct GridDesc {
     int N;
     int P;
     int npts;
     double off[32];
+    const double *tpar;
 };
 
 hipError_t launch_geometry(const CurveDev &c, const GridDesc &g, double *X, double *Y, double *J, hipStream_t s);

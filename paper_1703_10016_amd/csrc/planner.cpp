@@ -204,8 +204,6 @@ double int_poly_log(const double *c, int deg, double sigma)
 }
 
 // ------------------------------------------------------------------ small dense helpers
-namespace {
-
 // Minimum-norm solution of A w = mu, A (m x n) row-major with m <= n, by the
 // Householder QR factorisation of A^T.
 std::vector<double> min_norm_solve(const std::vector<double> &A, int m, int n, const std::vector<double> &mu)
@@ -254,6 +252,8 @@ std::vector<double> min_norm_solve(const std::vector<double> &A, int m, int n, c
     }
     return z;
 }
+
+namespace {
 
 // Solve G y = rhs (nrhs columns, rhs[k*nrhs + r]) for the symmetric positive
 // definite cyclic banded matrix G[k][l] = g[d], d = cyclic distance <= hb.

@@ -38,6 +38,30 @@ struct WQRules {
 // Build the rules; throws PlanError.
 WQRules build_wq_rules(int p, int N, int R);
 
+// Minimum-norm solution of A w = mu, A (m x n) row-major, m <= n (Householder
+// QR of A^T); throws PlanError on a rank-deficient A.
+std::vector<double> min_norm_solve(const std::vector<double> &A, int m, int n, const std::vector<double> &mu);
+
+// Rules on non-uniform periodic knots (no translation invariance): the
+// approximation space on the breakpoints tau[0] = 0 < ... < tau[N] = 1 of one
+// period, the exactness space on the knots refined by splitting every element
+// into R equal parts (M = R N), nodes eta at the refined breakpoints and
+// midpoints.  Row i's Q = 2R(p+1) - 1 support nodes are 2R i + 1 + q (mod 2M),
+// as for uniform knots.
+struct WQRulesKnots {
+    int p = 0, N = 0, R = 0;
+    int64_t M = 0, n_nodes = 0;
+    int Q = 0;
+    std::vector<double> eta;   // [2M] node parameters
+    std::vector<double> W;     // [N][Q] regular weights of B_i (Alg. 1)
+    std::vector<double> Bv;    // [N][Q] B_i at its support nodes
+    std::vector<double> Ws;    // [2M][2M] singular weights, row m: source eta_m (Alg. 2)
+};
+constexpr int64_t kMaxKnotNodes = 8192;   // 2M limit: the full singular table is (2M)^2 doubles
+
+// Build them (host threads); throws PlanError.
+WQRulesKnots build_wq_rules_knots(int p, int N, int R, const double *tau);
+
 struct NearField {
     double u[16], w[16];
     double mco[256], madj[256];

@@ -31,25 +31,28 @@ class Context:
     def __exit__(self, *exc):
         self.close()
 
-    def rules(self, p: int, N: int, n_ref: int = 1):
-        key = (p, N, n_ref)
+    def rules(self, p: int, N: int, n_ref: int = 1, knots=None):
+        """Rules handle of (p, N, n_ref) on uniform knots, or on the given knot
+        vector of N + 1 breakpoints (cached per knot vector)."""
+        key = (p, N, n_ref) if knots is None else (p, N, n_ref, np.asarray(knots, dtype=np.float64).tobytes())
         if key not in self._rules:
-            self._rules[key] = S.sgbem_weights(self.ctx, p, N, n_ref)
+            self._rules[key] = S.sgbem_weights(self.ctx, p, N, n_ref, knots)
         return self._rules[key]
 
-    def assemble(self, curve, p, N, method="wq", n_ref=1, n_gauss=6, precision="fp64", out=None):
+    def assemble(self, curve, p, N, method="wq", n_ref=1, n_gauss=6, precision="fp64", out=None, knots=None):
         dt = self.torch.float64 if precision == "fp64" else self.torch.float32
         if out is None:
             out = self.torch.empty((N, N), dtype=dt, device=self.device)
         assert out.dtype == dt and out.is_cuda and out.stride(1) == 1 and out.shape[0] >= N
-        S.sgbem_assemble(self.ctx, curve, self.rules(p, N, n_ref), _METHODS[method], n_gauss, _PREC[precision],
+        S.sgbem_assemble(self.ctx, curve, self.rules(p, N, n_ref, knots), _METHODS[method], n_gauss, _PREC[precision],
                          out.data_ptr(), out.stride(0))
         return out
 
-    def rhs_points(self, curve, p, N, method="wq", n_ref=1, n_gauss=6):
+    def rhs_points(self, curve, p, N, method="wq", n_ref=1, n_gauss=6, knots=None):
         count = 2 * n_ref * N if method == "wq" else N * n_gauss
         xy = self.torch.empty((count, 2), dtype=self.torch.float64, device=self.device)
-        S.sgbem_rhs_points(self.ctx, curve, self.rules(p, N, n_ref), _METHODS[method], n_gauss, xy.data_ptr(), count)
+        S.sgbem_rhs_points(self.ctx, curve, self.rules(p, N, n_ref, knots), _METHODS[method], n_gauss, xy.data_ptr(),
+                           count)
         return xy
 
     def sample(self, g, xy):
@@ -58,10 +61,10 @@ class Context:
         h = xy.cpu().numpy()
         return self.torch.from_numpy(np.ascontiguousarray(g(h[:, 0], h[:, 1]), dtype=np.float64)).to(self.device)
 
-    def rhs(self, curve, p, N, g, method="wq", n_ref=1, n_gauss=6):
-        gv = self.sample(g, self.rhs_points(curve, p, N, method, n_ref, n_gauss))
+    def rhs(self, curve, p, N, g, method="wq", n_ref=1, n_gauss=6, knots=None):
+        gv = self.sample(g, self.rhs_points(curve, p, N, method, n_ref, n_gauss, knots))
         beta = self.torch.empty(N, dtype=self.torch.float64, device=self.device)
-        S.sgbem_rhs(self.ctx, curve, self.rules(p, N, n_ref), _METHODS[method], n_gauss, gv.data_ptr(),
+        S.sgbem_rhs(self.ctx, curve, self.rules(p, N, n_ref, knots), _METHODS[method], n_gauss, gv.data_ptr(),
                     beta.data_ptr())
         return beta
 

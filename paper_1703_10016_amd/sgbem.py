@@ -92,7 +92,8 @@ def lib():
             "sgbem_ctx_set_stream": [vp, vp],
             "sgbem_ctx_set_timing": [vp, i32],
             "sgbem_ctx_kernel_time": [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)],
-            "sgbem_weights": [vp, i32, i32, i32, ctypes.POINTER(vp)],
+            "sgbem_weights": [vp, i32, i32, i32, dp, ctypes.POINTER(vp)],
+            "sgbem_weights_host_knots": [i32, i32, i32, dp, dp, dp, dp, dp],
             "sgbem_rules_free": [vp, vp],
             "sgbem_weights_host": [i32, i32, i32, dp, dp, dp],
             "sgbem_nearfield_host": [dp, dp, dp, dp],
@@ -145,7 +146,7 @@ def exported_symbols():
             "sgbem_server_create", "sgbem_server_submit", "sgbem_server_poll", "sgbem_server_clock",
             "sgbem_server_stats", "sgbem_server_destroy", "sgbem_rhs_direct",
             "sgbem_assemble_collocation", "sgbem_collocation_rhs", "sgbem_assemble_noalloc",
-            "sgbem_ctx_memory", "sgbem_memory_need"]
+            "sgbem_ctx_memory", "sgbem_memory_need", "sgbem_weights_host_knots"]
 
 
 # ------------------------------------------------------------------ curve marshalling
@@ -206,6 +207,7 @@ def sgbem_ctx_memory(ctx):
 
 
 SGBEM_MEM_RULES, SGBEM_MEM_ASSEMBLE_WQ, SGBEM_MEM_ASSEMBLE_EBE, SGBEM_MEM_RHS_DIRECT, SGBEM_MEM_SOLVE = 0, 1, 2, 3, 4
+SGBEM_MEM_RULES_KNOTS = 5
 
 
 def sgbem_memory_need(what, p=1, N=1, n_ref=1, n_gauss=0, n_ctrl=0):
@@ -232,10 +234,33 @@ def sgbem_ctx_kernel_time(ctx):
     return ms.value, n.value
 
 
-def sgbem_weights(ctx, p, N, n_ref=1):
+def _knots_ptr(knots, N):
+    """(pointer, keep-alive array) for an optional knot vector of N + 1 breakpoints."""
+    if knots is None:
+        return None, None
+    k = np.ascontiguousarray(knots, dtype=np.float64)
+    if k.shape != (N + 1,):
+        raise ValueError("knots must hold N + 1 breakpoints")
+    return k.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), k
+
+
+def sgbem_weights(ctx, p, N, n_ref=1, knots=None):
     h = ctypes.c_void_p()
-    _check(lib().sgbem_weights(ctx, int(p), int(N), int(n_ref), ctypes.byref(h)))
+    kp, keep = _knots_ptr(knots, N)
+    _check(lib().sgbem_weights(ctx, int(p), int(N), int(n_ref), kp, ctypes.byref(h)))
+    del keep
     return h
+
+
+def sgbem_weights_host_knots(p, N, n_ref, knots):
+    """(W[N, Q], Bv[N, Q], Ws[2M, 2M], eta[2M]) of the rules on non-uniform knots."""
+    Q, M = 2 * n_ref * (p + 1) - 1, n_ref * N
+    W, Bv, Ws, eta = np.zeros(N * Q), np.zeros(N * Q), np.zeros(4 * M * M), np.zeros(2 * M)
+    kp, keep = _knots_ptr(knots, N)
+    P = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    _check(lib().sgbem_weights_host_knots(int(p), int(N), int(n_ref), kp, P(W), P(Bv), P(Ws), P(eta)))
+    del keep
+    return W.reshape(N, Q), Bv.reshape(N, Q), Ws.reshape(2 * M, 2 * M), eta
 
 
 def sgbem_rules_free(ctx, rules):

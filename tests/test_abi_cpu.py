@@ -193,3 +193,55 @@ def test_memory_need_formulas():
         with pytest.raises(S.SgbemError) as e:
             S.sgbem_memory_need(kw.pop("what"), **kw)
         assert e.value.status == S.SGBEM_E_INVAL
+
+
+def _knots(N, seed, spread=0.6):
+    rng = np.random.default_rng(seed)
+    u = (np.arange(N + 1) + spread * (rng.uniform(0, 1, N + 1) - 0.5)) / N
+    u[0], u[-1] = 0.0, 1.0
+    return u
+
+
+@pytest.mark.parametrize("p,N,R,seed", [(2, 10, 1, 0), (3, 9, 2, 1), (4, 12, 1, 2), (1, 8, 1, 3), (6, 14, 1, 4)])
+def test_knot_planner_matches_oracle(p, N, R, seed):
+    """Rules on non-uniform knots from the library's host planner (Householder QR
+    per row, local Cox-de Boor pieces, general cyclic banded Cholesky) against
+    the oracle's dense least-squares route (O6)."""
+    from oracle import wq_knots as K
+    S = _lib()
+    tau = _knots(N, seed)
+    W, Bv, Ws, eta = S.sgbem_weights_host_knots(p, N, R, tau)
+    assert np.array_equal(eta, K.nodes(tau, R))
+    tb = K.refine(tau, R)
+    rules = K.regular_weights(tau, p, R)
+    for i, (nset, w) in rules.items():
+        Bloc = np.stack([K.basis(tb, p, int(k), eta[nset]) for k in K.exactness_set(p, N, R, i)])
+        tol = 20 * np.finfo(float).eps * np.linalg.cond(Bloc) * np.abs(w).max()
+        assert np.abs(W[i] - w).max() < tol, (i, np.abs(W[i] - w).max(), tol)
+        assert np.abs(Bv[i] - K.basis(tau, p, i, eta[nset])).max() < 4e-15   # (the oracle wraps by t + 1)
+    Wso = K.singular_weights(tau, p, R)
+    assert np.abs(Ws - Wso).max() < 2e-13 * np.abs(Wso).max(), np.abs(Ws - Wso).max() / np.abs(Wso).max()
+
+
+def test_knot_planner_on_uniform_knots_matches_uniform_tables():
+    S = _lib()
+    p, N, R = 3, 16, 2
+    W, Bv, Ws, eta = S.sgbem_weights_host_knots(p, N, R, np.arange(N + 1) / N)
+    w0, bv, ws = S.sgbem_weights_host(p, N, R)
+    assert np.abs(W - w0[None, :]).max() < 1e-13 and np.abs(Bv - bv[None, :]).max() < 1e-15
+    M2 = 2 * R * N
+    m = np.arange(M2)
+    full = ws[m[:, None] % 2, (m[None, :] - m[:, None]) % M2]
+    assert np.abs(Ws - full).max() < 1e-13 * np.abs(full).max()
+
+
+@pytest.mark.parametrize("args,status", [((3, 10, 1, np.linspace(0, 1, 10)), -1),
+                                         ((3, 10, 1, np.r_[0, 0.5, 0.4, np.linspace(0.5, 1, 8)]), -1),
+                                         ((2, 4096, 2, np.linspace(0, 1, 4097)), -6)])
+def test_knot_planner_rejects(args, status):
+    S = _lib()
+    p, N, R, tau = args
+    with pytest.raises((S.SgbemError, ValueError)) as e:
+        S.sgbem_weights_host_knots(p, N, R, tau)
+    if isinstance(e.value, S.SgbemError):
+        assert e.value.status == status
