@@ -33,6 +33,11 @@ Parts:
   non-uniform periodic knots (Section 3): Algorithm 1 per test function,
   Algorithm 2 per source with the full table of singular weights, modified
   moments from the local pieces of the Cox-de Boor recurrence.
+* ``wq_open`` (O7): the open arc (Section 2, exterior problem in indirect form;
+  Section 3, all N B-splines of the clamped knot vector; Section 4, p + 2 nodes
+  in the end elements, minimum-norm end systems; K2 = ln|s - t|), assembled by
+  eqs. IK1e2 / IK1e2_bis without mirroring, and the errors E_R, E_M of the
+  parabola test (Section 6, Table 2, pinned to the printed values).
 
 Solutions of A alpha = beta (eq. sistlin) in the tests use LAPACK's FP64
 solve (numpy) directly; there is no oracle solver of its own.

@@ -18,6 +18,16 @@ synthetic closed curves stand in for them):
 * ``star``: r(theta) = 1 + sum_{k=1..6} a_k cos(k theta + phi_k) with
   a_k ~ U(0, 0.1/k), phi_k ~ U(0, 2 pi), drawn from numpy's PCG64 seeded
   with ``[1703, idx]``.
+
+Open arcs (Section 2, exterior problem; Section 6, parabola test):
+
+* ``parabola``: f(t) = (t, 1 - t^2), t in [-1, 1], the quadratic arc with
+  control points (-1, 0), (0, 2), (1, 0) on the knots [-1, -1, -1, 1, 1, 1];
+* ``parabola_phi``: the density sqrt(1 + 4 x1^2) of the test, and
+  ``parabola_uD``: its single-layer potential u_D = V phi on the arc, the
+  Dirichlet datum, in closed form (an exact integral, not a quadrature);
+* ``open_arc_bspline``: seeded open cubic arcs (a wavy open curve) for
+  the general open-arc paths.
 """
 from __future__ import annotations
 
@@ -28,7 +38,8 @@ from typing import Callable, List, Tuple
 import numpy as np
 
 __all__ = [
-    "PolarCurve", "BSplineCurve", "circle", "ellipse_bspline", "ellipse_bspline_nonuniform", "star",
+    "PolarCurve", "BSplineCurve", "OpenBSplineCurve", "circle", "parabola", "parabola_uD", "parabola_phi",
+    "open_arc_bspline", "ellipse_bspline", "ellipse_bspline_nonuniform", "star",
     "g_x2_minus_y2", "g_exp_cos", "Problem", "config_circle", "config_ellipse",
     "config_stars", "config_batch", "config_serving",
 ]
@@ -56,6 +67,17 @@ class BSplineCurve:
     ctrl: np.ndarray
     kind: str = "bspline"
     knots: np.ndarray = None
+
+
+@dataclass(frozen=True)
+class OpenBSplineCurve:
+    """Open arc f(t) = sum_j ctrl[j] B_j(t), t in [knots[0], knots[-1]], on the
+    clamped knot vector ``knots`` (n_ctrl + degree + 1 values, the first and the
+    last degree + 1 equal, the inner ones strictly increasing)."""
+    degree: int
+    ctrl: np.ndarray
+    knots: np.ndarray
+    kind: str = "bspline_open"
 
 
 def circle(r: float = 0.5) -> PolarCurve:
@@ -93,6 +115,67 @@ def star(idx: int, n_modes: int = 6) -> PolarCurve:
     a = rng.uniform(0.0, 0.1 / k)
     phi = rng.uniform(0.0, 2.0 * math.pi, size=n_modes)
     return PolarCurve(r0=1.0, a=a, phi=phi)
+
+
+def parabola() -> OpenBSplineCurve:
+    """The arc of the parabola test: x1 = t, x2 = 1 - t^2, t in [-1, 1]."""
+    return OpenBSplineCurve(degree=2, ctrl=np.array([[-1.0, 0.0], [0.0, 2.0], [1.0, 0.0]]),
+                            knots=np.array([-1.0, -1.0, -1.0, 1.0, 1.0, 1.0]))
+
+
+def open_arc_bspline(idx: int = 0, n_ctrl: int = 12) -> OpenBSplineCurve:
+    """Open cubic arc over [0, 1]: control points (x_j, y_j) with x_j = j / (n - 1)
+    and y_j = 0.3 sin(3 x_j + c) + 0.1 u_j, c ~ U(0, 2 pi), u_j ~ U(-1, 1) from
+    PCG64 seeded with [1703, 50000 + idx]; clamped knots with uniform inner
+    knots (a graph over x1: no self-intersection)."""
+    rng = np.random.default_rng([1703, 50000 + int(idx)])
+    c = rng.uniform(0.0, 2.0 * math.pi)
+    x = np.arange(n_ctrl) / (n_ctrl - 1)
+    y = 0.3 * np.sin(3.0 * x + c) + 0.1 * rng.uniform(-1.0, 1.0, n_ctrl)
+    d = 3
+    inner = np.arange(1, n_ctrl - d) / (n_ctrl - d)
+    knots = np.concatenate([np.zeros(d + 1), inner, np.ones(d + 1)])
+    return OpenBSplineCurve(degree=d, ctrl=np.ascontiguousarray(np.stack([x, y], axis=1)), knots=knots)
+
+
+def parabola_phi(t):
+    """The exact density of the parabola test at f(t): sqrt(1 + 4 t^2)."""
+    t = np.asarray(t, dtype=np.float64)
+    return np.sqrt(1.0 + 4.0 * t * t)
+
+
+def _zlogz(k: int, z):
+    """int_0^z w^k ln|w| dw = z^(k+1) (ln|z| / (k+1) - 1 / (k+1)^2), 0 at z = 0."""
+    z = np.asarray(z, dtype=np.float64)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        v = z ** (k + 1) * (np.log(np.abs(z)) / (k + 1) - 1.0 / (k + 1) ** 2)
+    return np.where(z == 0.0, 0.0, v)
+
+
+def _ulog1p(k: int, u):
+    """Antiderivatives of u^k ln(1 + u^2), k = 0, 1, 2."""
+    u = np.asarray(u, dtype=np.float64)
+    L = np.log1p(u * u)
+    if k == 0:
+        return u * L - 2.0 * u + 2.0 * np.arctan(u)
+    if k == 1:
+        return 0.5 * ((1.0 + u * u) * L - u * u)
+    return u ** 3 / 3.0 * L - 2.0 * u ** 3 / 9.0 + 2.0 * u / 3.0 - 2.0 / 3.0 * np.arctan(u)
+
+
+def parabola_uD(x1, x2=None):
+    """Dirichlet datum of the parabola test, u_D(f(s)) = -(1/2pi) int_{-1}^{1}
+    ln|f(s) - f(t)| phi(f(t)) J(t) dt at the arc point with x1 = s.  On this arc
+    |f(s) - f(t)| = |s - t| sqrt(1 + (s + t)^2) and phi J = 1 + 4 t^2, so the
+    integral is int ln|z| [(1 + 4 s^2) + 8 s z + 4 z^2] dz over z = t - s plus
+    one half of int ln(1 + u^2) [(1 + 4 s^2) - 8 s u + 4 u^2] du over u = s + t,
+    both elementary."""
+    s = np.asarray(x1, dtype=np.float64)
+    c1 = (1.0 + 4.0 * s * s, 8.0 * s, 4.0)
+    I1 = sum(ck * (_zlogz(k, 1.0 - s) - _zlogz(k, -1.0 - s)) for k, ck in enumerate(c1))
+    c2 = (1.0 + 4.0 * s * s, -8.0 * s, 4.0)
+    I2 = sum(ck * (_ulog1p(k, s + 1.0) - _ulog1p(k, s - 1.0)) for k, ck in enumerate(c2))
+    return -(I1 + 0.5 * I2) / (2.0 * math.pi)
 
 
 # Dirichlet data: harmonic functions of the physical point (x1, x2).
