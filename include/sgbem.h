@@ -55,12 +55,13 @@ typedef struct sgbem_ctx_s *sgbem_ctx;       /* one device + one HIP stream     
 typedef struct sgbem_rules_s *sgbem_rules;   /* device-resident quadrature rules (p,N,R) */
 typedef struct sgbem_batch_s *sgbem_batch;   /* device-resident description of many curves */
 
-typedef enum { SGBEM_CURVE_BSPLINE = 0, SGBEM_CURVE_POLAR = 1 } sgbem_curve_kind;
+typedef enum { SGBEM_CURVE_BSPLINE = 0, SGBEM_CURVE_POLAR = 1, SGBEM_CURVE_BSPLINE_OPEN = 2 } sgbem_curve_kind;
 typedef enum { SGBEM_WQ = 0, SGBEM_EBE = 1 } sgbem_method;
 typedef enum { SGBEM_FP64 = 0, SGBEM_FP32 = 1 } sgbem_precision;
 
 /*
- * Closed curve f : [0, 1) -> R^2 (Section 3).  Host memory, read during the
+ * Closed curve f : [0, 1) -> R^2 (Section 3), or open arc f : [a, b] -> R^2
+ * (Section 2, exterior problem; kind BSPLINE_OPEN).  Host memory, read during the
  * call: up to 64 control points (or any polar curve) travel inline in the
  * kernel arguments; larger control nets are copied to device memory owned by
  * the context.
@@ -73,6 +74,13 @@ typedef enum { SGBEM_FP64 = 0, SGBEM_FP32 = 1 } sgbem_precision;
  *           knots = NULL for uniform knots tau_k = k / n_ctrl, else [n_ctrl + 1]
  *           breakpoints 0 = tau_0 < tau_1 < ... < tau_n = 1 (strictly
  *           increasing: simple knots, so the curve is C^(d-1)).
+ *  BSPLINE_OPEN: f(t) = sum_j ctrl[j] B_j(t), t in [a, b], on the open
+ *           (clamped) knot vector knots[n_ctrl + d + 1] (Section 3): the first
+ *           d + 1 knots equal a, the last d + 1 equal b, the inner ones strictly
+ *           increasing inside (a, b); degree d in [1, 7], n_ctrl > d,
+ *           ctrl_xy = [n_ctrl][2].  Served only with rules of sgbem_weights_open
+ *           on the same [a, b] (sgbem_assemble SGBEM_WQ FP64, sgbem_rhs and
+ *           sgbem_rhs_points with SGBEM_WQ); up to 64 control points travel inline.
  *  POLAR:   f(t) = r(theta) (cos theta, sin theta), theta = 2 pi t,
  *           r(theta) = r0 (1 + sum_{k=1..n_modes} a[k-1] cos(k theta + phi[k-1])),
  *           r0 > 0, 0 <= n_modes <= 64, r must stay positive.
@@ -128,13 +136,17 @@ sgbem_status sgbem_ctx_memory(sgbem_ctx ctx, int64_t *held_bytes, int64_t *budge
  *                          the double-layer sweep's workspace;
  *  SGBEM_MEM_SOLVE:        sgbem_solve of order N: 4 N_p^2 + about 1.8 N_p KB,
  *                          N_p = N rounded up to a multiple of 64;
+ *  SGBEM_MEM_RULES_OPEN:   one sgbem_weights_open handle (N = n_el elements):
+ *                          16 N Q_M + 8 n_q^2 + 8 n_q + 8 N bytes, Q_M = 2 n_ref (p + 1)
+ *                          - 1 + 2p, n_q = 2p + 2 n_ref n_el - 1 nodes, plus alignment;
  *  SGBEM_MEM_RULES_KNOTS:  one sgbem_weights handle on non-uniform knots:
  *                          32 M^2 + 16 N Q + 16 M bytes (the full singular table).
  * n_ctrl: control points of the B-spline curve of the call (0 for a polar
  * curve); beyond 64 they are copied to the device, 24 n_ctrl + 8 bytes more.
  * Errors: E_INVAL. */
 typedef enum { SGBEM_MEM_RULES = 0, SGBEM_MEM_ASSEMBLE_WQ = 1, SGBEM_MEM_ASSEMBLE_EBE = 2,
-               SGBEM_MEM_RHS_DIRECT = 3, SGBEM_MEM_SOLVE = 4, SGBEM_MEM_RULES_KNOTS = 5 } sgbem_memory_kind;
+               SGBEM_MEM_RHS_DIRECT = 3, SGBEM_MEM_SOLVE = 4, SGBEM_MEM_RULES_KNOTS = 5,
+               SGBEM_MEM_RULES_OPEN = 6 } sgbem_memory_kind;
 sgbem_status sgbem_memory_need(int32_t what, int32_t p, int32_t N, int32_t n_ref, int32_t n_gauss, int32_t n_ctrl,
                                int64_t *bytes);
 
@@ -216,6 +228,42 @@ sgbem_status sgbem_weights_host(int32_t p, int32_t N, int32_t n_ref,
 sgbem_status sgbem_weights_host_knots(int32_t p, int32_t N, int32_t n_ref, const double *knots,
                                       double *W, double *Bv, double *Ws, double *eta);
 
+/*
+ * Quadrature rules of Section 4 on an open arc (Section 2, exterior problem
+ * in the indirect form eq. prima_BIE), uploaded to the device.  Synchronous.
+ *  - approximation space (Section 3, eq. lift): all N = n_el + p B-splines of
+ *    degree p on the clamped knot vector over the breakpoints
+ *    breaks[0] = a < breaks[1] < ... < breaks[n_el] = b (host, read during the
+ *    call); B_0(a) = B_{N-1}(b) = 1, B_i supported on [T_i, T_{i+p+1}];
+ *  - exactness space: the same on the mesh refined by splitting every element
+ *    into n_ref equal parts (M = n_ref n_el elements, M + p functions);
+ *  - nodes (Section 4): p + 2 equally spaced points in the first and in the last
+ *    refined element, breakpoints and midpoints elsewhere: n_q = 2p + 2M - 1;
+ *  - regular rules (Alg. 1): for each B_i, minimum-norm weights on the nodes
+ *    where B_i is non-zero (underdetermined where an end element is involved);
+ *  - singular rules (Alg. 2): for each node as source s, minimum-norm weights on
+ *    all nodes exact for int Bbar_k(t) ln|t - s| dt (K2 = ln|s - t| as printed in
+ *    Section 3.1), modified moments in closed form (Section 4.2).
+ * The matrix of sgbem_assemble with these rules keeps every entry of eq.
+ * IK1e2_bis (it is not mirrored, so it is not exactly symmetric): each row
+ * integrates the whole spline space, which a mirrored row would not.
+ * Limits: p in [1, 6], n_ref in [1, 4], n_ref n_el >= 2, n_q <= 8192 (else
+ * E_UNSUPPORTED); assembly kernels exist for n_ref in {1, 2}.
+ * Errors: E_INVAL, E_NOMEM, E_DEVICE, E_SINGULAR, E_UNSUPPORTED.
+ */
+sgbem_status sgbem_weights_open(sgbem_ctx ctx, int32_t p, int32_t n_el, int32_t n_ref, const double *breaks,
+                                sgbem_rules *out);
+
+/* Host-only view of the open-arc rules (same arguments as sgbem_weights_open):
+ * *q_max = Q_M, the row length 2 n_ref (p + 1) - 1 + 2p of W and Bv;
+ * n0[N], cnt[N]: row i's support nodes n0[i] .. n0[i] + cnt[i] - 1;
+ * W[N][Q_M] regular weights of B_i on them (zeros beyond cnt[i]), Bv[N][Q_M] B_i
+ * there, Ws[n_q][n_q] singular weights (row m: source eta_m), eta[n_q] node
+ * parameters.  Any output may be NULL (a first call with only q_max gives the
+ * sizes).  Errors: E_INVAL, E_NOMEM, E_SINGULAR, E_UNSUPPORTED. */
+sgbem_status sgbem_weights_host_open(int32_t p, int32_t n_el, int32_t n_ref, const double *breaks, int32_t *q_max,
+                                     int32_t *n0, int32_t *cnt, double *W, double *Bv, double *Ws, double *eta);
+
 /* Host-only reference matrices of the element-by-element near-pair rule
  * (Section 5, Remark): on unit elements with the 16 Gauss-Legendre points u_a
  * and Lagrange polynomials l_a, mco[a][b] = int_0^1 int_0^1 l_a(u) l_b(v) ln|u - v|,
@@ -228,7 +276,8 @@ sgbem_status sgbem_nearfield_host(double *u16, double *w16, double *mco, double 
 /*
  * Points where the Dirichlet datum g must be sampled for sgbem_rhs, written
  * to device memory d_xy as [count][2] FP64 (x, y):
- *   WQ:  f(eta_n), n = 0..2M-1                                   (count = 2M)
+ *   WQ:  f(eta_n), n = 0..2M-1                                   (count = 2M;
+ *        open-arc rules: the n_q nodes of sgbem_weights_open)
  *   EBE: f((e + u_g) / N), e = 0..N-1, g = 0..n_gauss-1 (G-point Gauss-Legendre
  *        nodes on [0, 1])                                         (count = N n_gauss)
  * `cap` is the capacity of d_xy in points; *count receives the count (also
@@ -254,7 +303,10 @@ sgbem_status sgbem_node_points_host(const sgbem_curve *curve, int32_t N, int32_t
  *      factorisation (Alg. 3), the singular rule used for every pair as the paper
  *      does; K1 on the node grid with K1(s, s) = ln J(s) (eq. F1_lim).  The row of
  *      eq. IK1e2_bis is not exactly symmetric: rows i <= j are computed and
- *      mirrored, so d_A is exactly symmetric.
+ *      mirrored, so d_A is exactly symmetric.  Open arcs (rules of
+ *      sgbem_weights_open, a BSPLINE_OPEN curve on the same [a, b]): order
+ *      N = n_el + p, K1(s, t) = ln(|f(s) - f(t)| / |s - t|), every entry of eq.
+ *      IK1e2_bis computed (d_A not symmetric); FP64 only.
  *  EBE (plain form): eq. elbyelint; far element pairs by n_gauss x n_gauss
  *      Gauss-Legendre, coincident / adjacent pairs (the wrap pair included) by the
  *      kernel split: regular part with 16 x 16 Gauss, ln|s - t| part integrated
@@ -262,8 +314,10 @@ sgbem_status sgbem_node_points_host(const sgbem_curve *curve, int32_t N, int32_t
  * FP32: kernel values, products and sums in FP32 (node coordinates are
  *      differenced in FP64); the rule tables stay FP64 until rounded once.
  * Limits: n_gauss in [1, 8] for EBE (ignored by WQ).
- * Errors: E_INVAL, E_UNSUPPORTED (a (p, n_ref) or (p, n_gauss) pair without a
- *      compiled kernel), E_NOMEM, E_DEVICE.
+ * Errors: E_INVAL (also: an open arc with closed-curve rules or the reverse, or
+ *      an arc whose parameter interval is not the rules' [a, b]), E_UNSUPPORTED
+ *      (a (p, n_ref) or (p, n_gauss) pair without a compiled kernel), E_NOMEM,
+ *      E_DEVICE.
  */
 sgbem_status sgbem_assemble(sgbem_ctx ctx, const sgbem_curve *curve, sgbem_rules rules,
                             int32_t method, int32_t n_gauss, int32_t precision,
@@ -295,6 +349,8 @@ sgbem_status sgbem_assemble_noalloc(sgbem_ctx ctx, const sgbem_curve *curve, sgb
 /*
  * Right-hand side beta_i = int B_i J g(f) ds (eq. final_b1), FP64:
  *  WQ:  sum_n w_n^(i) J(eta_n) g_n (Section 5);   EBE: G-point Gauss per element.
+ *  Open arcs: the WQ form with the rules of sgbem_weights_open (the right-hand
+ *  side int B_i J u_D of the indirect form on the arc), d_beta [n_el + p].
  * d_g: device [count] FP64 samples of g at the sgbem_rhs_points of the same
  * method / n_gauss; d_beta: device [N] FP64.  Asynchronous.  Errors: E_INVAL.
  */

@@ -52,13 +52,10 @@ def knot_vector(breaks, p: int) -> np.ndarray:
 
 
 def refine(breaks, R: int) -> np.ndarray:
+    """Every element [x_e, x_{e+1}] split into R equal parts: x_e + (x_{e+1} - x_e) r / R."""
     x = check_breaks(breaks)
-    n = x.size - 1
-    xb = np.empty(R * n + 1)
-    for e in range(n):
-        xb[R * e:R * e + R] = x[e] + (x[e + 1] - x[e]) * np.arange(R) / R
-    xb[-1] = x[-1]
-    return xb
+    inner = x[:-1, None] + (np.diff(x)[:, None] * np.arange(R)[None, :]) / R
+    return np.append(inner.ravel(), x[-1])
 
 
 def nodes(breaks, p: int, R: int) -> np.ndarray:
@@ -92,11 +89,11 @@ def collocation(T, p: int, t) -> np.ndarray:
 
 
 # ---------------------------------------------------------------- Algorithm 1
-def support_nodes(breaks, p: int, R: int, i: int) -> np.ndarray:
+def support_nodes(breaks, p: int, R: int, i: int, eta=None) -> np.ndarray:
     """N^(i): nodes where B_i is non-zero: inside (T_i, T_{i+p+1}), plus a for
-    B_0 and b for B_{N-1}."""
+    B_0 and b for B_{N-1}.  eta: ``nodes(breaks, p, R)`` if already formed."""
     T = knot_vector(breaks, p)
-    eta = nodes(breaks, p, R)
+    eta = nodes(breaks, p, R) if eta is None else eta
     inside = (eta > T[i]) & (eta < T[i + p + 1])
     if i == 0:
         inside |= eta == T[0]
@@ -129,7 +126,7 @@ def regular_weights(breaks, p: int, R: int, rows=None) -> dict:
     N = T.size - p - 1
     for i in (range(N) if rows is None else rows):
         Jset = exactness_set(breaks, p, R, i)
-        Nset = support_nodes(breaks, p, R, i)
+        Nset = support_nodes(breaks, p, R, i, eta)
         el = np.nonzero((xb[:-1] >= T[i]) & (xb[1:] <= T[i + p + 1]))[0]
         h = xb[el + 1] - xb[el]
         tq = (xb[el][:, None] + h[:, None] * gu[None, :]).ravel()
@@ -241,6 +238,26 @@ def full_matrix(curve, breaks, p: int, R: int):
     What = W * J[None, :]
     A_full = -(What @ (K1 @ What.T + Ws @ (J[:, None] * Bmat.T))) / (2.0 * math.pi)
     return A_full, dict(W=W, Ws=Ws, Bmat=Bmat, K1=K1, x=x, y=y, J=J, eta=eta)
+
+
+def full_rows(curve, breaks, p: int, R: int, rows) -> np.ndarray:
+    """Rows of A_full (eqs. IK1e2, IK1e2_bis) without the whole matrix: the
+    singular weights only for the sources in the supports of those rows."""
+    eta = nodes(breaks, p, R)
+    x, y, _, _, J = arc_evaluate(curve, eta)
+    W = regular_weight_matrix(breaks, p, R)
+    Bmat = collocation(knot_vector(breaks, p), p, eta)
+    What = W * J[None, :]
+    src = np.unique(np.concatenate([np.nonzero(W[i])[0] for i in rows]))
+    Ws = singular_weights(breaks, p, R, sources=eta[src])
+    dx = x[src, None] - x[None, :]
+    dy = y[src, None] - y[None, :]
+    dt = eta[src, None] - eta[None, :]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        K1 = 0.5 * np.log((dx * dx + dy * dy) / (dt * dt))
+    K1[np.arange(src.size), src] = np.log(J[src])
+    inner = K1 @ What.T + Ws @ (J[:, None] * Bmat.T)          # (sources, N)
+    return np.array([-(What[i, src] @ inner) / (2.0 * math.pi) for i in rows])
 
 
 def matrix(curve, breaks, p: int, R: int) -> np.ndarray:

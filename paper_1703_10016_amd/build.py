@@ -17,9 +17,9 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsgbem.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-HIP_UNITS = ["api.hip", "kernels.hip", "solve.hip", "batch.hip", "serve.hip", "dlayer.hip", "colloc.hip", "knots.hip",
+HIP_UNITS = ["api.hip", "kernels.hip", "solve.hip", "batch.hip", "serve.hip", "dlayer.hip", "colloc.hip", "knots.hip", "arc.hip",
              "asm_wq_f64.hip", "asm_wq_f32.hip", "asm_ebe_f64.hip", "asm_ebe_f32.hip"]
-CXX_UNITS = ["planner.cpp", "planner_knots.cpp"]
+CXX_UNITS = ["planner.cpp", "planner_knots.cpp", "planner_open.cpp"]
 # the register-resident LU panel needs its 64 x 64 column loop fully unrolled
 UNIT_FLAGS = {"solve.hip": ["-mllvm", "-pragma-unroll-threshold=1000000"]}
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -21,6 +21,7 @@
 #include "dlayer.hpp"
 #include "colloc.hpp"
 #include "knots.hpp"
+#include "arc.hpp"
 
 namespace sgbem {
 hipError_t launch_wq_f64(int p, int P, const TileArgs &a, hipStream_t s, const KernelEvents *ev);
@@ -142,6 +143,13 @@ size_t knot_rules_block_bytes(int N, int R, int p)
     return 2 * align256(size_t(N) * Q * 8) + align256(nn * nn * 8) + align256(nn * 8);
 }
 
+size_t open_rules_block_bytes(int n_el, int R, int p)
+{
+    const size_t N = size_t(n_el) + size_t(p), QM = size_t(arc_qm(p, 2 * R));
+    const size_t nn = size_t(2 * p) + size_t(2) * R * size_t(n_el) - 1;
+    return 2 * align256(N * QM * 8) + align256(nn * nn * 8) + align256(nn * 8) + 2 * align256(N * 4);
+}
+
 void free_rules(sgbem_rules r)
 {
     if (!r) return;
@@ -224,10 +232,27 @@ namespace {
 }  // namespace
 
 namespace sgbem {
-sgbem_status check_curve(const sgbem_curve *c)
+sgbem_status check_curve(const sgbem_curve *c, bool open)
 {
     if (!c) return set_err(SGBEM_E_INVAL, "curve is NULL");
-    if (c->kind == SGBEM_CURVE_BSPLINE) {
+    if (open && c->kind != SGBEM_CURVE_BSPLINE_OPEN)
+        return set_err(SGBEM_E_INVAL, "rules of sgbem_weights_open need an open arc (SGBEM_CURVE_BSPLINE_OPEN)");
+    if (c->kind == SGBEM_CURVE_BSPLINE_OPEN) {
+        if (!open)
+            return set_err(SGBEM_E_INVAL, "an open arc needs the rules of sgbem_weights_open and the fast form");
+        const int d = c->degree, n = c->n_ctrl;
+        if (d < 1 || d > 7) return set_err(SGBEM_E_INVAL, "B-spline curve degree must be in [1, 7]");
+        if (n <= d) return set_err(SGBEM_E_INVAL, "B-spline curve needs n_ctrl > degree");
+        if (!c->ctrl_xy || !c->knots) return set_err(SGBEM_E_INVAL, "open arc without control points or knots");
+        const double *k = c->knots;
+        const double a = k[0], b = k[n + d];
+        if (!std::isfinite(a) || !std::isfinite(b) || !(b > a)) return set_err(SGBEM_E_INVAL, "open arc: knots[0] < knots[n_ctrl + d] needed");
+        for (int i = 0; i <= d; ++i)
+            if (k[i] != a || k[n + i] != b)
+                return set_err(SGBEM_E_INVAL, "open arc: the first and the last d + 1 knots must be equal (clamped)");
+        for (int i = d; i < n; ++i)
+            if (!(k[i + 1] > k[i])) return set_err(SGBEM_E_INVAL, "open arc: inner knots must be strictly increasing");
+    } else if (c->kind == SGBEM_CURVE_BSPLINE) {
         if (c->degree < 1 || c->degree > 7) return set_err(SGBEM_E_INVAL, "B-spline curve degree must be in [1, 7]");
         if (c->n_ctrl <= c->degree) return set_err(SGBEM_E_INVAL, "B-spline curve needs n_ctrl > degree");
         if (!c->ctrl_xy) return set_err(SGBEM_E_INVAL, "B-spline curve without control points");
@@ -256,14 +281,20 @@ sgbem_status check_curve(const sgbem_curve *c)
 namespace {
 
 // Device description of a curve whose arrays fit the inline storage.
-sgbem_status inline_curve(const sgbem_curve *cv, CurveDev &d)
+sgbem_status inline_curve(const sgbem_curve *cv, CurveDev &d, bool open = false)
 {
-    sgbem_status st = check_curve(cv);
+    sgbem_status st = check_curve(cv, open);
     if (st) return st;
     std::memset(&d, 0, sizeof d);
     d.kind = cv->kind;
     d.inline_data = 1;
-    if (cv->kind == SGBEM_CURVE_BSPLINE) {
+    if (cv->kind == SGBEM_CURVE_BSPLINE_OPEN) {
+        if (cv->n_ctrl > 64) return set_err(SGBEM_E_UNSUPPORTED, "a curve that travels inline has at most 64 control points");
+        d.degree = cv->degree;
+        d.n_ctrl = cv->n_ctrl;
+        std::memcpy(d.inl, cv->ctrl_xy, size_t(cv->n_ctrl) * 2 * sizeof(double));
+        std::memcpy(d.inl + 128, cv->knots, size_t(cv->n_ctrl + cv->degree + 1) * sizeof(double));
+    } else if (cv->kind == SGBEM_CURVE_BSPLINE) {
         if (cv->n_ctrl > 64) return set_err(SGBEM_E_UNSUPPORTED, "a curve that travels inline has at most 64 control points");
         d.degree = cv->degree;
         d.n_ctrl = cv->n_ctrl;
@@ -319,13 +350,14 @@ sgbem_status scratch_address(int device, double *&out)
 }
 
 // Upload the curve's arrays and return the device description.
-sgbem_status upload_curve(sgbem_ctx c, const sgbem_curve *cv, CurveDev &d)
+sgbem_status upload_curve(sgbem_ctx c, const sgbem_curve *cv, CurveDev &d, bool open = false)
 {
-    sgbem_status st = check_curve(cv);
+    sgbem_status st = check_curve(cv, open);
     if (st) return st;
     std::memset(&d, 0, sizeof d);
     d.kind = cv->kind;
-    if (cv->kind == SGBEM_CURVE_BSPLINE && cv->n_ctrl <= 64) return inline_curve(cv, d);
+    if ((cv->kind == SGBEM_CURVE_BSPLINE || cv->kind == SGBEM_CURVE_BSPLINE_OPEN) && cv->n_ctrl <= 64)
+        return inline_curve(cv, d, open);
     if (cv->kind == SGBEM_CURVE_POLAR) {
         d.r0 = cv->r0;
         d.n_modes = cv->n_modes;
@@ -337,11 +369,12 @@ sgbem_status upload_curve(sgbem_ctx c, const sgbem_curve *cv, CurveDev &d)
         return SGBEM_OK;
     }
     {
-        // control points, then the knots of a non-uniform curve
+        // control points, then the knots of a non-uniform curve or of an open arc
         d.degree = cv->degree;
         d.n_ctrl = cv->n_ctrl;
+        const bool arc = cv->kind == SGBEM_CURVE_BSPLINE_OPEN;
         const size_t bc = size_t(cv->n_ctrl) * 2 * sizeof(double);
-        const size_t bk = cv->knots ? size_t(cv->n_ctrl + 1) * sizeof(double) : 0;
+        const size_t bk = cv->knots ? size_t(cv->n_ctrl + 1 + (arc ? cv->degree : 0)) * sizeof(double) : 0;
         if ((st = ensure(c, c->params, bc + bk))) return st;
         HIPCHK(hipMemcpyAsync(c->params.ptr, cv->ctrl_xy, bc, hipMemcpyHostToDevice, c->stream));
         d.ctrl = static_cast<const double *>(c->params.ptr);
@@ -349,7 +382,7 @@ sgbem_status upload_curve(sgbem_ctx c, const sgbem_curve *cv, CurveDev &d)
             double *kd = static_cast<double *>(c->params.ptr) + 2 * size_t(cv->n_ctrl);
             HIPCHK(hipMemcpyAsync(kd, cv->knots, bk, hipMemcpyHostToDevice, c->stream));
             d.knots = kd;
-            d.nonuniform = 1;
+            d.nonuniform = arc ? 0 : 1;
         }
     }
     return SGBEM_OK;
@@ -372,7 +405,7 @@ GridDesc wq_grid(sgbem_rules r)
     g.N = r->N;
     g.P = 0;
     g.npts = int(r->npts);
-    g.tpar = r->knots ? r->d_eta : nullptr;   // non-uniform knots: the node parameters
+    g.tpar = (r->knots || r->open) ? r->d_eta : nullptr;   // non-uniform knots, open arcs: the node parameters
     return g;
 }
 
@@ -523,7 +556,7 @@ sgbem_status sgbem_memory_need(int32_t what, int32_t p, int32_t N, int32_t n_ref
     *bytes = 0;
     if (N < 1 || N > (1 << 24) || n_ctrl < 0) return set_err(SGBEM_E_INVAL, "bad N or n_ctrl");
     const bool need_rules = what == SGBEM_MEM_RULES || what == SGBEM_MEM_ASSEMBLE_WQ || what == SGBEM_MEM_RHS_DIRECT ||
-                            what == SGBEM_MEM_RULES_KNOTS;
+                            what == SGBEM_MEM_RULES_KNOTS || what == SGBEM_MEM_RULES_OPEN;
     if (need_rules && (n_ref < 1 || n_ref > 4)) return set_err(SGBEM_E_INVAL, "n_ref must be in [1, 4]");
     if (what != SGBEM_MEM_SOLVE && (p < 1 || p > 6)) return set_err(SGBEM_E_INVAL, "p must be in [1, 6]");
     const size_t n = size_t(N), M = size_t(n_ref) * n;
@@ -558,6 +591,9 @@ sgbem_status sgbem_memory_need(int32_t what, int32_t p, int32_t N, int32_t n_ref
         break;
     case SGBEM_MEM_RULES_KNOTS:
         b = buf_bytes(knot_rules_block_bytes(N, n_ref, p));
+        break;
+    case SGBEM_MEM_RULES_OPEN:
+        b = buf_bytes(open_rules_block_bytes(N, n_ref, p));
         break;
     default:
         return set_err(SGBEM_E_INVAL, "unknown memory kind");
@@ -730,6 +766,145 @@ sgbem_status make_knot_rules(sgbem_ctx c, int p, int N, int R, const double *kno
 }
 }  // namespace
 
+namespace {
+// Rules on an open arc: built on the host, uploaded into one block of the
+// context (within its budget); the tile windows of the assembly are checked here.
+sgbem_status make_open_rules(sgbem_ctx c, int p, int n_el, int R, const double *breaks, sgbem_rules &out)
+{
+    out = nullptr;
+    WQRulesOpen K;
+    try {
+        K = build_wq_rules_open(p, n_el, R, breaks);
+    } catch (const PlanError &e) {
+        return set_err(sgbem_status(e.status), e.msg);
+    } catch (const std::bad_alloc &) {
+        return set_err(SGBEM_E_NOMEM, "host allocation failed");
+    }
+    const int N = K.N, P = 2 * R, QM = arc_qm(p, P);
+    if (K.QM > QM) return set_err(SGBEM_E_SINGULAR, "open-arc rules: a support longer than its bound (internal)");
+    for (int I0 = 0; I0 < N; I0 += kArcTile)
+        if (K.n0[size_t(std::min(I0 + kArcTile - 1, N - 1))] - K.n0[size_t(I0)] + QM > arc_window(p, P))
+            return set_err(SGBEM_E_UNSUPPORTED, "open-arc rules: a tile's node window exceeds the kernel's (internal)");
+    const size_t nb = buf_bytes(open_rules_block_bytes(n_el, R, p));
+    void *block = nullptr;
+    sgbem_status st = ctx_malloc(c, &block, nb);
+    if (st) return st;
+    auto *r = new (std::nothrow) sgbem_rules_s;
+    if (!r) {
+        ctx_free(c, block, nb);
+        return set_err(SGBEM_E_NOMEM, "host allocation failed");
+    }
+    r->p = p;
+    r->N = N;
+    r->R = R;
+    r->Q = QM;
+    r->QM = QM;
+    r->M = K.M;
+    r->npts = K.n_nodes;
+    r->open = true;
+    r->n_el = n_el;
+    r->a = breaks[0];
+    r->b = breaks[n_el];
+    r->block = block;
+    r->block_bytes = nb;
+    r->owned = true;
+    const size_t NQ = size_t(N) * QM, nn = size_t(K.n_nodes);
+    std::vector<double> Wp(NQ, 0.0), Bp(NQ, 0.0);    // rows padded from K.QM to the kernel's QM
+    for (int i = 0; i < N; ++i)
+        for (int q = 0; q < K.QM; ++q) {
+            Wp[size_t(i) * QM + q] = K.W[size_t(i) * K.QM + q];
+            Bp[size_t(i) * QM + q] = K.Bv[size_t(i) * K.QM + q];
+        }
+    char *b = static_cast<char *>(block);
+    r->d_W = reinterpret_cast<double *>(b);
+    b += align256(NQ * 8);
+    r->d_Bv = reinterpret_cast<double *>(b);
+    b += align256(NQ * 8);
+    r->d_Wsg = reinterpret_cast<double *>(b);
+    b += align256(nn * nn * 8);
+    r->d_eta = reinterpret_cast<double *>(b);
+    b += align256(nn * 8);
+    r->d_n0 = reinterpret_cast<int32_t *>(b);
+    b += align256(size_t(N) * 4);
+    r->d_cnt = reinterpret_cast<int32_t *>(b);
+    try {
+        r->n0 = K.n0;
+    } catch (...) {
+        ctx_free(c, block, nb);
+        delete r;
+        return set_err(SGBEM_E_NOMEM, "host allocation failed");
+    }
+    hipError_t e = hipMemcpy(r->d_W, Wp.data(), NQ * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(r->d_Bv, Bp.data(), NQ * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(r->d_Wsg, K.Ws.data(), nn * nn * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(r->d_eta, K.eta.data(), nn * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(r->d_n0, K.n0.data(), size_t(N) * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(r->d_cnt, K.cnt.data(), size_t(N) * 4, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        ctx_free(c, block, nb);
+        delete r;
+        return set_err(SGBEM_E_DEVICE, std::string("rules upload: ") + hipGetErrorString(e));
+    }
+    out = r;
+    return SGBEM_OK;
+}
+}  // namespace
+
+sgbem_status sgbem_weights_open(sgbem_ctx c, int32_t p, int32_t n_el, int32_t n_ref, const double *breaks,
+                                sgbem_rules *out)
+{
+    if (!c || !out || !breaks) return set_err(SGBEM_E_INVAL, "ctx, breaks or out is NULL");
+    *out = nullptr;
+    if (p < 1 || p > 6 || n_ref < 1 || n_ref > 4 || n_el < 1 || int64_t(n_ref) * n_el < 2)
+        return set_err(SGBEM_E_INVAL, "need p in [1, 6], n_ref in [1, 4], n_ref n_el >= 2");
+    if (int64_t(2) * p + int64_t(2) * n_ref * n_el - 1 > kMaxKnotNodes)
+        return set_err(SGBEM_E_UNSUPPORTED, "open arc: 2p + 2 n_ref n_el - 1 exceeds the limit of the full singular table");
+    DeviceGuard g(c->device);
+    sgbem_rules r = nullptr;
+    sgbem_status st = make_open_rules(c, p, n_el, n_ref, breaks, r);
+    if (st) return st;
+    try {
+        c->rules.push_back(r);
+    } catch (...) {
+        ctx_free(c, r->block, r->block_bytes);
+        r->owned = false;
+        free_rules(r);
+        return set_err(SGBEM_E_NOMEM, "host allocation failed");
+    }
+    *out = r;
+    return SGBEM_OK;
+}
+
+sgbem_status sgbem_weights_host_open(int32_t p, int32_t n_el, int32_t n_ref, const double *breaks, int32_t *q_max,
+                                     int32_t *n0, int32_t *cnt, double *W, double *Bv, double *Ws, double *eta)
+{
+    if (!breaks) return set_err(SGBEM_E_INVAL, "breaks is NULL");
+    if (p < 1 || p > 6 || n_ref < 1 || n_ref > 4 || n_el < 1 || int64_t(n_ref) * n_el < 2)
+        return set_err(SGBEM_E_INVAL, "need p in [1, 6], n_ref in [1, 4], n_ref n_el >= 2");
+    const int QM = arc_qm(p, 2 * n_ref);
+    if (q_max) *q_max = QM;
+    if (!n0 && !cnt && !W && !Bv && !Ws && !eta) return SGBEM_OK;
+    try {
+        const WQRulesOpen K = build_wq_rules_open(p, n_el, n_ref, breaks);
+        if (K.QM > QM) return set_err(SGBEM_E_SINGULAR, "open-arc rules: a support longer than its bound (internal)");
+        if (n0) std::memcpy(n0, K.n0.data(), K.n0.size() * sizeof(int32_t));
+        if (cnt) std::memcpy(cnt, K.cnt.data(), K.cnt.size() * sizeof(int32_t));
+        for (int i = 0; i < K.N; ++i)
+            for (int q = 0; q < QM; ++q) {
+                const bool in = q < K.QM;
+                if (W) W[size_t(i) * QM + q] = in ? K.W[size_t(i) * K.QM + q] : 0.0;
+                if (Bv) Bv[size_t(i) * QM + q] = in ? K.Bv[size_t(i) * K.QM + q] : 0.0;
+            }
+        if (Ws) std::memcpy(Ws, K.Ws.data(), K.Ws.size() * sizeof(double));
+        if (eta) std::memcpy(eta, K.eta.data(), K.eta.size() * sizeof(double));
+    } catch (const PlanError &e) {
+        return set_err(sgbem_status(e.status), e.msg);
+    } catch (const std::bad_alloc &) {
+        return set_err(SGBEM_E_NOMEM, "host allocation failed");
+    }
+    return SGBEM_OK;
+}
+
 sgbem_status sgbem_weights(sgbem_ctx c, int32_t p, int32_t N, int32_t n_ref, const double *knots, sgbem_rules *out)
 {
     if (!c || !out) return set_err(SGBEM_E_INVAL, "ctx or out is NULL");
@@ -800,6 +975,18 @@ sgbem_status sgbem_rules_free(sgbem_ctx c, sgbem_rules r)
     return SGBEM_OK;
 }
 
+namespace {
+// An open arc served by open-arc rules must have the rules' parameter interval.
+sgbem_status check_arc_interval(const sgbem_curve *curve, sgbem_rules r)
+{
+    if (!r->open || !curve || curve->kind != SGBEM_CURVE_BSPLINE_OPEN || !curve->knots) return SGBEM_OK;
+    const double a = curve->knots[0], b = curve->knots[curve->n_ctrl + curve->degree];
+    if (a != r->a || b != r->b)
+        return set_err(SGBEM_E_INVAL, "open arc: the curve's parameter interval differs from the rules' [a, b]");
+    return SGBEM_OK;
+}
+}  // namespace
+
 sgbem_status sgbem_rhs_points(sgbem_ctx c, const sgbem_curve *curve, sgbem_rules r, int32_t method, int32_t n_gauss,
                               double *d_xy, int64_t cap, int64_t *count)
 {
@@ -807,13 +994,16 @@ sgbem_status sgbem_rhs_points(sgbem_ctx c, const sgbem_curve *curve, sgbem_rules
     if (!valid_rules(c, r)) return set_err(SGBEM_E_INVAL, "rules handle does not belong to this context");
     if (method != SGBEM_WQ && method != SGBEM_EBE) return set_err(SGBEM_E_INVAL, "unknown method");
     if (r->knots && method != SGBEM_WQ) return set_err(SGBEM_E_UNSUPPORTED, "rules on non-uniform knots: fast-form assembly and its right-hand side only");
+    if (r->open && method != SGBEM_WQ) return set_err(SGBEM_E_UNSUPPORTED, "open-arc rules: fast-form assembly (FP64), its right-hand side and node points only");
     if (method == SGBEM_EBE && (n_gauss < 1 || n_gauss > 8)) return set_err(SGBEM_E_INVAL, "n_gauss must be in [1, 8]");
     DeviceGuard g(c->device);
     const GridDesc grid = method == SGBEM_WQ ? wq_grid(r) : gauss_grid(r->N, n_gauss);
     *count = grid.npts;
     if (cap < grid.npts || !d_xy) return set_err(SGBEM_E_INVAL, "output capacity too small");
     CurveDev cd;
-    sgbem_status st = upload_curve(c, curve, cd);
+    sgbem_status st = check_arc_interval(curve, r);
+    if (st) return st;
+    st = upload_curve(c, curve, cd, r->open);
     if (st) return st;
     double *X, *Y, *J;
     if ((st = geometry(c, cd, grid, c->geo, X, Y, J))) return st;
@@ -832,6 +1022,39 @@ sgbem_status sgbem_assemble(sgbem_ctx c, const sgbem_curve *curve, sgbem_rules r
     if (method == SGBEM_EBE && (n_gauss < 1 || n_gauss > 8)) return set_err(SGBEM_E_INVAL, "n_gauss must be in [1, 8]");
     const int p = r->p, N = r->N;
     const int P = method == SGBEM_WQ ? 2 * r->R : n_gauss;
+    if (r->open) {
+        // open arc: ragged per-row rules, the full singular table, every entry of eq. IK1e2_bis
+        if (method != SGBEM_WQ || precision != SGBEM_FP64 || !assemble_arc_supported(p, P))
+            return set_err(SGBEM_E_UNSUPPORTED, "open-arc rules: FP64 fast form with n_ref in {1, 2} only");
+        sgbem_status st = check_arc_interval(curve, r);
+        if (st) return st;
+        DeviceGuard g(c->device);
+        CurveDev cd;
+        if ((st = upload_curve(c, curve, cd, true))) return st;
+        const GridDesc grid = wq_grid(r);
+        double *X, *Y, *J;
+        if ((st = geometry(c, cd, grid, c->geo, X, Y, J))) return st;
+        ArcArgs aa;
+        aa.N = N;
+        aa.npts = grid.npts;
+        aa.P = P;
+        aa.X = X;
+        aa.Y = Y;
+        aa.J = J;
+        aa.eta = r->d_eta;
+        aa.W = r->d_W;
+        aa.Bv = r->d_Bv;
+        aa.Ws = r->d_Wsg;
+        aa.n0 = r->d_n0;
+        aa.scale = -1.0 / (2.0 * kPi);
+        aa.out = static_cast<double *>(d_A);
+        aa.lda = lda;
+        KernelEvents ke;
+        const KernelEvents *kev;
+        if ((st = timing_events(c, ke, kev))) return st;
+        HIPCHK(launch_assemble_arc(p, aa, c->stream, kev));
+        return SGBEM_OK;
+    }
     if (r->knots) {
         // non-uniform knots: per-row rules and the full singular table (FP64 fast form)
         if (method != SGBEM_WQ || precision != SGBEM_FP64 || !assemble_knots_supported(p, P))
@@ -936,6 +1159,7 @@ sgbem_status sgbem_assemble_noalloc(sgbem_ctx c, const sgbem_curve *curve, sgbem
     if (r->npts > SGBEM_NOALLOC_MAX_NODES)
         return set_err(SGBEM_E_INVAL, "2 n_ref N exceeds SGBEM_NOALLOC_MAX_NODES (the fixed geometry array)");
     if (r->knots) return set_err(SGBEM_E_UNSUPPORTED, "rules on non-uniform knots: fast-form assembly and its right-hand side only");
+    if (r->open) return set_err(SGBEM_E_UNSUPPORTED, "open-arc rules: fast-form assembly (FP64), its right-hand side and node points only");
     const int p = r->p, P = 2 * r->R;
     if (!assemble_supported(SGBEM_WQ, precision, p, P))
         return set_err(SGBEM_E_UNSUPPORTED, "no kernel compiled for this (p, n_ref)");
@@ -965,16 +1189,19 @@ sgbem_status sgbem_rhs(sgbem_ctx c, const sgbem_curve *curve, sgbem_rules r, int
     if (!valid_rules(c, r)) return set_err(SGBEM_E_INVAL, "rules handle does not belong to this context");
     if (method != SGBEM_WQ && method != SGBEM_EBE) return set_err(SGBEM_E_INVAL, "unknown method");
     if (method == SGBEM_EBE && (n_gauss < 1 || n_gauss > 8)) return set_err(SGBEM_E_INVAL, "n_gauss must be in [1, 8]");
+    if (r->open && method != SGBEM_WQ) return set_err(SGBEM_E_UNSUPPORTED, "open-arc rules: fast-form assembly (FP64), its right-hand side and node points only");
+    sgbem_status st = check_arc_interval(curve, r);
+    if (st) return st;
     DeviceGuard g(c->device);
     CurveDev cd;
-    sgbem_status st = upload_curve(c, curve, cd);
-    if (st) return st;
+    if ((st = upload_curve(c, curve, cd, r->open))) return st;
     const int p = r->p, N = r->N;
     if (method == SGBEM_WQ) {
         const GridDesc grid = wq_grid(r);
         double *X, *Y, *J;
         if ((st = geometry(c, cd, grid, c->geo, X, Y, J))) return st;
-        if (r->knots) HIPCHK(launch_rhs_knots(N, grid.npts, 2 * r->R, r->Q, r->d_W, J, d_g, d_beta, c->stream));
+        if (r->open) HIPCHK(launch_rhs_arc(N, r->QM, r->d_n0, r->d_cnt, r->d_W, J, d_g, d_beta, c->stream));
+        else if (r->knots) HIPCHK(launch_rhs_knots(N, grid.npts, 2 * r->R, r->Q, r->d_W, J, d_g, d_beta, c->stream));
         else HIPCHK(launch_rhs(N, grid.npts, 2 * r->R, 1, r->Q, r->d_w0, 1.0, J, d_g, d_beta, c->stream));
         return SGBEM_OK;
     }
@@ -997,6 +1224,7 @@ sgbem_status sgbem_rhs_direct(sgbem_ctx c, const sgbem_curve *curve, sgbem_rules
     if (n_gauss < 2 || n_gauss > 8 || (n_gauss & 1))
         return set_err(SGBEM_E_INVAL, "n_gauss must be 2, 4, 6 or 8 (even: no Gauss point on a node)");
     if (r->knots) return set_err(SGBEM_E_UNSUPPORTED, "rules on non-uniform knots: fast-form assembly and its right-hand side only");
+    if (r->open) return set_err(SGBEM_E_UNSUPPORTED, "open-arc rules: fast-form assembly (FP64), its right-hand side and node points only");
     DeviceGuard g(c->device);
     CurveDev cd;
     sgbem_status st = upload_curve(c, curve, cd);
@@ -1035,6 +1263,7 @@ sgbem_status sgbem_assemble_collocation(sgbem_ctx c, const sgbem_curve *curve, s
     if (!valid_rules(c, r)) return set_err(SGBEM_E_INVAL, "rules handle does not belong to this context");
     if (lda < r->N) return set_err(SGBEM_E_INVAL, "lda < N");
     if (r->knots) return set_err(SGBEM_E_UNSUPPORTED, "rules on non-uniform knots: fast-form assembly and its right-hand side only");
+    if (r->open) return set_err(SGBEM_E_UNSUPPORTED, "open-arc rules: fast-form assembly (FP64), its right-hand side and node points only");
     const int p = r->p, P = 2 * r->R;
     if (!colloc_supported(p, P)) return set_err(SGBEM_E_UNSUPPORTED, "collocation: n_ref in {1, 2} only");
     DeviceGuard g(c->device);
@@ -1072,6 +1301,7 @@ sgbem_status sgbem_collocation_rhs(sgbem_ctx c, sgbem_rules r, const double *d_g
     if (!c || !r || !d_g_nodes || !d_b) return set_err(SGBEM_E_INVAL, "NULL argument");
     if (!valid_rules(c, r)) return set_err(SGBEM_E_INVAL, "rules handle does not belong to this context");
     if (r->knots) return set_err(SGBEM_E_UNSUPPORTED, "rules on non-uniform knots: fast-form assembly and its right-hand side only");
+    if (r->open) return set_err(SGBEM_E_UNSUPPORTED, "open-arc rules: fast-form assembly (FP64), its right-hand side and node points only");
     DeviceGuard g(c->device);
     HIPCHK(launch_colloc_gather(r->N, int(r->npts), 2 * r->R, r->R * (r->p + 1), d_g_nodes, d_b, c->stream));
     return SGBEM_OK;
@@ -1096,6 +1326,7 @@ sgbem_status sgbem_batch_create(sgbem_ctx c, int32_t n, const sgbem_curve *curve
         sgbem_rules r = rules[b];
         if (!r || !valid_rules(c, r)) return set_err(SGBEM_E_INVAL, "batch: rules handle does not belong to this context");
         if (r->knots) return set_err(SGBEM_E_UNSUPPORTED, "batch: rules on non-uniform knots are not batched");
+        if (r->open) return set_err(SGBEM_E_UNSUPPORTED, "batch: open-arc rules are not batched");
         if (r->R != 1 || r->p < 2 || r->p > 4)
             return set_err(SGBEM_E_UNSUPPORTED, "batch: n_ref = 1 and p in {2, 3, 4} only");
         if (!d_A[b] || lda[b] < r->N) return set_err(SGBEM_E_INVAL, "batch: NULL matrix or lda < N");

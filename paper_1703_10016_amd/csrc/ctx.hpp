@@ -68,6 +68,14 @@ struct sgbem_rules_s {
     // W[N][Q], Bv[N][Q], Ws[2M][2M], eta[2M] in the block
     bool knots = false;
     double *d_W = nullptr, *d_Bv = nullptr, *d_Wsg = nullptr, *d_eta = nullptr;
+    // rules on an open arc (sgbem_weights_open): N = n_el + p, npts = 2p + 2M - 1,
+    // W[N][QM], Bv[N][QM], Ws[npts][npts], eta[npts], n0[N], cnt[N] in the block
+    // (d_W, d_Bv, d_Wsg, d_eta as above); [a, b] the parameter interval
+    bool open = false;
+    int QM = 0, n_el = 0;
+    double a = 0.0, b = 0.0;
+    int32_t *d_n0 = nullptr, *d_cnt = nullptr;
+    std::vector<int32_t> n0;      // host copy of n0 (tile windows are checked at launch)
 };
 
 struct sgbem_batch_s {
@@ -131,6 +139,7 @@ size_t rules_block_bytes(int64_t npts);
 
 // Bytes of the device block of rules on non-uniform knots.
 size_t knot_rules_block_bytes(int N, int R, int p);
+size_t open_rules_block_bytes(int n_el, int R, int p);
 
 // Build the rules of (p, N, R) on the host and upload them on `stream`
 // (synchronised before return).  block: device memory of rules_block_bytes
@@ -142,6 +151,6 @@ void free_rules(sgbem_rules r);
 bool valid_rules(sgbem_ctx c, sgbem_rules r);
 
 // Argument check of a curve description.
-sgbem_status check_curve(const sgbem_curve *c);
+sgbem_status check_curve(const sgbem_curve *c, bool open = false);
 
 }  // namespace sgbem

@@ -4,7 +4,10 @@
 //  B-spline (periodic knots, Section 3): de Boor's algorithm on the span
 //           containing t, and on the derivative curve with control points
 //           d (Q_j - Q_{j-1}) / (tau_{j+d} - tau_j) at degree d-1 (uniform
-//           knots tau_k = k / n_ctrl: n_ctrl (Q_j - Q_{j-1})).
+//           knots tau_k = k / n_ctrl: n_ctrl (Q_j - Q_{j-1}));
+//  open B-spline (clamped knot vector T of n_ctrl + d + 1 values, Section 3):
+//           the same on the span T_l <= t < T_{l+1}, d <= l < n_ctrl (the
+//           last span also holds t = T_{n_ctrl}).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -64,31 +67,45 @@ __host__ __device__ __forceinline__ void eval_curve_d(const CurveDev &c, double 
         y = r * sn;
         dx = 6.283185307179586476925286766559 * (dr * cs - r * sn);
         dy = 6.283185307179586476925286766559 * (dr * sn + r * cs);
-    } else if (c.nonuniform) {
-        // breakpoints tau_0 = 0 < ... < tau_n = 1 of one period, tau_{k+n} = tau_k + 1;
-        // B_j supported on [tau_j, tau_{j+d+1})
+    } else if (c.kind == 2 || c.nonuniform) {
         const int d = c.degree, nc = c.n_ctrl;
         const double *tk = c.inline_data ? c.inl + 128 : c.knots;
-        int lo = 0, hi = nc - 1;      // the span l with tau_l <= t < tau_{l+1}
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (tk[mid] <= t) lo = mid;
-            else hi = mid - 1;
-        }
-        const int l = lo;
-        // tau_k for k in [l - d, l + d]
-        double tau[16];
-        for (int i = 0; i <= 2 * d; ++i) {
-            const int k = l - d + i;
-            const int kk = k < 0 ? k + nc : (k >= nc ? k - nc : k);
-            tau[i] = tk[kk] + (k < 0 ? -1.0 : (k >= nc ? 1.0 : 0.0));
-        }
-        double px[8], py[8];
-        for (int i = 0; i <= d; ++i) {
-            int j = l - d + i;
-            j = ((j % nc) + nc) % nc;
-            px[i] = cq[2 * j];
-            py[i] = cq[2 * j + 1];
+        // tau[i] = knot l - d + i, i = 0 .. 2d, and the control points l - d .. l of the span l
+        double tau[16], px[8], py[8];
+        if (c.kind == 2) {
+            int lo = d, hi = nc - 1;      // the span l with T_l <= t < T_{l+1}
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (tk[mid] <= t) lo = mid;
+                else hi = mid - 1;
+            }
+            const int l = lo;
+            for (int i = 0; i <= 2 * d; ++i) tau[i] = tk[l - d + i];
+            for (int i = 0; i <= d; ++i) {
+                px[i] = cq[2 * (l - d + i)];
+                py[i] = cq[2 * (l - d + i) + 1];
+            }
+        } else {
+            // breakpoints tau_0 = 0 < ... < tau_n = 1 of one period, tau_{k+n} = tau_k + 1;
+            // B_j supported on [tau_j, tau_{j+d+1})
+            int lo = 0, hi = nc - 1;      // the span l with tau_l <= t < tau_{l+1}
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (tk[mid] <= t) lo = mid;
+                else hi = mid - 1;
+            }
+            const int l = lo;
+            for (int i = 0; i <= 2 * d; ++i) {
+                const int k = l - d + i;
+                const int kk = k < 0 ? k + nc : (k >= nc ? k - nc : k);
+                tau[i] = tk[kk] + (k < 0 ? -1.0 : (k >= nc ? 1.0 : 0.0));
+            }
+            for (int i = 0; i <= d; ++i) {
+                int j = l - d + i;
+                j = ((j % nc) + nc) % nc;
+                px[i] = cq[2 * j];
+                py[i] = cq[2 * j + 1];
+            }
         }
         // derivative control points d (Q_j - Q_{j-1}) / (tau_{j+d} - tau_j), j = l-d+1 .. l
         double qx[8], qy[8];

@@ -9,18 +9,18 @@ namespace sgbem {
 
 // Curve description in device memory.
 struct CurveDev {
-    int kind;        // 0 = periodic B-spline, 1 = polar
+    int kind;        // 0 = periodic B-spline, 1 = polar, 2 = open B-spline (clamped knots)
     int degree;      // B-spline degree d
     int n_ctrl;      // B-spline control points
     int n_modes;     // polar Fourier modes
     double r0;       // polar base radius
     const double *ctrl;   // [n_ctrl][2]
-    const double *knots;  // [n_ctrl + 1] breakpoints of one period (nonuniform only)
+    const double *knots;  // [n_ctrl + 1] breakpoints of one period (nonuniform), [n_ctrl + degree + 1] (open)
     const double *a;      // [n_modes]
     const double *phi;    // [n_modes]
     int nonuniform;       // B-spline: 0 = uniform knots k / n_ctrl, 1 = knots[]
     int inline_data;      // 1: ctrl / knots / a / phi live in inl[] below (no upload needed)
-    double inl[196];      // B-spline: ctrl[64][2], knots[65] from inl + 128; polar: a[64], phi[64]
+    double inl[200];      // B-spline: ctrl[64][2], knots (<= 72) from inl + 128; polar: a[64], phi[64]
 };
 
 // Point grid on [0, 1): n = e * P + q  ->  t = (e + off[q]) / N  (P <= 32),

@@ -62,6 +62,23 @@ constexpr int64_t kMaxKnotNodes = 8192;   // 2M limit: the full singular table i
 // Build them (host threads); throws PlanError.
 WQRulesKnots build_wq_rules_knots(int p, int N, int R, const double *tau);
 
+// Rules on an open arc (Section 3, all N = n_el + p B-splines of the clamped
+// knot vector on the breakpoints x_0 < ... < x_{n_el}; Section 4, nodes with
+// p + 2 equally spaced points in the first and the last refined element,
+// midpoints and breakpoints elsewhere; K2 = ln|s - t|).  Row i's support nodes
+// are n0[i] .. n0[i] + cnt[i] - 1 (the nodes where B_i is non-zero); its
+// weights and B_i values are padded with zeros to QM = max cnt.
+struct WQRulesOpen {
+    int p = 0, n_el = 0, R = 0, N = 0;
+    int64_t M = 0, n_nodes = 0;       // M = R n_el refined elements, 2p + 2M - 1 nodes
+    int QM = 0;
+    std::vector<double> eta;          // [n_nodes]
+    std::vector<int32_t> n0, cnt;     // [N]
+    std::vector<double> W, Bv;        // [N][QM]
+    std::vector<double> Ws;           // [n_nodes][n_nodes], row m: source eta_m
+};
+WQRulesOpen build_wq_rules_open(int p, int n_el, int R, const double *breaks);
+
 struct NearField {
     double u[16], w[16];
     double mco[256], madj[256];

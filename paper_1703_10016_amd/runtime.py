@@ -68,6 +68,37 @@ class Context:
                     beta.data_ptr())
         return beta
 
+    # ---- open arcs (exterior problem, indirect form): N = n_el + p unknowns
+    def rules_open(self, p: int, breaks, n_ref: int = 1):
+        """Open-arc rules on the breakpoints breaks[0] = a < ... < breaks[n_el] = b (cached)."""
+        b = np.ascontiguousarray(breaks, dtype=np.float64)
+        key = ("open", p, n_ref, b.tobytes())
+        if key not in self._rules:
+            self._rules[key] = S.sgbem_weights_open(self.ctx, p, b, n_ref)
+        return self._rules[key]
+
+    def assemble_arc(self, curve, p, breaks, n_ref=1, out=None):
+        N = len(breaks) - 1 + p
+        if out is None:
+            out = self.torch.empty((N, N), dtype=self.torch.float64, device=self.device)
+        assert out.dtype == self.torch.float64 and out.is_cuda and out.stride(1) == 1 and out.shape[0] >= N
+        S.sgbem_assemble(self.ctx, curve, self.rules_open(p, breaks, n_ref), S.SGBEM_WQ, 0, S.SGBEM_FP64,
+                         out.data_ptr(), out.stride(0))
+        return out
+
+    def rhs_points_arc(self, curve, p, breaks, n_ref=1):
+        count = 2 * p + 2 * n_ref * (len(breaks) - 1) - 1
+        xy = self.torch.empty((count, 2), dtype=self.torch.float64, device=self.device)
+        S.sgbem_rhs_points(self.ctx, curve, self.rules_open(p, breaks, n_ref), S.SGBEM_WQ, 0, xy.data_ptr(), count)
+        return xy
+
+    def rhs_arc(self, curve, p, breaks, uD, n_ref=1):
+        """F_i = int B_i J u_D on the arc (indirect form) by the regular rule."""
+        gv = self.sample(uD, self.rhs_points_arc(curve, p, breaks, n_ref))
+        beta = self.torch.empty(len(breaks) - 1 + p, dtype=self.torch.float64, device=self.device)
+        S.sgbem_rhs(self.ctx, curve, self.rules_open(p, breaks, n_ref), S.SGBEM_WQ, 0, gv.data_ptr(), beta.data_ptr())
+        return beta
+
     def rhs_direct(self, curve, p, N, g, n_gauss=4, n_ref=1, with_b2=False):
         """F = b1/2 - b2/(2 pi) of the direct formulation (and b2 when asked)."""
         gn = self.sample(g, self.rhs_points(curve, p, N, "wq", n_ref))

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libsgbem.so")
 
 SGBEM_OK, SGBEM_E_INVAL, SGBEM_E_NOMEM, SGBEM_E_SINGULAR = 0, -1, -2, -3
 SGBEM_E_NOCONV, SGBEM_E_DEVICE, SGBEM_E_UNSUPPORTED = -4, -5, -6
-SGBEM_CURVE_BSPLINE, SGBEM_CURVE_POLAR = 0, 1
+SGBEM_CURVE_BSPLINE, SGBEM_CURVE_POLAR, SGBEM_CURVE_BSPLINE_OPEN = 0, 1, 2
 SGBEM_WQ, SGBEM_EBE = 0, 1
 SGBEM_FP64, SGBEM_FP32 = 0, 1
 SGBEM_NOALLOC_MAX_NODES = 65536
@@ -94,6 +94,9 @@ def lib():
             "sgbem_ctx_kernel_time": [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)],
             "sgbem_weights": [vp, i32, i32, i32, dp, ctypes.POINTER(vp)],
             "sgbem_weights_host_knots": [i32, i32, i32, dp, dp, dp, dp, dp],
+            "sgbem_weights_open": [vp, i32, i32, i32, dp, ctypes.POINTER(vp)],
+            "sgbem_weights_host_open": [i32, i32, i32, dp, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                        ctypes.POINTER(i32), dp, dp, dp, dp],
             "sgbem_rules_free": [vp, vp],
             "sgbem_weights_host": [i32, i32, i32, dp, dp, dp],
             "sgbem_nearfield_host": [dp, dp, dp, dp],
@@ -146,7 +149,8 @@ def exported_symbols():
             "sgbem_server_create", "sgbem_server_submit", "sgbem_server_poll", "sgbem_server_clock",
             "sgbem_server_stats", "sgbem_server_destroy", "sgbem_rhs_direct",
             "sgbem_assemble_collocation", "sgbem_collocation_rhs", "sgbem_assemble_noalloc",
-            "sgbem_ctx_memory", "sgbem_memory_need", "sgbem_weights_host_knots"]
+            "sgbem_ctx_memory", "sgbem_memory_need", "sgbem_weights_host_knots", "sgbem_weights_open",
+            "sgbem_weights_host_open"]
 
 
 # ------------------------------------------------------------------ curve marshalling
@@ -180,8 +184,19 @@ class Curve:
                     raise ValueError("knots must hold n_ctrl + 1 breakpoints")
                 self._keep.append(kn)
                 c.knots = kn.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        elif kind == "bspline_open":
+            c.kind = SGBEM_CURVE_BSPLINE_OPEN
+            c.degree = int(curve.degree)
+            q = np.ascontiguousarray(curve.ctrl, dtype=np.float64)
+            c.n_ctrl = q.shape[0]
+            kn = np.ascontiguousarray(curve.knots, dtype=np.float64)
+            if kn.shape != (q.shape[0] + c.degree + 1,):
+                raise ValueError("an open arc's knots must hold n_ctrl + degree + 1 values")
+            self._keep += [q, kn]
+            c.ctrl_xy = q.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            c.knots = kn.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         else:
-            raise ValueError("curve must have kind 'polar' or 'bspline'")
+            raise ValueError("curve must have kind 'polar', 'bspline' or 'bspline_open'")
         self.c = c
 
     def ref(self):
@@ -207,7 +222,7 @@ def sgbem_ctx_memory(ctx):
 
 
 SGBEM_MEM_RULES, SGBEM_MEM_ASSEMBLE_WQ, SGBEM_MEM_ASSEMBLE_EBE, SGBEM_MEM_RHS_DIRECT, SGBEM_MEM_SOLVE = 0, 1, 2, 3, 4
-SGBEM_MEM_RULES_KNOTS = 5
+SGBEM_MEM_RULES_KNOTS, SGBEM_MEM_RULES_OPEN = 5, 6
 
 
 def sgbem_memory_need(what, p=1, N=1, n_ref=1, n_gauss=0, n_ctrl=0):
@@ -261,6 +276,39 @@ def sgbem_weights_host_knots(p, N, n_ref, knots):
     _check(lib().sgbem_weights_host_knots(int(p), int(N), int(n_ref), kp, P(W), P(Bv), P(Ws), P(eta)))
     del keep
     return W.reshape(N, Q), Bv.reshape(N, Q), Ws.reshape(2 * M, 2 * M), eta
+
+
+def _breaks_ptr(breaks):
+    b = np.ascontiguousarray(breaks, dtype=np.float64)
+    if b.ndim != 1 or b.size < 2:
+        raise ValueError("breaks must hold n_el + 1 breakpoints")
+    return b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), b
+
+
+def sgbem_weights_open(ctx, p, breaks, n_ref=1):
+    """Rules of an open arc on the breakpoints breaks[0] = a < ... < breaks[n_el] = b."""
+    h = ctypes.c_void_p()
+    bp, keep = _breaks_ptr(breaks)
+    _check(lib().sgbem_weights_open(ctx, int(p), keep.size - 1, int(n_ref), bp, ctypes.byref(h)))
+    return h
+
+
+def sgbem_weights_host_open(p, breaks, n_ref=1):
+    """(n0[N], cnt[N], W[N, QM], Bv[N, QM], Ws[nq, nq], eta[nq]) of the open-arc rules."""
+    bp, keep = _breaks_ptr(breaks)
+    n_el = keep.size - 1
+    N, nq = n_el + p, 2 * p + 2 * n_ref * n_el - 1
+    qm = ctypes.c_int32()
+    I = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    D = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    _check(lib().sgbem_weights_host_open(int(p), n_el, int(n_ref), bp, ctypes.byref(qm), None, None, None, None, None,
+                                         None))
+    QM = qm.value
+    n0, cnt = np.zeros(N, dtype=np.int32), np.zeros(N, dtype=np.int32)
+    W, Bv, Ws, eta = np.zeros(N * QM), np.zeros(N * QM), np.zeros(nq * nq), np.zeros(nq)
+    _check(lib().sgbem_weights_host_open(int(p), n_el, int(n_ref), bp, ctypes.byref(qm), I(n0), I(cnt), D(W), D(Bv),
+                                         D(Ws), D(eta)))
+    return n0, cnt, W.reshape(N, QM), Bv.reshape(N, QM), Ws.reshape(nq, nq), eta
 
 
 def sgbem_rules_free(ctx, rules):

@@ -245,3 +245,76 @@ def test_knot_planner_rejects(args, status):
         S.sgbem_weights_host_knots(p, N, R, tau)
     if isinstance(e.value, S.SgbemError):
         assert e.value.status == status
+
+
+# ---------------------------------------------------------------- open arcs
+def _breaks(n, seed, a=-1.0, b=1.0, spread=0.6):
+    rng = np.random.default_rng([1703, 80000 + seed])
+    u = (np.arange(n + 1) + spread * (rng.uniform(0, 1, n + 1) - 0.5)) / n
+    u[0], u[-1] = 0.0, 1.0
+    return a + (b - a) * u
+
+
+@pytest.mark.parametrize("p,n,R,seed", [(2, 10, 1, 0), (3, 7, 2, 1), (1, 5, 1, 2), (6, 9, 1, 3), (4, 3, 2, 4),
+                                        (2, 1, 2, 5), (5, 12, 2, 6), (1, 2, 1, 7)])
+def test_open_planner_matches_oracle(p, n, R, seed):
+    """Open-arc rules from the library's host planner (Householder QR per row, clamped Cox-de Boor pieces,
+    banded Cholesky of the Gram matrix) against the oracle's dense least-squares route (O7)."""
+    from oracle import wq_open as O
+    S = _lib()
+    br = _breaks(n, seed)
+    n0, cnt, W, Bv, Ws, eta = S.sgbem_weights_host_open(p, br, R)
+    assert np.array_equal(eta, O.nodes(br, p, R))
+    assert W.shape[1] == 2 * R * (p + 1) - 1 + 2 * p
+    T = O.knot_vector(br, p)
+    Tb = O.knot_vector(O.refine(br, R), p)
+    for i, (nset, w) in O.regular_weights(br, p, R).items():
+        assert n0[i] == nset[0] and cnt[i] == nset.size and np.array_equal(nset, n0[i] + np.arange(cnt[i]))
+        Bloc = np.stack([O.basis(Tb, p, int(k), eta[nset]) for k in O.exactness_set(br, p, R, i)])
+        tol = 20 * np.finfo(float).eps * np.linalg.cond(Bloc) * np.abs(w).max()
+        assert np.abs(W[i, :cnt[i]] - w).max() < tol, (i, np.abs(W[i, :cnt[i]] - w).max(), tol)
+        assert np.all(W[i, cnt[i]:] == 0) and np.all(Bv[i, cnt[i]:] == 0)
+        assert np.abs(Bv[i, :cnt[i]] - O.basis(T, p, i, eta[nset])).max() < 2e-15
+    Wso = O.singular_weights(br, p, R)
+    assert np.abs(Ws - Wso).max() < 2e-13 * np.abs(Wso).max(), np.abs(Ws - Wso).max() / np.abs(Wso).max()
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("R", [1, 2])
+def test_open_tile_windows_fit_the_kernel(p, R):
+    """The assembly kernel's node window per 24-row tile is P (T - 1) + (p - 1) + QM: the row starts n0 grow
+    by 2R per row except once by 2R + p - 1 (after the rows whose support holds the first element)."""
+    S = _lib()
+    P, T = 2 * R, 24
+    QM = P * (p + 1) - 1 + 2 * p
+    for n in [1, 2, 3, p + 1, 23, 24, 25, 47, 60, 101]:
+        if R * n < 2:
+            continue
+        n0, cnt = S.sgbem_weights_host_open(p, np.linspace(0.0, 1.0, n + 1), R)[:2]
+        assert cnt.max() <= QM and np.all(np.diff(n0) >= 0)
+        N = n + p
+        for I0 in range(0, N, T):
+            assert n0[min(I0 + T - 1, N - 1)] - n0[I0] + QM <= P * (T - 1) + (p - 1) + QM
+
+
+def test_open_memory_need():
+    S = _lib()
+    for p, n, R in [(2, 640, 1), (3, 100, 2), (6, 5, 4)]:
+        N, QM, nq = n + p, 2 * R * (p + 1) - 1 + 2 * p, 2 * p + 2 * R * n - 1
+        want = 2 * _al256(8 * N * QM) + _al256(8 * nq * nq) + _al256(8 * nq) + 2 * _al256(4 * N)
+        assert S.sgbem_memory_need(S.SGBEM_MEM_RULES_OPEN, p, n, R) == _buf(want)
+
+
+@pytest.mark.parametrize("args,status", [((2, np.array([0.0, 0.5, 0.5, 1.0]), 1), -1),
+                                         ((2, np.array([1.0, 0.0]), 1), -1),
+                                         ((2, np.array([0.0, 1.0]), 1), -1),
+                                         ((7, np.linspace(0, 1, 5), 1), -1),
+                                         ((2, np.linspace(0, 1, 5), 5), -1),
+                                         ((2, np.array([0.0, np.nan, 1.0]), 1), -1),
+                                         ((2, np.linspace(0, 1, 4096), 1), -6)])
+def test_open_planner_rejects(args, status):
+    S = _lib()
+    p, br, R = args
+    with pytest.raises(S.SgbemError) as e:
+        S.sgbem_weights_host_open(p, br, R)
+    assert e.value.status == status
