@@ -28,7 +28,12 @@ Also measured in the same run (reported beside the headline value):
    and the oracle's G = 24 solution as a second reference of the equal-error
    comparison;
  * a serving sweep (Poisson arrivals at 10 .. 1000 req/s, about 10 s of
-   arrivals per rate, 100 to 2000 requests).
+   arrivals per rate, 100 to 2000 requests);
+ * the general-rule paths: the parabola test on an open arc (Table 2's largest
+   case, DoF 642, and the largest singular table, 8191 nodes) and a closed
+   curve on graded non-uniform periodic knots (N = 1024 and 4096): rule
+   construction on the host, the assembly kernel, right-hand side and solve,
+   and for the arc E_R / E_M against the exact density.
 """
 from __future__ import annotations
 
@@ -177,6 +182,94 @@ def _serve_drain(S, srv, n, timeout=900.0):
     return got
 
 
+def _timed_kernel(S, ctx, fn, reps):
+    """Average duration of the assembly kernel of fn() (HIP events of its own dispatch)."""
+    fn()
+    S.sgbem_ctx_set_timing(ctx.ctx, 1)
+    for _ in range(reps):
+        fn()
+    tms, cnt = S.sgbem_ctx_kernel_time(ctx.ctx)
+    S.sgbem_ctx_set_timing(ctx.ctx, 0)
+    return tms / cnt
+
+
+def general_rules(ctx, S, synth, torch, stream):
+    """Open arcs (the parabola test of Section 6) and non-uniform periodic knots: per-row rules and the
+    full singular table.  Flops per entry as for the uniform fast form (wq_flops_per_entry); the arc
+    computes every entry (N^2), the closed curve the upper triangle (N(N+1)/2)."""
+    from scipy.interpolate import BSpline
+
+    def arc_errors(br, d, alpha):
+        """E_R (relative L2 error, 8-point Gauss per element) and E_M (maximum on 500 uniform points) of
+        phi_h = sum_j alpha_j B_j against the exact density sqrt(1 + 4 t^2) of the parabola test."""
+        T = np.concatenate([np.full(d, br[0]), br, np.full(d, br[-1])])
+        phi_h = BSpline(T, alpha, d)
+        gu, gw = np.polynomial.legendre.leggauss(8)
+        h = np.diff(br)
+        tq = (br[:-1, None] + h[:, None] * (gu[None, :] + 1) / 2).ravel()
+        wq = (h[:, None] * gw[None, :] / 2).ravel()
+        e = phi_h(tq) - synth.parabola_phi(tq)
+        tu = np.linspace(br[0], br[-1], 500)
+        return (math.sqrt(np.sum(wq * e * e) / np.sum(wq * synth.parabola_phi(tq) ** 2)),
+                float(np.abs(phi_h(tu) - synth.parabola_phi(tu)).max()))
+
+    out = {"open_arc": [], "knots": []}
+    for d, n in ((2, 640), (2, 4094)):
+        br = np.linspace(-1.0, 1.0, n + 1)
+        cur = synth.parabola()
+        Nd = n + d
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.rules_open(d, br)
+        t_rules = time.perf_counter() - t0
+        A = torch.empty((Nd, Nd), dtype=torch.float64, device="cuda")
+        kms = _timed_kernel(S, ctx, lambda: ctx.assemble_arc(cur, d, br, out=A), 10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.assemble_arc(cur, d, br, out=A)
+        beta = ctx.rhs_arc(cur, d, br, synth.parabola_uD)
+        x, info = ctx.solve(A, beta, tol=1e-12, max_iter=30)
+        torch.cuda.synchronize()
+        t_req = time.perf_counter() - t0
+        ER, EM = arc_errors(br, d, x.cpu().numpy())
+        fl = float(Nd) * Nd * wq_flops_per_entry(d, 1)
+        row = {"workload": f"parabola x2 = 1 - x1^2, d={d}, n_el={n} (DoF {Nd}, {2 * d + 2 * n - 1} nodes), n_ref=1",
+               "rules_build_ms": t_rules * 1e3, "assembly_kernel_us": kms * 1e3,
+               "entries_per_s": Nd * Nd / (kms * 1e-3), "tflops": fl / (kms * 1e-3) / 1e12,
+               "frac_of_fp64_peak": fl / (kms * 1e-3) / PEAK_FP64,
+               "request_ms": t_req * 1e3, "request": "assemble + rhs (host-sampled u_D) + solve",
+               "solve_pivoted": int(info.pivoted), "E_R": ER, "E_M": EM}
+        out["open_arc"].append(row)
+        log(f"[bench] open arc {row['workload']}: rules {t_rules*1e3:.1f} ms, kernel {kms*1e3:.1f} us "
+            f"({row['entries_per_s']:.3e} entries/s, {row['tflops']:.2f} TFLOP/s), request {t_req*1e3:.2f} ms, "
+            f"E_R {ER:.3e}, E_M {EM:.3e}")
+        del A
+        S.sgbem_rules_free(ctx.ctx, ctx._rules.pop(("open", d, 1, np.ascontiguousarray(br).tobytes())))
+    for Nk in (1024, 4096):
+        u = np.arange(Nk + 1) / Nk
+        tau = u + 0.3 * np.sin(2 * math.pi * u) / (2 * math.pi)
+        tau[0], tau[-1] = 0.0, 1.0
+        crv, pk = synth.ellipse_bspline_nonuniform(0), 3
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.rules(pk, Nk, 1, tau)
+        t_rules = time.perf_counter() - t0
+        A = torch.empty((Nk, Nk), dtype=torch.float64, device="cuda")
+        kms = _timed_kernel(S, ctx, lambda: ctx.assemble(crv, pk, Nk, "wq", out=A, knots=tau), 10)
+        fl = Nk * (Nk + 1) / 2 * wq_flops_per_entry(pk, 1)
+        row = {"workload": f"ellipse on graded periodic knots (32-point cubic net), p={pk}, N={Nk}, n_ref=1",
+               "rules_build_ms": t_rules * 1e3, "assembly_kernel_us": kms * 1e3,
+               "entries_per_s": Nk * Nk / (kms * 1e-3), "tflops": fl / (kms * 1e-3) / 1e12,
+               "frac_of_fp64_peak": fl / (kms * 1e-3) / PEAK_FP64}
+        out["knots"].append(row)
+        log(f"[bench] knots {row['workload']}: rules {t_rules*1e3:.1f} ms, kernel {kms*1e3:.1f} us "
+            f"({row['entries_per_s']:.3e} entries/s, {row['tflops']:.2f} TFLOP/s)")
+        del A
+        S.sgbem_rules_free(ctx.ctx, ctx._rules.pop((pk, Nk, 1, np.asarray(tau, dtype=np.float64).tobytes())))
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -193,6 +286,7 @@ def main():
     ap.add_argument("--serve-rates", type=str, default="10,30,100,300,1000", help="arrival rates, req/s")
     ap.add_argument("--serve-workers", type=int, default=8)
     ap.add_argument("--solves", type=int, default=60)
+    ap.add_argument("--no-general", action="store_true", help="skip the open-arc and non-uniform-knot paths")
     ap.add_argument("--profile-run", action="store_true",
                     help="only K direct WQ assemblies of the workload and one 256 MiB device copy "
                          "(the copy calibrates the byte counters of a profiler run)")
@@ -542,6 +636,11 @@ def main():
             f"{ms_batch:.3f} ms ({entries/(ms_batch*1e-3):.3e} entries/s), tuned T={cfgs[cfg][0]} S={cfgs[cfg][1]}; "
             f"256 sequential launches {ms_seq:.3f} ms, with a sync each {ms_seq_sync:.3f} ms")
 
+    # ---------------------------------------------------------------- general rules: open arc, non-uniform knots
+    general = None
+    if not args.no_general:
+        general = general_rules(ctx, S, synth, torch, stream)
+
     # ---------------------------------------------------------------- serving loop (Poisson arrivals)
     serving = None
     if not args.no_serving:
@@ -632,6 +731,7 @@ def main():
         "collocation": colloc,
         "batch_256_stars": batch,
         "serving": serving,
+        "general_rules": general,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
