@@ -74,7 +74,7 @@ def ebe_flops_per_entry(p: int, G: int) -> float:
 def kernel_source_hash() -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in ("tile_kernel.hpp", "kernels.hpp", "asm_wq_f64.hip"):
+    for f in ("tile_kernel.hpp", "kernels.hpp", "log_table.hpp", "asm_wq_f64.hip"):
         with open(os.path.join(ROOT, "paper_1703_10016_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -290,6 +290,8 @@ def main():
     ap.add_argument("--profile-run", action="store_true",
                     help="only K direct WQ assemblies of the workload and one 256 MiB device copy "
                          "(the copy calibrates the byte counters of a profiler run)")
+    ap.add_argument("--profile-n", type=int, default=0,
+                    help="with --profile-run: assemble the star curve (p = 3) at this N instead of the workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: there is no multi-GPU path (the matrix would be "
@@ -315,6 +317,8 @@ def main():
     ctx.rules(p, N, R)
     t_rules = time.perf_counter() - t0
     if args.profile_run:
+        if args.profile_n:
+            curve, N = synth.star(0), args.profile_n
         A = torch.empty((N, N), dtype=torch.float64, device="cuda")
         for _ in range(W + K):
             ctx.assemble(curve, p, N, "wq", n_ref=R, out=A)

@@ -82,8 +82,11 @@ __global__ __launch_bounds__(256) void arc_tile_kernel(ArcArgs a)
         for (int c2 = c_lo; c2 < c_hi; ++c2) {
             const int g2 = sg2[c2];
             const double dx = x1 - sx2[c2], dy = y1 - sy2[c2];
-            const double dt = t1 - st2[c2];
-            const double ratio = (g2 == g1) ? J1 * J1 : (dx * dx + dy * dy) / (dt * dt);
+            // diagonal: the same node, |f1 - f2|^2 = 0 exactly; the parameter difference is
+            // replaced by 1 there so that the quotient stays finite (no branch per value)
+            const bool diag = g2 == g1;
+            const double dt = diag ? 1.0 : t1 - st2[c2];
+            const double ratio = (dx * dx + dy * dy) / (dt * dt) + (diag ? J1 * J1 : 0.0);
             const double U = 0.5 * log_atanh64(ratio);
             const double V = wsrow[g2];
             const double J2 = sJ2[c2];

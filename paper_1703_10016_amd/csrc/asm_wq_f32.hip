@@ -7,19 +7,19 @@ namespace sgbem {
 hipError_t launch_wq_f32(int p, int P, const TileArgs &a, hipStream_t s, const KernelEvents *ev)
 {
     switch (p * 16 + P) {
-    case 18: return launch_tile<2, 3, 1, true, float, 28, 7>(a, s, ev);
+    case 18: return launch_tile<2, 3, 1, true, float, 28, 7, 6>(a, s, ev);
     case 20: return launch_tile<4, 7, 1, true, float, 28, 7>(a, s, ev);
     case 22: return launch_tile<6, 11, 1, true, float, 20, 5>(a, s, ev);
     case 24: return launch_tile<8, 15, 1, true, float, 28, 7>(a, s, ev);
-    case 34: return launch_tile<2, 5, 1, true, float, 28, 7>(a, s, ev);
+    case 34: return launch_tile<2, 5, 1, true, float, 28, 7, 6>(a, s, ev);
     case 36: return launch_tile<4, 11, 1, true, float, 28, 7>(a, s, ev);
     case 38: return launch_tile<6, 17, 1, true, float, 28, 7>(a, s, ev);
     case 40: return launch_tile<8, 23, 1, true, float, 28, 7>(a, s, ev);
-    case 50: return launch_tile<2, 7, 1, true, float, 28, 7>(a, s, ev);
+    case 50: return launch_tile<2, 7, 1, true, float, 28, 7, 6>(a, s, ev);
     case 52: return launch_tile<4, 15, 1, true, float, 28, 7>(a, s, ev);
     case 54: return launch_tile<6, 23, 1, true, float, 24, 8>(a, s, ev);
     case 56: return launch_tile<8, 31, 1, true, float, 28, 7>(a, s, ev);
-    case 66: return launch_tile<2, 9, 1, true, float, 28, 7>(a, s, ev);
+    case 66: return launch_tile<2, 9, 1, true, float, 28, 7, 6>(a, s, ev);
     case 68: return launch_tile<4, 19, 1, true, float, 28, 7>(a, s, ev);
     case 70: return launch_tile<6, 29, 1, true, float, 24, 8>(a, s, ev);
     case 72: return launch_tile<8, 39, 1, true, float, 28, 7>(a, s, ev);

@@ -77,6 +77,10 @@ def main():
                 k = f"launch_tile<{P}, {Q}, {S0}, {wq}, {real}, {T}, {S}"
                 if big and real == "double":
                     s += f"    case {p * 16 + P}: return a.N >= 4096 ? {k}, 4>(a, s, ev) : {k}>(a, s, ev);\n"
+                elif big:
+                    # FP32: bound the registers to >= 6 waves per SIMD (left alone, the compiler
+                    # hoists the sweep's loads into 152 VGPRs; 56 VGPRs run 1.3x faster)
+                    s += f"    case {p * 16 + P}: return {k}, 6>(a, s, ev);\n"
                 else:
                     s += f"    case {p * 16 + P}: return {k}>(a, s, ev);\n"
             s += "    default: return hipErrorInvalidValue;\n    }\n}\n\n}  // namespace sgbem\n"

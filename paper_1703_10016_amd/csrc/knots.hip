@@ -78,8 +78,11 @@ __global__ __launch_bounds__(256) void knot_tile_kernel(KnotArgs a)
             const double r2 = dx * dx + dy * dy;
             double d = t1 - st2[c2];
             d -= rint(d);
-            const double sp = sinpi(d);
-            const double ratio = (g2 == g1) ? J1 * J1 : r2 * ((kPiK / sp) * (kPiK / sp));
+            // diagonal: the same node, r2 = 0 exactly; sin replaced by 1 there so that the
+            // product stays finite (no branch per kernel value around the node loads)
+            const bool diag = g2 == g1;
+            const double sp = diag ? 1.0 : sinpi(d);
+            const double ratio = fma(r2, (kPiK / sp) * (kPiK / sp), diag ? J1 * J1 : 0.0);
             const double U = 0.5 * log_atanh64(ratio);
             const double V = wsrow[g2];
             const double J2 = sJ2[c2];

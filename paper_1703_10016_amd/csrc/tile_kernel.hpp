@@ -24,46 +24,47 @@
 #pragma once
 
 #include <hip/hip_ext.h>
+#include <type_traits>
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
+#include "log_table.hpp"
 
 namespace sgbem {
 
 // FP64 natural logarithm for positive normal arguments, table driven (Tang's scheme):
-// x = 2^e m with m in [1, 2); j = the top 6 fraction bits of m;
-// c_j = 1 / (1 + (j + 1/2)/64), r = m c_j - 1 (|r| < 1/128, one rounding by the fma);
-// log x = e ln2 + log(1/c_j) + log1p(r), log1p by its Taylor series to r^8
-// (truncation |r|^9/9 < 1e-20).  tab[2j] = c_j, tab[2j+1] = log(1/c_j); ln 2 is
-// split into a 32-bit head (e ln2_hi exact) and a tail.  Absolute error a few
-// units in the last place of the result's scale.
-__device__ __forceinline__ void build_log_tab(double *tab)
+// x = 2^e m with m in [1/2, 1) (frexp); j = the top 8 fraction bits of x;
+// c_j = 2 / (1 + (j + 1/2)/256), r = m c_j - 1 (|r| < 2^-9, one rounding by the
+// fma); log x = e ln2 + log(1/c_j) + log1p(r), log1p(r) = r + r^2 q(r) with q
+// the Taylor series to r^5/5 (truncation |r|^6/6 < 1e-17).  tab[j] =
+// (c_j, log(1/c_j)) from log_table.hpp, copied to LDS per workgroup; ln 2 is
+// split into a 32-bit head (e ln2_hi exact) and a tail.  Absolute error
+// <= 1.2e-16 over [4e-18, 2e17] (arithmetic checked against 50-digit values).
+__device__ __forceinline__ void load_log_tab(double2 *tab)
 {
-    for (int j = threadIdx.x; j < 64; j += blockDim.x) {
-        const double c = 1.0 / (1.0 + (j + 0.5) / 64.0);
-        tab[2 * j] = c;
-        tab[2 * j + 1] = -log(c);
-    }
+    for (int j = threadIdx.x; j < 256; j += blockDim.x) tab[j] = make_double2(kLogTab256[2 * j], kLogTab256[2 * j + 1]);
 }
-__device__ __forceinline__ double log_tab64(double x, const double *tab)
+// The LDS copy of the table: one per kernel, whichever tile variants it inlines.
+__device__ __forceinline__ double2 *log_tab_lds()
+{
+    __shared__ double2 tab[256];
+    return tab;
+}
+__device__ __forceinline__ double log_tab64(double x, const double2 *tab)
 {
     constexpr double ln2_hi = 0.69314718036912381649017333984375;
     constexpr double ln2_lo = 1.9082149292705877000220e-10;
-    int e = __builtin_amdgcn_frexp_exp(x) - 1;              // x = m 2^e, m in [1, 2)
-    const double m = 2.0 * __builtin_amdgcn_frexp_mant(x);
-    const int j = (__double2hiint(m) >> 14) & 63;
-    const double c = tab[2 * j], lc = tab[2 * j + 1];
-    const double r = fma(m, c, -1.0);
-    double p = -0.125;
-    p = fma(p, r, 1.0 / 7.0);
-    p = fma(p, r, -1.0 / 6.0);
-    p = fma(p, r, 0.2);
-    p = fma(p, r, -0.25);
-    p = fma(p, r, 1.0 / 3.0);
-    p = fma(p, r, -0.5);
-    p = fma(p, r, 1.0);
+    const int e = __builtin_amdgcn_frexp_exp(x);
+    const double m = __builtin_amdgcn_frexp_mant(x);
+    const uint32_t hi = uint32_t(__double_as_longlong(x) >> 32);
+    const double2 cl = tab[(hi >> 12) & 255];
+    const double r = fma(m, cl.x, -1.0);
+    double q = 0.2;
+    q = fma(q, r, -0.25);
+    q = fma(q, r, 1.0 / 3.0);
+    q = fma(q, r, -0.5);
     const double ed = double(e);
-    return fma(ed, ln2_hi, lc + fma(ed, ln2_lo, p * r));
+    return fma(ed, ln2_hi, cl.y + fma(ed, ln2_lo, fma(q, r * r, r)));
 }
 
 // FP64 natural logarithm without tables: x = 2^e m, m in [sqrt(1/2), sqrt(2)),
@@ -103,21 +104,21 @@ __device__ __forceinline__ double log_atanh64(double x)
     return fma(ed, ln2_hi, fma(ed, ln2_lo, lm));
 }
 
-// Logarithm of the kernel sweep (choices measured on MI355X): FP64 weighted
-// quadrature uses the table-free series above (1.4x faster than the device
-// library's log there; the sweep's LDS already carries the node windows and
-// rule tables), the FP64 element-by-element sweep the table-driven log (2x
-// faster than the library's there).  FP32: v_log_f32.
+// Logarithm of the kernel sweep (choices measured on MI355X): FP64 uses the
+// table-driven log above (a 64-entry version cost 23 FP64-operation
+// equivalents per log against 41 for the table-free series and 91 for the
+// device library's log, measured as throughput on independent chains; the
+// 256-entry table shortens the polynomial by three more FMAs); FP32: v_log_f32.
 template <typename Real, bool TableLog>
-__device__ __forceinline__ Real k_log(Real x, const double *tab);
+__device__ __forceinline__ Real k_log(Real x, const double2 *tab);
 template <>
-__device__ __forceinline__ double k_log<double, true>(double x, const double *tab) { return log_tab64(x, tab); }
+__device__ __forceinline__ double k_log<double, true>(double x, const double2 *tab) { return log_tab64(x, tab); }
 template <>
-__device__ __forceinline__ double k_log<double, false>(double x, const double *) { return log_atanh64(x); }
+__device__ __forceinline__ double k_log<double, false>(double x, const double2 *) { return log_atanh64(x); }
 template <>
-__device__ __forceinline__ float k_log<float, true>(float x, const double *) { return __logf(x); }
+__device__ __forceinline__ float k_log<float, true>(float x, const double2 *) { return __logf(x); }
 template <>
-__device__ __forceinline__ float k_log<float, false>(float x, const double *) { return __logf(x); }
+__device__ __forceinline__ float k_log<float, false>(float x, const double2 *) { return __logf(x); }
 
 struct TileArgsF {          // FP32 copies of the per-support coefficients
     float coefA[64];
@@ -139,9 +140,10 @@ __device__ __forceinline__ Real coef_b(const Args &a, const ArgsF &f, int q)
 
 __device__ __forceinline__ void tile_coords(int nb, int b, int &bi, int &bj)
 {
-    // linear index b over the upper-triangle tiles, row by row
-    const double tn = 2.0 * nb + 1.0;
-    int r = int((tn - sqrt(tn * tn - 8.0 * b)) * 0.5);
+    // linear index b over the upper-triangle tiles, row by row; the FP32 estimate
+    // of the row is corrected by the two integer loops below
+    const float tn = 2.0f * float(nb) + 1.0f;
+    int r = int((tn - __builtin_sqrtf(fmaxf(tn * tn - 8.0f * float(b), 0.0f))) * 0.5f);
     if (r < 0) r = 0;
     while (r > 0 && r * nb - (r * (r - 1)) / 2 > b) --r;
     while ((r + 1) * nb - ((r + 1) * r) / 2 <= b) ++r;
@@ -162,12 +164,19 @@ __device__ __forceinline__ void tile_body(const Args &a, const ArgsF &af, int bi
     __shared__ double sx1[L], sy1[L], sx2[L], sy2[L];
     __shared__ Real sJ1[L], sJ2[L];
     __shared__ int se1[WQ ? 1 : L], se2[WQ ? 1 : L];
-    __shared__ Real sinv[WQ ? LT : 1], sw[WQ ? 2 * LT : 1];   // sw[par * LT + dl]
-    __shared__ Real C1[L][T + 1];
-    __shared__ Real tileo[T][T + 1];
-    constexpr bool kTableLog = !WQ && sizeof(Real) == 8;
-    __shared__ double ltab[kTableLog ? 128 : 1];
-    if constexpr (kTableLog) build_log_tab(ltab);
+    // sinvz[dl] = ((pi / sin(pi d / npts))^2, 1 if d = 0 else 0) of the slice; sw[par * LT + dl]
+    using Real2 = typename std::conditional<sizeof(Real) == 8, double2, float2>::type;
+    __shared__ Real2 sinvz[WQ ? LT : 1];
+    __shared__ Real sw[WQ ? 2 * LT : 1];
+    constexpr int TW = (T % 2 == 0) ? T + 2 : T + 1;      // row pitch: even for paired columns
+    __shared__ __align__(16) Real C1[L][TW];
+    __shared__ __align__(16) Real tileo[T][TW];
+    constexpr bool kTableLog = sizeof(Real) == 8;
+    double2 *ltab = nullptr;
+    if constexpr (kTableLog) {
+        ltab = log_tab_lds();
+        load_log_tab(ltab);
+    }
 
     const int N = a.N, npts = a.npts;
     const int I0 = bi * T, J0 = bj * T;
@@ -175,8 +184,15 @@ __device__ __forceinline__ void tile_body(const Args &a, const ArgsF &af, int bi
     const int start2 = (P * J0 + S0) % npts;
 
     for (int r = threadIdx.x; r < L; r += blockDim.x) {
-        const int g1 = (start1 + r) % npts;
-        const int g2 = (start2 + r) % npts;
+        // start + r < 2 npts whenever the window is not longer than the grid
+        int g1 = start1 + r, g2 = start2 + r;
+        if (L <= npts) {
+            g1 = g1 >= npts ? g1 - npts : g1;
+            g2 = g2 >= npts ? g2 - npts : g2;
+        } else {
+            g1 %= npts;
+            g2 %= npts;
+        }
         sx1[r] = a.X[g1];
         sy1[r] = a.Y[g1];
         sJ1[r] = Real(a.J[g1]);
@@ -193,13 +209,16 @@ __device__ __forceinline__ void tile_body(const Args &a, const ArgsF &af, int bi
         int dbase = (start2 - start1 - (L - 1)) % npts;
         if (dbase < 0) dbase += npts;
         for (int dl = threadIdx.x; dl < LT; dl += blockDim.x) {
-            const int d = (dbase + dl) % npts;
+            int d = dbase + dl;
+            if (LT <= npts) d = d >= npts ? d - npts : d;
+            else d %= npts;
+            const Real z = d == 0 ? Real(1) : Real(0);
             if constexpr (sizeof(Real) == 8) {
-                sinv[dl] = Real(a.inv_s2[d]);
+                sinvz[dl] = Real2{Real(a.inv_s2[d]), z};
                 sw[dl] = Real(a.ws[d]);
                 sw[LT + dl] = Real(a.ws[npts + d]);
             } else {
-                sinv[dl] = Real(a.inv_s2f[d]);
+                sinvz[dl] = Real2{Real(a.inv_s2f[d]), z};
                 sw[dl] = Real(a.wsf[d]);
                 sw[LT + dl] = Real(a.wsf[npts + d]);
             }
@@ -207,13 +226,19 @@ __device__ __forceinline__ void tile_body(const Args &a, const ArgsF &af, int bi
     }
     __syncthreads();
 
+    // halved regular weights of stage 1 (exact: a power of two)
+    Real ah[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) ah[q] = Real(0.5) * coef_a<Real>(a, af, q);
+
     // ---------------- stage 1: kernel sweep and contraction over the n2 supports
     for (int item = threadIdx.x; item < L * NSTRIP; item += blockDim.x) {
         const int r = item % L;
         const int st = item / L;
         const double x1 = sx1[r], y1 = sy1[r];
         const Real J1 = sJ1[r];
-        const int par = (start1 + r) % npts & 1;
+        const Real J1sq = J1 * J1;
+        const int par = (start1 + r) & 1;     // npts is even: the parity of the node index
         const Real *swp = WQ ? sw + par * LT : sw;     // singular weights of this row's node class
         const int e1 = WQ ? 0 : se1[r];
         Real acc[S];
@@ -230,18 +255,23 @@ __device__ __forceinline__ void tile_body(const Args &a, const ArgsF &af, int bi
                 const float fx = float(dx), fy = float(dy);
                 r2 = fx * fx + fy * fy;
             }
+            // U = 2 K1 (the 1/2 of K1 = 1/2 ln(...) sits in the halved weights ah[q])
             Real U, V = Real(0);
             if constexpr (WQ) {
+                // the diagonal (d = 0, z = 1, inv = 0) is the same node: r2 = 0 exactly, and
+                // the ratio is J1^2; elsewhere z = 0 and the ratio is r2 * inv.  No
+                // conditional on r2, so that the node loads are not sunk into a branch per
+                // kernel value.
                 const int dl = c2 - r + (L - 1);
-                const Real inv = sinv[dl];
-                const Real ratio = (inv == Real(0)) ? J1 * J1 : r2 * inv;
-                U = Real(0.5) * k_log<Real, kTableLog>(ratio, ltab);
+                const Real2 iz = sinvz[dl];
+                const Real ratio = fma(J1sq, iz.y, r2 * iz.x);
+                U = k_log<Real, kTableLog>(ratio, ltab);
                 V = swp[dl];
             } else {
                 int de = se2[c2] - e1;
                 if (de < 0) de += N;
                 const bool near = (de == 0) | (de == 1) | (de == N - 1);
-                U = near ? Real(0) : Real(0.5) * k_log<Real, kTableLog>(r2, ltab);
+                U = near ? Real(0) : k_log<Real, kTableLog>(r2, ltab);
             }
             const Real J2 = sJ2[c2];
             const Real JU = J2 * U, JV = J2 * V;
@@ -249,7 +279,7 @@ __device__ __forceinline__ void tile_body(const Args &a, const ArgsF &af, int bi
             for (int s = 0; s < S; ++s) {
                 const int q = k2 - s * P;
                 if (q >= 0 && q < Q) {
-                    acc[s] = fma(coef_a<Real>(a, af, q), JU, acc[s]);
+                    acc[s] = fma(ah[q], JU, acc[s]);
                     if constexpr (WQ) acc[s] = fma(coef_b<Real>(a, af, q), JV, acc[s]);
                 }
             }
@@ -261,17 +291,52 @@ __device__ __forceinline__ void tile_body(const Args &a, const ArgsF &af, int bi
 
     // ---------------- stage 2: contraction over the n1 supports
     const Real scale = Real(a.scale);
-    for (int e = threadIdx.x; e < T * T; e += blockDim.x) {
-        const int il = e / T, jl = e % T;
-        Real v = Real(0);
+    if constexpr (T % 2 == 0) {
+        // two adjacent columns per work item (one paired LDS read per support point)
+        constexpr int TP = T / 2;
+        for (int e = threadIdx.x; e < T * TP; e += blockDim.x) {
+            const int il = e / TP, jl = 2 * (e - (e / TP) * TP);
+            Real v0 = Real(0), v1 = Real(0);
 #pragma unroll
-        for (int q = 0; q < Q; ++q) v += coef_a<Real>(a, af, q) * C1[P * il + q][jl];
-        tileo[il][jl] = v * scale;
+            for (int q = 0; q < Q; ++q) {
+                const Real2 c = *reinterpret_cast<const Real2 *>(&C1[P * il + q][jl]);
+                const Real w = coef_a<Real>(a, af, q);
+                v0 += w * c.x;
+                v1 += w * c.y;
+            }
+            *reinterpret_cast<Real2 *>(&tileo[il][jl]) = Real2{v0 * scale, v1 * scale};
+        }
+    } else {
+        for (int e = threadIdx.x; e < T * T; e += blockDim.x) {
+            const int il = e / T, jl = e % T;
+            Real v = Real(0);
+#pragma unroll
+            for (int q = 0; q < Q; ++q) v += coef_a<Real>(a, af, q) * C1[P * il + q][jl];
+            tileo[il][jl] = v * scale;
+        }
     }
     __syncthreads();
 
     OutT *out = reinterpret_cast<OutT *>(a.out);
     const int64_t lda = a.lda;
+    // an off-diagonal tile inside the matrix, with every pair of columns (j even from J0)
+    // aligned for one paired store: no per-entry checks
+    using OutT2 = typename std::conditional<sizeof(OutT) == 8, double2, float2>::type;
+    const bool paired = (T % 2 == 0) && bi != bj && I0 + T <= N && J0 + T <= N &&
+                        ((reinterpret_cast<uintptr_t>(out) | uintptr_t(lda) * sizeof(OutT)) % (2 * sizeof(OutT))) == 0;
+    if (paired) {
+        constexpr int TP = T / 2;
+        for (int e = threadIdx.x; e < T * TP; e += blockDim.x) {
+            const int rl = e / TP, cl = 2 * (e - (e / TP) * TP);
+            const Real2 v = *reinterpret_cast<const Real2 *>(&tileo[rl][cl]);
+            *reinterpret_cast<OutT2 *>(out + int64_t(I0 + rl) * lda + J0 + cl) = OutT2{OutT(v.x), OutT(v.y)};
+            // mirror: row J0 + rl, columns I0 + cl, I0 + cl + 1
+            *reinterpret_cast<OutT2 *>(out + int64_t(J0 + rl) * lda + I0 + cl) =
+                OutT2{OutT(tileo[cl][rl]), OutT(tileo[cl + 1][rl])};
+        }
+        __syncthreads();   // LDS is reused by the next tile of a persistent block
+        return;
+    }
     for (int e = threadIdx.x; e < T * T; e += blockDim.x) {
         const int il = e / T, jl = e % T;
         const int i = I0 + il, j = J0 + jl;
@@ -293,18 +358,26 @@ __device__ __forceinline__ void tile_body(const Args &a, const ArgsF &af, int bi
 // WPE: minimum waves per SIMD the register allocation must allow (1: no
 // constraint).  Large matrices gain from 4 (more waves to hide the latency of
 // the logarithm's dependent chain), small ones lose to the extra spills.
-template <int P, int Q, int S0, bool WQ, typename Real, typename OutT, int T, int S, int WPE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void tile_kernel(TileArgs a, TileArgsF af)
+// NT: threads per workgroup (a multiple of 64; the sweep's L T/S items are
+// spread over them).
+template <int P, int Q, int S0, bool WQ, typename Real, typename OutT, int T, int S, int WPE, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void tile_kernel(TileArgs a, TileArgsF af)
 {
     const int nb = (a.N + T - 1) / T;
+    // workgroups go round-robin to the 8 XCDs; give each XCD a contiguous run of tiles
+    // (row by row), so that neighbouring tiles writing the same output lines share an L2
+    const int ntiles = nb * (nb + 1) / 2;
+    const int q = ntiles >> 3, rem = ntiles & 7;
+    const int x = int(blockIdx.x & 7), k = int(blockIdx.x >> 3);
     int bi, bj;
-    tile_coords(nb, blockIdx.x, bi, bj);
+    tile_coords(nb, x * q + min(x, rem) + k, bi, bj);
     tile_body<P, Q, S0, WQ, Real, OutT, T, S>(a, af, bi, bj);
 }
 
-template <int P, int Q, int S0, bool WQ, typename Real, int T, int S, int WPE = 1>
+template <int P, int Q, int S0, bool WQ, typename Real, int T, int S, int WPE = 1, int NT = 256>
 hipError_t launch_tile(const TileArgs &a, hipStream_t s, const KernelEvents *ev = nullptr)
 {
+    static_assert(NT % 64 == 0 && NT <= 1024, "workgroup size");
     TileArgsF af;
     for (int q = 0; q < 64; ++q) {
         af.coefA[q] = float(a.coefA[q]);
@@ -314,10 +387,10 @@ hipError_t launch_tile(const TileArgs &a, hipStream_t s, const KernelEvents *ev 
     const int blocks = nb * (nb + 1) / 2;
     using OutT = Real;
     if (ev)
-        hipExtLaunchKernelGGL((tile_kernel<P, Q, S0, WQ, Real, OutT, T, S, WPE>), dim3(blocks), dim3(256), 0, s,
+        hipExtLaunchKernelGGL((tile_kernel<P, Q, S0, WQ, Real, OutT, T, S, WPE, NT>), dim3(blocks), dim3(NT), 0, s,
                               ev->start, ev->stop, 0, a, af);
     else
-        hipLaunchKernelGGL((tile_kernel<P, Q, S0, WQ, Real, OutT, T, S, WPE>), dim3(blocks), dim3(256), 0, s, a, af);
+        hipLaunchKernelGGL((tile_kernel<P, Q, S0, WQ, Real, OutT, T, S, WPE, NT>), dim3(blocks), dim3(NT), 0, s, a, af);
     return hipGetLastError();
 }
 
