@@ -29,6 +29,8 @@ __global__ __launch_bounds__(256) void arc_tile_kernel(ArcArgs a)
     __shared__ int off1[T], off2[T];
     __shared__ double sW1[T][QM], sW2[T][QM], sB2[T][QM];
     __shared__ double C1[L][T + 1];
+    double2 *ltab = log_tab_lds();
+    load_log_tab(ltab);
 
     const int N = a.N, npts = a.npts;
     const int nb = (N + T - 1) / T;
@@ -87,7 +89,7 @@ __global__ __launch_bounds__(256) void arc_tile_kernel(ArcArgs a)
             const bool diag = g2 == g1;
             const double dt = diag ? 1.0 : t1 - st2[c2];
             const double ratio = (dx * dx + dy * dy) / (dt * dt) + (diag ? J1 * J1 : 0.0);
-            const double U = 0.5 * log_atanh64(ratio);
+            const double U = 0.5 * log_tab64(ratio, ltab);
             const double V = wsrow[g2];
             const double J2 = sJ2[c2];
             const double JU = J2 * U, JV = J2 * V;

@@ -26,7 +26,11 @@ __global__ __launch_bounds__(256) void colloc_kernel(TileArgs a)
     static_assert(TC % S == 0, "strip must divide tile");
     __shared__ double sx1[TR], sy1[TR], sJ1[TR];
     __shared__ double sx2[L2], sy2[L2], sJ2[L2];
-    __shared__ double sinv[LT], sw[2 * LT];
+    // sinvz[dl] = ((pi / sin(pi d / npts))^2, 1 if d = 0 else 0); sw[par * LT + dl]
+    __shared__ double2 sinvz[LT];
+    __shared__ double sw[2 * LT];
+    double2 *ltab = log_tab_lds();
+    load_log_tab(ltab);
     __shared__ double tileo[TR][TC + 1];
 
     const int N = a.N, npts = a.npts;
@@ -52,16 +56,21 @@ __global__ __launch_bounds__(256) void colloc_kernel(TileArgs a)
     if (dbase < 0) dbase += npts;
     for (int dl = threadIdx.x; dl < LT; dl += blockDim.x) {
         const int d = (dbase + dl) % npts;
-        sinv[dl] = a.inv_s2[d];
+        sinvz[dl] = make_double2(a.inv_s2[d], d == 0 ? 1.0 : 0.0);
         sw[dl] = a.ws[d];
         sw[LT + dl] = a.ws[npts + d];
     }
     __syncthreads();
 
+    // halved regular weights: the 1/2 of K1 = 1/2 ln(...) (exact: a power of two)
+    double ah[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) ah[q] = 0.5 * a.coefA[q];
     for (int item = threadIdx.x; item < TR * NSTRIP; item += blockDim.x) {
         const int r = item % TR, st = item / TR;
         const double x1 = sx1[r], y1 = sy1[r], J1 = sJ1[r];
-        const int par = ((r0 + P * r) % npts) & 1;
+        const double J1sq = J1 * J1;
+        const int par = (r0 + P * r) & 1;        // npts is even: the parity of the node index
         const double *swp = sw + par * LT;      // singular weights of this collocation node's class
         double acc[S];
 #pragma unroll
@@ -72,15 +81,17 @@ __global__ __launch_bounds__(256) void colloc_kernel(TileArgs a)
             const double dx = x1 - sx2[c2], dy = y1 - sy2[c2];
             const double r2 = dx * dx + dy * dy;
             const int dl = c2 - P * r + SPAN1 - 1;
-            const double inv = sinv[dl];
-            const double ratio = (inv == 0.0) ? J1 * J1 : r2 * inv;    // K1(s, s) = ln J(s) (eq. F1_lim)
-            const double U = 0.5 * log_atanh64(ratio);
+            // the diagonal (z = 1, inv = 0) is the same node, r2 = 0 exactly: K1(s, s) = ln J(s)
+            // (eq. F1_lim); U = 2 K1, the 1/2 sits in ah[q]
+            const double2 iz = sinvz[dl];
+            const double ratio = fma(J1sq, iz.y, r2 * iz.x);
+            const double U = log_tab64(ratio, ltab);
             const double J2 = sJ2[c2];
             const double JU = J2 * U, JV = J2 * swp[dl];
 #pragma unroll
             for (int s = 0; s < S; ++s) {
                 const int q = k2 - s * P;
-                if (q >= 0 && q < Q) acc[s] = fma(a.coefA[q], JU, fma(a.coefB[q], JV, acc[s]));
+                if (q >= 0 && q < Q) acc[s] = fma(ah[q], JU, fma(a.coefB[q], JV, acc[s]));
             }
         }
 #pragma unroll

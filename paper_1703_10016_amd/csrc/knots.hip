@@ -30,6 +30,8 @@ __global__ __launch_bounds__(256) void knot_tile_kernel(KnotArgs a)
     __shared__ int sg1[L], sg2[L];
     __shared__ double sW1[T][Q], sW2[T][Q], sB2[T][Q];
     __shared__ double C1[L][T + 1];
+    double2 *ltab = log_tab_lds();
+    load_log_tab(ltab);
     __shared__ double tileo[T][T + 1];
 
     const int N = a.N, npts = a.npts;
@@ -83,7 +85,7 @@ __global__ __launch_bounds__(256) void knot_tile_kernel(KnotArgs a)
             const bool diag = g2 == g1;
             const double sp = diag ? 1.0 : sinpi(d);
             const double ratio = fma(r2, (kPiK / sp) * (kPiK / sp), diag ? J1 * J1 : 0.0);
-            const double U = 0.5 * log_atanh64(ratio);
+            const double U = 0.5 * log_tab64(ratio, ltab);
             const double V = wsrow[g2];
             const double J2 = sJ2[c2];
             const double JU = J2 * U, JV = J2 * V;
