@@ -21,6 +21,7 @@ namespace {
 
 constexpr int NB = 64;            // widest panel (register panels); longer panels use 32 columns
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 struct WS {
     float *LU;       // the FP32 factor (column-major, ld N) or the Gauss-Jordan inverse (row-major, ld Np)
@@ -561,6 +562,116 @@ __global__ __launch_bounds__(256) void gemm_update_kernel(int N, float *LU, int 
                 const int c = n0 + wc + a * 16 + 4 * (lane >> 4) + i;
                 const int r = m0 + wr + b * 16 + (lane & 15);
                 if (r < N && c < cend) LU[int64_t(c) * N + r] = cpre[a][b][i] - acc[a][b][i];
+            }
+}
+
+// The trailing update C -= L21 U12 of the blocked LU (same operands as
+// gemm_update_kernel) for N % 4 == 0, r0 % 4 == 0, klen % 4 == 0: 128 x 128
+// blocks of C on v_mfma_f32_32x32x2_f32, a 64 x 64 quarter (2 x 2 MFMA blocks,
+// accumulators in AGPRs) per wavefront, K in chunks of 16 double-buffered in
+// LDS (one barrier per chunk; the next chunk's loads are in flight during the
+// current chunk's products).  L21 is staged as [k][m] (its column-major
+// layout; the row pitch 160 puts the two k of a 32x32x2 step in disjoint
+// banks), U12 as [n][k] (pitch 18: conflict-free reads).  Each lane's results
+// are four runs of four rows of one column of C, so C moves in 16-byte
+// accesses.  One workgroup per block of C (ntr x ntc blocks); workgroup ids
+// go round-robin over the eight XCDs, and each XCD takes a contiguous run of
+// blocks in an order of bands 16 blocks wide, so that its L2 holds the
+// band's U12 columns while the L21 rows stream through.
+__global__ __launch_bounds__(256) void update128_kernel(int N, float *LU, int r0, int c0, int cend, int kb, int klen,
+                                                        int ntr, int ntc)
+{
+    constexpr int KC = 16, SA = 160, SB = 18;
+    __shared__ __align__(16) float As[2][KC][SA];
+    __shared__ __align__(16) float Bs[2][128][SB];
+    const int ntiles = ntr * ntc, q = ntiles >> 3, rem = ntiles & 7;
+    const int x = int(blockIdx.x & 7), t = x * q + min(x, rem) + int(blockIdx.x >> 3);
+    const int band = t / (16 * ntr), tb = t - band * 16 * ntr, wb = min(16, ntc - band * 16);
+    const int m0 = r0 + (tb / wb) * 128, n0 = c0 + (band * 16 + tb % wb) * 128;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int mw = (wave & 1) * 64, nw = (wave >> 1) * 64, li = lane & 31, lg = lane >> 5;
+    floatx16 acc[2][2];
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) acc[mb][nb][i] = 0.0f;
+    // staging: two float4 of L21 (4 rows of one k) and two of U12 (4 k of one column) per thread,
+    // loaded from clamped addresses and scaled by 0 or 1
+    float4 ra[2], rb[2];
+    auto gload = [&](int kc) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int e = tid + 256 * i, k = e >> 5, m4 = (e & 31) * 4;
+            const float s = (kc + k < klen && m0 + m4 < N) ? 1.0f : 0.0f;
+            const float4 v = *reinterpret_cast<const float4 *>(LU + int64_t(kb + min(kc + k, klen - 1)) * N + min(m0 + m4, N - 4));
+            ra[i] = make_float4(v.x * s, v.y * s, v.z * s, v.w * s);
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int e = tid + 256 * i, n = e >> 2, k4 = (e & 3) * 4;
+            const float s = (n0 + n < cend && kc + k4 < klen) ? 1.0f : 0.0f;
+            const float4 v = *reinterpret_cast<const float4 *>(LU + int64_t(min(n0 + n, cend - 1)) * N + kb + min(kc + k4, klen - 4));
+            rb[i] = make_float4(v.x * s, v.y * s, v.z * s, v.w * s);
+        }
+    };
+    auto swrite = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int e = tid + 256 * i;
+            *reinterpret_cast<float4 *>(&As[buf][e >> 5][(e & 31) * 4]) = ra[i];
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int e = tid + 256 * i, n = e >> 2, k4 = (e & 3) * 4;
+            *reinterpret_cast<float2 *>(&Bs[buf][n][k4]) = make_float2(rb[i].x, rb[i].y);
+            *reinterpret_cast<float2 *>(&Bs[buf][n][k4 + 2]) = make_float2(rb[i].z, rb[i].w);
+        }
+    };
+    const int nc = (klen + KC - 1) / KC;
+    gload(0);
+    swrite(0);
+    __syncthreads();
+    for (int c = 0; c < nc; ++c) {
+        const int buf = c & 1;
+        if (c + 1 < nc) gload((c + 1) * KC);
+        // 32x32x2: lanes 0-31 carry k = 2s, lanes 32-63 k = 2s + 1; A lane i holds row i of the
+        // 32-row block, B lane j column j of the 32-column block
+#pragma unroll
+        for (int s = 0; s < KC / 2; ++s) {
+            const int k = 2 * s + lg;
+            float a[2], b[2];
+#pragma unroll
+            for (int mb = 0; mb < 2; ++mb) a[mb] = As[buf][k][mw + mb * 32 + li];
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb) b[nb] = Bs[buf][nw + nb * 32 + li][k];
+#pragma unroll
+            for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+                for (int nb = 0; nb < 2; ++nb)
+                    acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[mb], b[nb], acc[mb][nb], 0, 0, 0);
+        }
+        if (c + 1 < nc) swrite(buf ^ 1);
+        __syncthreads();
+    }
+    // result (i, j) of a 32x32 block sits in lane j + 32 * ((i / 4) % 2), entry 4 * (i / 8) + i % 4
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+            for (int qq = 0; qq < 4; ++qq) {
+                const int row = m0 + mw + mb * 32 + 8 * qq + 4 * lg, col = n0 + nw + nb * 32 + li;
+                if (row < N && col < cend) {
+                    float4 *p = reinterpret_cast<float4 *>(LU + int64_t(col) * N + row);
+                    float4 cv = *p;
+                    cv.x -= acc[mb][nb][4 * qq + 0];
+                    cv.y -= acc[mb][nb][4 * qq + 1];
+                    cv.z -= acc[mb][nb][4 * qq + 2];
+                    cv.w -= acc[mb][nb][4 * qq + 3];
+                    *p = cv;
+                }
             }
 }
 
@@ -1558,6 +1669,11 @@ namespace {
 // The rank-bk update of the trailing matrix [KE, N) x [KE, N).
 void trailing_update(int N, float *LU, int KE, int K0, int bk, hipStream_t s)
 {
+    if (N % 4 == 0 && KE % 4 == 0 && bk % 4 == 0) {
+        const int nt = (N - KE + 127) / 128;
+        hipLaunchKernelGGL(update128_kernel, dim3(nt * nt), dim3(256), 0, s, N, LU, KE, KE, N, K0, bk, nt, nt);
+        return;
+    }
     const int nb = (N - KE + 63) / 64;
     hipLaunchKernelGGL(gemm_update_kernel, dim3(nb, nb), dim3(256), 0, s, N, LU, KE, KE, N, K0, bk);
 }
@@ -1566,8 +1682,8 @@ void trailing_update(int N, float *LU, int KE, int K0, int bk, hipStream_t s)
 hipError_t lu_factor_f32(int N, float *LU, int *piv, int *info, void *diag_inv, bool pivot, hipStream_t s)
 {
     // Without pivoting (pivot false, N <= 16384, diag_inv required): blocked LU
-    // in 64-column blocks up to N = 4096, 128-column blocks of two 64-column
-    // halves beyond (half the trailing matrix's traffic), the diagonal as pivot
+    // in 64-column blocks up to N = 4096, 256-column blocks of four 64-column
+    // quarters beyond (a quarter of the trailing matrix's traffic), the diagonal as pivot
     // and no interchange anywhere; the inverted 64 x 64 diagonal blocks go to
     // diag_inv.  With partial pivoting, two levels: blocks of BK columns, each
     // factored by narrow register panels whose triangular solves and updates
@@ -1597,31 +1713,30 @@ hipError_t lu_factor_f32(int N, float *LU, int *piv, int *info, void *diag_inv, 
         return hipGetLastError();
     }
     if (!pivot) {
-        // beyond N = 4096: blocks of 128 columns made of two 64-column halves.
-        // Each half is factored and inverted by diag64_kernel and gets its L21
-        // and U12 from panel_mul_kernel; between the halves only the second
-        // half's column strip and row strip take the first half's rank-64
-        // update; the trailing matrix then takes one rank-128 update.
+        // beyond N = 4096: blocks of 256 columns made of four 64-column quarters.
+        // Each quarter is factored and inverted by diag64_kernel and gets its L21
+        // and U12 from panel_mul_kernel; its rank-64 update then goes only to the
+        // block's remaining columns (the column strip, every row below) and to
+        // the block's remaining rows right of the block (the row strip); the
+        // trailing matrix takes one rank-256 update per block.
         float *DI = static_cast<float *>(diag_inv);
-        for (int K0 = 0; K0 < N; K0 += 128) {
-            const int bka = std::min(64, N - K0), KEa = K0 + bka;
-            hipLaunchKernelGGL(diag64_kernel, dim3(1), dim3(128), 0, s, N, LU, K0, bka, DI, info);
-            if (KEa < N) {
-                const int nra = (N - KEa + 63) / 64;
-                hipLaunchKernelGGL(panel_mul_kernel, dim3(2 * nra), dim3(256), 0, s, N, LU, K0, bka, KEa, DI, nra);
-                const int bkb = std::min(64, N - KEa), KEb = KEa + bkb;
-                // column strip (rows from KEa, the second half's columns), then its row strip
-                hipLaunchKernelGGL(gemm_update_kernel, dim3(nra, 1), dim3(256), 0, s, N, LU, KEa, KEa, KEb, K0, bka);
-                if (KEb < N)
-                    hipLaunchKernelGGL(gemm_update_kernel, dim3(1, (N - KEb + 63) / 64), dim3(256), 0, s, N, LU, KEa, KEb,
-                                       N, K0, bka);
-                hipLaunchKernelGGL(diag64_kernel, dim3(1), dim3(128), 0, s, N, LU, KEa, bkb, DI, info);
-                if (KEb < N) {
-                    const int nrb = (N - KEb + 63) / 64;
-                    hipLaunchKernelGGL(panel_mul_kernel, dim3(2 * nrb), dim3(256), 0, s, N, LU, KEa, bkb, KEb, DI, nrb);
-                    trailing_update(N, LU, KEb, K0, KEb - K0, s);
+        for (int K0 = 0; K0 < N; K0 += 256) {
+            const int KE = std::min(N, K0 + 256);
+            for (int Kq = K0; Kq < KE; Kq += 64) {
+                const int bq = std::min(64, N - Kq), KEq = Kq + bq;
+                hipLaunchKernelGGL(diag64_kernel, dim3(1), dim3(128), 0, s, N, LU, Kq, bq, DI, info);
+                if (KEq >= N) break;
+                const int nr = (N - KEq + 63) / 64;
+                hipLaunchKernelGGL(panel_mul_kernel, dim3(2 * nr), dim3(256), 0, s, N, LU, Kq, bq, KEq, DI, nr);
+                if (KEq < KE) {
+                    hipLaunchKernelGGL(gemm_update_kernel, dim3(nr, (KE - KEq + 63) / 64), dim3(256), 0, s, N, LU, KEq, KEq,
+                                       KE, Kq, bq);
+                    if (KE < N)
+                        hipLaunchKernelGGL(gemm_update_kernel, dim3((KE - KEq + 63) / 64, (N - KE + 63) / 64), dim3(256), 0,
+                                           s, N, LU, KEq, KE, N, Kq, bq);
                 }
             }
+            if (KE < N) trailing_update(N, LU, KE, K0, KE - K0, s);
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
