@@ -565,29 +565,29 @@ __global__ __launch_bounds__(256) void gemm_update_kernel(int N, float *LU, int 
             }
 }
 
-// The trailing update C -= L21 U12 of the blocked LU (same operands as
-// gemm_update_kernel) for N % 4 == 0, r0 % 4 == 0, klen % 4 == 0: 128 x 128
-// blocks of C on v_mfma_f32_32x32x2_f32, a 64 x 64 quarter (2 x 2 MFMA blocks,
-// accumulators in AGPRs) per wavefront, K in chunks of 16 double-buffered in
-// LDS (one barrier per chunk; the next chunk's loads are in flight during the
-// current chunk's products).  L21 is staged as [k][m] (its column-major
-// layout; the row pitch 160 puts the two k of a 32x32x2 step in disjoint
-// banks), U12 as [n][k] (pitch 18: conflict-free reads).  Each lane's results
-// are four runs of four rows of one column of C, so C moves in 16-byte
-// accesses.  One workgroup per block of C (ntr x ntc blocks); workgroup ids
-// go round-robin over the eight XCDs, and each XCD takes a contiguous run of
-// blocks in an order of bands 16 blocks wide, so that its L2 holds the
-// band's U12 columns while the L21 rows stream through.
-__global__ __launch_bounds__(256) void update128_kernel(int N, float *LU, int r0, int c0, int cend, int kb, int klen,
-                                                        int ntr, int ntc)
+// One 128 x 128 block at (m0, n0) of the trailing update C -= L21 U12 of the
+// blocked LU (same operands as gemm_update_kernel) for N % 4 == 0,
+// m0 % 4 == 0, klen % 4 == 0, on v_mfma_f32_32x32x2_f32: a 64 x 64 quarter
+// (2 x 2 MFMA blocks, accumulators in AGPRs) per wavefront, K in chunks of 16
+// double-buffered in LDS (one barrier per chunk; the next chunk's loads are in
+// flight during the current chunk's products, and their 0/1 edge masks are
+// applied only when they go to LDS, so no wait sits before the products).
+// L21 is staged as [k][m] (its column-major layout; the row pitch 160 puts the
+// two k of a 32x32x2 step in disjoint banks).  U12 is staged as [n][k] (pitch
+// 18: conflict-free reads), or, with SYM (a symmetric matrix factored without
+// interchanges, where U = D L^T), formed on the fly as U12(k, n) = D_k L(n, k)
+// from the rows n of the column panel and staged as [k][n] like L21.  Each
+// lane's results are four runs of four rows of one column of C, so C moves in
+// 16-byte accesses.
+constexpr int kUpdKC = 16, kUpdSA = 160, kUpdSB = 18;
+constexpr int kUpdBFloats = 2 * kUpdKC * kUpdSA;   // >= 2 * 128 * kUpdSB
+template <bool SYM>
+__device__ __forceinline__ void update128_tile(float (&As)[2][kUpdKC][kUpdSA], float *Bsm, int m0, int n0, int N, float *LU,
+                                               int cend, int kb, int klen)
 {
-    constexpr int KC = 16, SA = 160, SB = 18;
-    __shared__ __align__(16) float As[2][KC][SA];
-    __shared__ __align__(16) float Bs[2][128][SB];
-    const int ntiles = ntr * ntc, q = ntiles >> 3, rem = ntiles & 7;
-    const int x = int(blockIdx.x & 7), t = x * q + min(x, rem) + int(blockIdx.x >> 3);
-    const int band = t / (16 * ntr), tb = t - band * 16 * ntr, wb = min(16, ntc - band * 16);
-    const int m0 = r0 + (tb / wb) * 128, n0 = c0 + (band * 16 + tb % wb) * 128;
+    constexpr int KC = kUpdKC;
+    auto &Bs = *reinterpret_cast<float (*)[2][128][kUpdSB]>(Bsm);
+    auto &Bt = *reinterpret_cast<float (*)[2][kUpdKC][kUpdSA]>(Bsm);
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int mw = (wave & 1) * 64, nw = (wave >> 1) * 64, li = lane & 31, lg = lane >> 5;
     floatx16 acc[2][2];
@@ -598,35 +598,47 @@ __global__ __launch_bounds__(256) void update128_kernel(int N, float *LU, int r0
 #pragma unroll
             for (int i = 0; i < 16; ++i) acc[mb][nb][i] = 0.0f;
     // staging: two float4 of L21 (4 rows of one k) and two of U12 (4 k of one column) per thread,
-    // loaded from clamped addresses and scaled by 0 or 1
+    // loaded from clamped addresses; the 0/1 masks scale them on the way to LDS
     float4 ra[2], rb[2];
+    float sa[2], sb[2];
     auto gload = [&](int kc) {
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
             const int e = tid + 256 * i, k = e >> 5, m4 = (e & 31) * 4;
-            const float s = (kc + k < klen && m0 + m4 < N) ? 1.0f : 0.0f;
-            const float4 v = *reinterpret_cast<const float4 *>(LU + int64_t(kb + min(kc + k, klen - 1)) * N + min(m0 + m4, N - 4));
-            ra[i] = make_float4(v.x * s, v.y * s, v.z * s, v.w * s);
+            sa[i] = (kc + k < klen && m0 + m4 < N) ? 1.0f : 0.0f;
+            ra[i] = *reinterpret_cast<const float4 *>(LU + int64_t(kb + min(kc + k, klen - 1)) * N + min(m0 + m4, N - 4));
         }
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
-            const int e = tid + 256 * i, n = e >> 2, k4 = (e & 3) * 4;
-            const float s = (n0 + n < cend && kc + k4 < klen) ? 1.0f : 0.0f;
-            const float4 v = *reinterpret_cast<const float4 *>(LU + int64_t(min(n0 + n, cend - 1)) * N + kb + min(kc + k4, klen - 4));
-            rb[i] = make_float4(v.x * s, v.y * s, v.z * s, v.w * s);
+            if (SYM) {   // L(n0 + n4 .. + 3, kb + kc + k), scaled by the pivot D_k on the way to LDS
+                const int e = tid + 256 * i, k = e >> 5, n4 = (e & 31) * 4, kk = kb + min(kc + k, klen - 1);
+                sb[i] = (kc + k < klen && n0 + n4 < cend) ? LU[int64_t(kk) * N + kk] : 0.0f;
+                rb[i] = *reinterpret_cast<const float4 *>(LU + int64_t(kk) * N + min(n0 + n4, cend - 4));
+            } else {
+                const int e = tid + 256 * i, n = e >> 2, k4 = (e & 3) * 4;
+                sb[i] = (n0 + n < cend && kc + k4 < klen) ? 1.0f : 0.0f;
+                rb[i] = *reinterpret_cast<const float4 *>(LU + int64_t(min(n0 + n, cend - 1)) * N + kb + min(kc + k4, klen - 4));
+            }
         }
     };
     auto swrite = [&](int buf) {
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
             const int e = tid + 256 * i;
-            *reinterpret_cast<float4 *>(&As[buf][e >> 5][(e & 31) * 4]) = ra[i];
+            const float4 v = ra[i];
+            *reinterpret_cast<float4 *>(&As[buf][e >> 5][(e & 31) * 4]) = make_float4(v.x * sa[i], v.y * sa[i], v.z * sa[i], v.w * sa[i]);
         }
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
-            const int e = tid + 256 * i, n = e >> 2, k4 = (e & 3) * 4;
-            *reinterpret_cast<float2 *>(&Bs[buf][n][k4]) = make_float2(rb[i].x, rb[i].y);
-            *reinterpret_cast<float2 *>(&Bs[buf][n][k4 + 2]) = make_float2(rb[i].z, rb[i].w);
+            const float4 v = rb[i];
+            if (SYM) {
+                const int e = tid + 256 * i;
+                *reinterpret_cast<float4 *>(&Bt[buf][e >> 5][(e & 31) * 4]) = make_float4(v.x * sb[i], v.y * sb[i], v.z * sb[i], v.w * sb[i]);
+            } else {
+                const int e = tid + 256 * i, n = e >> 2, k4 = (e & 3) * 4;
+                *reinterpret_cast<float2 *>(&Bs[buf][n][k4]) = make_float2(v.x * sb[i], v.y * sb[i]);
+                *reinterpret_cast<float2 *>(&Bs[buf][n][k4 + 2]) = make_float2(v.z * sb[i], v.w * sb[i]);
+            }
         }
     };
     const int nc = (klen + KC - 1) / KC;
@@ -645,7 +657,7 @@ __global__ __launch_bounds__(256) void update128_kernel(int N, float *LU, int r0
 #pragma unroll
             for (int mb = 0; mb < 2; ++mb) a[mb] = As[buf][k][mw + mb * 32 + li];
 #pragma unroll
-            for (int nb = 0; nb < 2; ++nb) b[nb] = Bs[buf][nw + nb * 32 + li][k];
+            for (int nb = 0; nb < 2; ++nb) b[nb] = SYM ? Bt[buf][k][nw + nb * 32 + li] : Bs[buf][nw + nb * 32 + li][k];
 #pragma unroll
             for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
@@ -673,6 +685,83 @@ __global__ __launch_bounds__(256) void update128_kernel(int N, float *LU, int r0
                     *p = cv;
                 }
             }
+}
+
+// Block coordinates.  Rectangle: ntr x ntc blocks numbered in bands 16 blocks
+// wide (row by row within a band), so that a run of consecutive blocks shares
+// the band's U12 columns while the L21 rows stream through.  Lower: the blocks
+// of an nt x nt grid that lie in 256 x 256 blocks on or below the diagonal
+// (tr / 2 >= tc / 2), column by column; columns 2j and 2j + 1 hold nt - 2j
+// blocks each, 2j (nt + 1 - j) blocks come before them.
+__device__ __forceinline__ void band_coords(int t, int ntr, int ntc, int &tr, int &tc)
+{
+    const int band = t / (16 * ntr), tb = t - band * 16 * ntr, wb = min(16, ntc - band * 16);
+    tr = tb / wb;
+    tc = band * 16 + tb % wb;
+}
+
+__device__ __forceinline__ void lower256_coords(int t, int nt, int &tr, int &tc)
+{
+    int j = max(0, int(((nt + 1) - sqrtf(float((nt + 1) * (nt + 1) - 2 * t))) * 0.5f));
+    while (j > 0 && 2 * j * (nt + 1 - j) > t) --j;
+    while (2 * (j + 1) * (nt - j) <= t) ++j;
+    const int u = t - 2 * j * (nt + 1 - j), h = nt - 2 * j;
+    tr = 2 * j + u % h;
+    tc = 2 * j + u / h;
+}
+
+// Number of blocks of the lower order for an nt x nt grid.
+inline int lower256_count(int nt) { return 2 * (nt / 2) * (nt + 1 - nt / 2) + (nt % 2); }
+
+// The update over ntiles blocks of 128 x 128 (rectangle or lower order).
+// Workgroup ids go round-robin over the eight XCDs; XCD x takes a contiguous
+// run of the block numbers, and its per_xcd workgroups stride through that
+// run, so one launch of 8 * ceil(blocks / 8) workgroups does one block each
+// and a smaller grid is persistent (it leaves CU slots free for other work on
+// the device).
+template <bool SYM, bool LOWER>
+__global__ __launch_bounds__(256) void update128_kernel(int N, float *LU, int r0, int c0, int cend, int kb, int klen,
+                                                        int ntr, int ntc, int ntiles, int per_xcd)
+{
+    __shared__ __align__(16) float As[2][kUpdKC][kUpdSA];
+    __shared__ __align__(16) float Bsm[kUpdBFloats];
+    const int q = ntiles >> 3, rem = ntiles & 7;
+    const int x = int(blockIdx.x & 7), cnt = q + (x < rem ? 1 : 0), base = x * q + min(x, rem);
+    for (int lt = int(blockIdx.x >> 3); lt < cnt; lt += per_xcd) {
+        int tr, tc;
+        if (LOWER) lower256_coords(base + lt, ntr, tr, tc);
+        else band_coords(base + lt, ntr, ntc, tr, tc);
+        update128_tile<SYM>(As, Bsm, r0 + 128 * tr, c0 + 128 * tc, N, LU, cend, kb, klen);
+    }
+}
+
+// U above the diagonal 256 x 256 blocks of a symmetric matrix factored
+// without interchanges: U(r, c) = D_r L(c, r) for c >= 256 (r / 256 + 1),
+// by 64 x 64 blocks transposed through LDS (the 64 x 64 block (I, J) of U from
+// block (J, I) of L); blocks on or below that line return at once.
+__global__ __launch_bounds__(256) void fill_upper_kernel(int N, float *LU)
+{
+    __shared__ float T[64][65];
+    const int I = blockIdx.y, J = blockIdx.x;   // U rows 64 I.., columns 64 J..
+    if (J < (I / 4 + 1) * 4) return;
+    const int tid = threadIdx.x, r0 = 64 * I, c0 = 64 * J;
+    float v[16];
+#pragma unroll
+    for (int it = 0; it < 16; ++it) {   // L(c0 + i, r0 + j): i fastest (contiguous)
+        const int e = tid + 256 * it, i = e & 63, j = e >> 6;
+        v[it] = LU[int64_t(min(r0 + j, N - 1)) * N + min(c0 + i, N - 1)];
+    }
+#pragma unroll
+    for (int it = 0; it < 16; ++it) {
+        const int e = tid + 256 * it;
+        T[e >> 6][e & 63] = v[it];   // T[j][i] = L(c0 + i, r0 + j)
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < 16; ++it) {   // U(r0 + j, c0 + i): j fastest (contiguous)
+        const int e = tid + 256 * it, j = e & 63, i = e >> 6, r = r0 + j, c = c0 + i;
+        if (r < N && c < N) LU[int64_t(c) * N + r] = LU[int64_t(r) * N + r] * T[j][i];
+    }
 }
 
 // ---------------------------------------------------------------- blocked LU without interchanges
@@ -1670,12 +1759,80 @@ namespace {
 void trailing_update(int N, float *LU, int KE, int K0, int bk, hipStream_t s)
 {
     if (N % 4 == 0 && KE % 4 == 0 && bk % 4 == 0) {
-        const int nt = (N - KE + 127) / 128;
-        hipLaunchKernelGGL(update128_kernel, dim3(nt * nt), dim3(256), 0, s, N, LU, KE, KE, N, K0, bk, nt, nt);
+        const int nt = (N - KE + 127) / 128, per = (nt * nt + 7) / 8;
+        hipLaunchKernelGGL((update128_kernel<false, false>), dim3(8 * per), dim3(256), 0, s, N, LU, KE, KE, N, K0, bk, nt, nt,
+                           nt * nt, per);
         return;
     }
     const int nb = (N - KE + 63) / 64;
     hipLaunchKernelGGL(gemm_update_kernel, dim3(nb, nb), dim3(256), 0, s, N, LU, KE, KE, N, K0, bk);
+}
+
+// C -= L U on rows [r0, rend) and columns [c0, cend) of the factor, L = its
+// columns [kb, kb + klen), U = its rows [kb, kb + klen); rend - r0 is a
+// multiple of 64 or rend = N (the launches cover whole 64- or 128-row blocks
+// and mask only at N).  The 128 x 128 kernel for the rank-256 updates (at most
+// max_per_xcd workgroups per XCD), the 64 x 64 one for the narrow strips of the
+// panel work.
+void update_region(int N, float *LU, int r0, int rend, int c0, int cend, int kb, int klen, hipStream_t s,
+                   int max_per_xcd = 1 << 30)
+{
+    if (rend <= r0 || cend <= c0) return;
+    if (klen > 64 && N % 4 == 0 && r0 % 4 == 0 && klen % 4 == 0 && ((rend - r0) % 128 == 0 || rend == N)) {
+        const int ntr = (rend - r0 + 127) / 128, ntc = (cend - c0 + 127) / 128;
+        const int per = std::min(max_per_xcd, (ntr * ntc + 7) / 8);
+        hipLaunchKernelGGL((update128_kernel<false, false>), dim3(8 * per), dim3(256), 0, s, N, LU, r0, c0, cend, kb, klen,
+                           ntr, ntc, ntr * ntc, per);
+        return;
+    }
+    hipLaunchKernelGGL(gemm_update_kernel, dim3((rend - r0 + 63) / 64, (cend - c0 + 63) / 64), dim3(256), 0, s, N, LU, r0,
+                       c0, cend, kb, klen);
+}
+
+// The symmetric update C -= L21 D L21^T (U12 = D L21^T formed from the column
+// panel, columns [kb, kb + klen) of the factor) for N % 4 == 0: on the
+// rectangle [r0, N) x [c0, cend) (whole 128-row blocks down to N), or, with
+// lower, on the 256 x 256 blocks on or below the diagonal of [r0, N)^2.
+void update_sym_region(int N, float *LU, int r0, int c0, int cend, int kb, int klen, bool lower, hipStream_t s,
+                       int max_per_xcd = 1 << 30)
+{
+    if (r0 >= N || cend <= c0) return;
+    const int ntr = (N - r0 + 127) / 128, ntc = lower ? ntr : (cend - c0 + 127) / 128;
+    const int ntiles = lower ? lower256_count(ntr) : ntr * ntc, per = std::min(max_per_xcd, (ntiles + 7) / 8);
+    if (lower)
+        hipLaunchKernelGGL((update128_kernel<true, true>), dim3(8 * per), dim3(256), 0, s, N, LU, r0, r0, N, kb, klen, ntr,
+                           ntr, ntiles, per);
+    else
+        hipLaunchKernelGGL((update128_kernel<true, false>), dim3(8 * per), dim3(256), 0, s, N, LU, r0, c0, cend, kb, klen, ntr,
+                           ntc, ntiles, per);
+}
+
+// The second stream and events of the look-ahead, one set per host thread and
+// device (each serving thread keeps its own), made on first use and kept for
+// the life of the process.  nullptr if they cannot be made: the updates then
+// all go to the caller's stream, in the same order.
+struct LookAhead {
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_panel = nullptr, ev_rest[2] = {nullptr, nullptr};
+    bool ready = false;
+};
+
+LookAhead *look_ahead_resources()
+{
+    constexpr int kMaxDevices = 16;
+    static thread_local LookAhead la[kMaxDevices];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    LookAhead &r = la[dev];
+    if (!r.ready) {
+        if (hipStreamCreateWithFlags(&r.aux, hipStreamNonBlocking) != hipSuccess) return nullptr;
+        if (hipEventCreateWithFlags(&r.ev_panel, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&r.ev_rest[0], hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&r.ev_rest[1], hipEventDisableTiming) != hipSuccess)
+            return nullptr;
+        r.ready = true;
+    }
+    return &r;
 }
 }  // namespace
 
@@ -1716,29 +1873,84 @@ hipError_t lu_factor_f32(int N, float *LU, int *piv, int *info, void *diag_inv, 
         // beyond N = 4096: blocks of 256 columns made of four 64-column quarters.
         // Each quarter is factored and inverted by diag64_kernel and gets its L21
         // and U12 from panel_mul_kernel; its rank-64 update then goes only to the
-        // block's remaining columns (the column strip, every row below) and to
-        // the block's remaining rows right of the block (the row strip); the
-        // trailing matrix takes one rank-256 update per block.
+        // block's remaining columns (the column strip, every row below) and, for
+        // a general A, to the block's remaining rows right of the block (the row
+        // strip).  Each block's rank-256 trailing update is split in two: the
+        // next block's columns (and rows) (the cross, on s, ahead of the next
+        // block's panel work) and the rest, on a second stream, which runs while
+        // s factors the next block (look-ahead of one block).  Every region is
+        // written by one launch at a time: the cross of block b + 1 waits for the
+        // rest of block b - 1, and the rest of block b for the panel work of
+        // block b.
+        //
+        // The matrices factored here are exactly symmetric (the caller's
+        // symmetry test), so U = D L^T with D the pivots.  For N % 4 == 0 that
+        // halves the work: only the 256 x 256 blocks on or below the diagonal are
+        // updated, with U12 formed as D L21^T from the column panel; U12 is
+        // formed by panel_mul_kernel only inside the diagonal block; no row
+        // strips; and at the end U above the diagonal 256 x 256 blocks is filled
+        // in as D L^T for the triangular solves.
         float *DI = static_cast<float *>(diag_inv);
-        for (int K0 = 0; K0 < N; K0 += 256) {
+        const bool sym = N % 4 == 0;
+        LookAhead *la = look_ahead_resources();
+        hipStream_t aux = la ? la->aux : s;
+        bool aux_used = false;
+        int b = 0;
+        for (int K0 = 0; K0 < N; K0 += 256, ++b) {
             const int KE = std::min(N, K0 + 256);
+            if (K0 > 0) {
+                // the cross of this block takes the previous block's rank-256 update
+                if (la && b >= 2) {
+                    if (hipError_t e = hipStreamWaitEvent(s, la->ev_rest[b & 1], 0); e != hipSuccess) return e;
+                }
+                const int Kp = K0 - 256;
+                if (sym) {
+                    update_sym_region(N, LU, K0, K0, KE, Kp, 256, false, s);
+                } else {
+                    update_region(N, LU, K0, N, K0, KE, Kp, 256, s);
+                    if (KE < N) update_region(N, LU, K0, KE, KE, N, Kp, 256, s);
+                }
+            }
             for (int Kq = K0; Kq < KE; Kq += 64) {
                 const int bq = std::min(64, N - Kq), KEq = Kq + bq;
                 hipLaunchKernelGGL(diag64_kernel, dim3(1), dim3(128), 0, s, N, LU, Kq, bq, DI, info);
                 if (KEq >= N) break;
-                const int nr = (N - KEq + 63) / 64;
-                hipLaunchKernelGGL(panel_mul_kernel, dim3(2 * nr), dim3(256), 0, s, N, LU, Kq, bq, KEq, DI, nr);
+                const int nr = (N - KEq + 63) / 64, nc = sym ? (KE - KEq + 63) / 64 : nr;
+                hipLaunchKernelGGL(panel_mul_kernel, dim3(nr + nc), dim3(256), 0, s, N, LU, Kq, bq, KEq, DI, nr);
                 if (KEq < KE) {
-                    hipLaunchKernelGGL(gemm_update_kernel, dim3(nr, (KE - KEq + 63) / 64), dim3(256), 0, s, N, LU, KEq, KEq,
-                                       KE, Kq, bq);
-                    if (KE < N)
-                        hipLaunchKernelGGL(gemm_update_kernel, dim3((KE - KEq + 63) / 64, (N - KE + 63) / 64), dim3(256), 0,
-                                           s, N, LU, KEq, KE, N, Kq, bq);
+                    update_region(N, LU, KEq, N, KEq, KE, Kq, bq, s);
+                    if (!sym && KE < N) update_region(N, LU, KEq, KE, KE, N, Kq, bq, s);
                 }
             }
-            if (KE < N) trailing_update(N, LU, KE, K0, KE - K0, s);
+            // the rest of this block's trailing update, [KE + 256, N)^2
+            if (KE + 256 < N) {
+                if (la) {
+                    hipError_t e;
+                    if ((e = hipEventRecord(la->ev_panel, s)) != hipSuccess ||
+                        (e = hipStreamWaitEvent(aux, la->ev_panel, 0)) != hipSuccess)
+                        return e;
+                }
+                // two workgroups per CU (as fast as a full grid, measured): the
+                // third slot stays free for the panel work on s
+                if (sym) update_sym_region(N, LU, KE + 256, KE + 256, N, K0, 256, true, aux, la ? 64 : 1 << 30);
+                else update_region(N, LU, KE + 256, N, KE + 256, N, K0, 256, aux, la ? 64 : 1 << 30);
+                if (la) {
+                    if (hipError_t e = hipEventRecord(la->ev_rest[b & 1], aux); e != hipSuccess) return e;
+                    aux_used = true;
+                }
+            }
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
+        }
+        // s resumes after the last rest update
+        if (aux_used) {
+            hipError_t e;
+            if ((e = hipEventRecord(la->ev_panel, aux)) != hipSuccess || (e = hipStreamWaitEvent(s, la->ev_panel, 0)) != hipSuccess)
+                return e;
+        }
+        if (sym) {
+            const int nt = (N + 63) / 64;
+            hipLaunchKernelGGL(fill_upper_kernel, dim3(nt, nt), dim3(256), 0, s, N, LU);
         }
         return hipGetLastError();
     }

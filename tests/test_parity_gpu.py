@@ -239,13 +239,15 @@ def test_positive_definite_solve_without_interchanges(ctx, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("N", [4200, 8200])
+@pytest.mark.parametrize("N", [4200, 4301, 8200])
 def test_positive_definite_large_keeps_factor_without_interchanges(ctx, N, prec):
-    """Beyond N = 4096 the factorisation without interchanges runs in 128-column
-    blocks of two 64-column halves; N = 4200 and 8200 leave ragged second halves
-    (40 and 8 columns).  On the ellipse (positive definite) that factor must be
-    kept (no silent fallback to partial pivoting) and the refined solution must
-    equal LAPACK's FP64 solve of the same stored matrix."""
+    """Beyond N = 4096 the factorisation without interchanges runs in 256-column
+    blocks of four 64-column quarters; N = 4200 and 8200 leave ragged last
+    blocks (104 and 8 columns) and take the symmetric form (U = D L^T, updates
+    of the lower blocks only, U filled in at the end), N = 4301 (not a multiple
+    of 4) the general form.  On the ellipse (positive definite) that factor must
+    be kept (no silent fallback to partial pivoting) and the refined solution
+    must equal LAPACK's FP64 solve of the same stored matrix."""
     c = synth.config_ellipse()
     A = ctx.assemble(c.curve, c.p, N, "wq", precision=prec)
     beta = ctx.rhs(c.curve, c.p, N, c.g)
