@@ -107,6 +107,31 @@ __global__ void to_colmajor_kernel(int N, const InT *A, int64_t lda, float *LU)
     }
 }
 
+// The FP32 factor's starting copy of an exactly symmetric A: column j of the
+// column-major copy is row j of A (equal to the transpose's column), so the
+// copy streams rows and needs no transpose.  With VEC (rows of A 16-byte
+// aligned, N % 4 == 0) four entries per thread move as one vector.
+template <typename InT, bool VEC>
+__global__ __launch_bounds__(256) void copy_rows_kernel(int N, const InT *A, int64_t lda, float *LU)
+{
+    const int j = blockIdx.y, i0 = (blockIdx.x * 256 + threadIdx.x) * 4;
+    if (i0 >= N) return;
+    const InT *a = A + int64_t(j) * lda + i0;
+    float *o = LU + int64_t(j) * N + i0;
+    if (VEC && i0 + 4 <= N) {
+        float4 v;
+        if constexpr (sizeof(InT) == 4) {
+            v = *reinterpret_cast<const float4 *>(a);
+        } else {
+            const double2 lo = *reinterpret_cast<const double2 *>(a), hi = *reinterpret_cast<const double2 *>(a + 2);
+            v = make_float4(float(lo.x), float(lo.y), float(hi.x), float(hi.y));
+        }
+        *reinterpret_cast<float4 *>(o) = v;
+    } else {
+        for (int e = 0; e < 4 && i0 + e < N; ++e) o[e] = float(a[e]);
+    }
+}
+
 // ---------------------------------------------------------------- panel
 // Factor LU[k0:N, k0:k0+w] in place (one workgroup): for every column the
 // pivot is the entry of largest magnitude (lowest row on ties), rows are
@@ -736,31 +761,33 @@ __global__ __launch_bounds__(256) void update128_kernel(int N, float *LU, int r0
 }
 
 // U above the diagonal 256 x 256 blocks of a symmetric matrix factored
-// without interchanges: U(r, c) = D_r L(c, r) for c >= 256 (r / 256 + 1),
-// by 64 x 64 blocks transposed through LDS (the 64 x 64 block (I, J) of U from
-// block (J, I) of L); blocks on or below that line return at once.
+// without interchanges: U(r, c) = D_r L(c, r) for c >= 256 (r / 256 + 1), by
+// blocks of 64 rows x 128 columns of U transposed through LDS (from 128-entry,
+// 512-byte runs of L's columns); blocks left of that line return at once.
 __global__ __launch_bounds__(256) void fill_upper_kernel(int N, float *LU)
 {
-    __shared__ float T[64][65];
-    const int I = blockIdx.y, J = blockIdx.x;   // U rows 64 I.., columns 64 J..
-    if (J < (I / 4 + 1) * 4) return;
-    const int tid = threadIdx.x, r0 = 64 * I, c0 = 64 * J;
-    float v[16];
+    __shared__ float T[64][129];
+    const int I = blockIdx.y, J = blockIdx.x;   // U rows 64 I.., columns 128 J..
+    if (2 * J < (I / 4 + 1) * 4) return;
+    const int tid = threadIdx.x, r0 = 64 * I, c0 = 128 * J;
+    float v[32];
 #pragma unroll
-    for (int it = 0; it < 16; ++it) {   // L(c0 + i, r0 + j): i fastest (contiguous)
-        const int e = tid + 256 * it, i = e & 63, j = e >> 6;
+    for (int it = 0; it < 32; ++it) {   // L(c0 + i, r0 + j): i fastest (contiguous)
+        const int e = tid + 256 * it, i = e & 127, j = e >> 7;
         v[it] = LU[int64_t(min(r0 + j, N - 1)) * N + min(c0 + i, N - 1)];
     }
 #pragma unroll
-    for (int it = 0; it < 16; ++it) {
+    for (int it = 0; it < 32; ++it) {
         const int e = tid + 256 * it;
-        T[e >> 6][e & 63] = v[it];   // T[j][i] = L(c0 + i, r0 + j)
+        T[e >> 7][e & 127] = v[it];   // T[j][i] = L(c0 + i, r0 + j)
     }
     __syncthreads();
+    const int j = tid & 63, r = r0 + j;
+    const float d = LU[int64_t(min(r, N - 1)) * N + min(r, N - 1)];
 #pragma unroll
-    for (int it = 0; it < 16; ++it) {   // U(r0 + j, c0 + i): j fastest (contiguous)
-        const int e = tid + 256 * it, j = e & 63, i = e >> 6, r = r0 + j, c = c0 + i;
-        if (r < N && c < N) LU[int64_t(c) * N + r] = LU[int64_t(r) * N + r] * T[j][i];
+    for (int it = 0; it < 32; ++it) {   // U(r0 + j, c0 + i): j fastest (contiguous)
+        const int i = (tid >> 6) + 4 * it, c = c0 + i;
+        if (r < N && c < N) LU[int64_t(c) * N + r] = d * T[j][i];
     }
 }
 
@@ -1504,52 +1531,137 @@ __global__ __launch_bounds__(256) void inv_apply_kernel(int N, int Np, const flo
 
 // ---------------------------------------------------------------- refinement pieces
 // r = beta - A x (FP64), one wavefront per row; A row-major as stored.
-template <typename InT>
+// Row access of A for the residual and the row sums: one wavefront per row;
+// with VEC (rows 16-byte aligned) each lane takes 16-byte vectors (four FP32 or
+// two FP64 entries), eight of them in flight, then the rest of the row entry
+// by entry.
+template <typename InT, bool VEC>
+struct RowVec {
+    static constexpr int V = VEC ? 16 / int(sizeof(InT)) : 1;
+    // entries [V i, V i + V) of row a, as doubles
+    __device__ static __forceinline__ void load(const InT *a, int i, double (&v)[V])
+    {
+        if constexpr (!VEC) {
+            v[0] = double(a[i]);
+        } else if constexpr (sizeof(InT) == 4) {
+            const float4 f = *reinterpret_cast<const float4 *>(a + 4 * i);
+            v[0] = f.x; v[1] = f.y; v[2] = f.z; v[3] = f.w;
+        } else {
+            const double2 f = *reinterpret_cast<const double2 *>(a + 2 * i);
+            v[0] = f.x; v[1] = f.y;
+        }
+    }
+};
+
+// r = beta - A x, FP64 accumulation: each wavefront takes kResRows rows, so
+// that every load of x serves all of them (x is re-read once per wavefront
+// rather than once per row), two vectors per row in flight per step.
+constexpr int kResRows = 4;
+template <typename InT, bool VEC>
 __global__ __launch_bounds__(256) void residual_kernel(int N, const InT *A, int64_t lda, const double *x,
                                                        const double *beta, double *r, const double *ctl)
 {
-    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    using R = RowVec<InT, VEC>;
+    constexpr int V = R::V, RR = kResRows;
+    const int row0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * RR;
     const int lane = threadIdx.x & 63;
-    if (row >= N || ctl_stopped(ctl)) return;
-    const InT *a = A + int64_t(row) * lda;
-    // eight loads of the row (and of x) in flight per lane, four partial sums
-    double p4[4] = {0.0, 0.0, 0.0, 0.0};
-    int j = lane;
-    for (; j + 7 * 64 < N; j += 8 * 64) {
-        double av[8], xv[8];
+    if (row0 >= N || ctl_stopped(ctl)) return;
+    const InT *a[RR];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) av[u] = double(a[j + 64 * u]);
+    for (int q = 0; q < RR; ++q) a[q] = A + int64_t(min(row0 + q, N - 1)) * lda;
+    const int NV = N / V;
+    double acc[RR][2];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) xv[u] = x[j + 64 * u];
+    for (int q = 0; q < RR; ++q) acc[q][0] = acc[q][1] = 0.0;
+    int i = lane;
+    for (; i + 64 < NV; i += 2 * 64) {
+        double av[2][RR][V], xv[2][V];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) p4[u & 3] += av[u] * xv[u];
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int q = 0; q < RR; ++q) R::load(a[q], i + 64 * h, av[h][q]);
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int e = 0; e < V; ++e) xv[h][e] = x[V * (i + 64 * h) + e];
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int q = 0; q < RR; ++q)
+#pragma unroll
+                for (int e = 0; e < V; ++e) acc[q][h] += av[h][q][e] * xv[h][e];
     }
-    for (; j < N; j += 64) p4[0] += double(a[j]) * x[j];
-    double s = (p4[0] + p4[1]) + (p4[2] + p4[3]);
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-    if (lane == 0) r[row] = beta[row] - s;
+    for (; i < NV; i += 64) {
+        double xv[V];
+#pragma unroll
+        for (int e = 0; e < V; ++e) xv[e] = x[V * i + e];
+#pragma unroll
+        for (int q = 0; q < RR; ++q) {
+            double av[V];
+            R::load(a[q], i, av);
+#pragma unroll
+            for (int e = 0; e < V; ++e) acc[q][0] += av[e] * xv[e];
+        }
+    }
+    for (int j = NV * V + lane; j < N; j += 64)
+#pragma unroll
+        for (int q = 0; q < RR; ++q) acc[q][0] += double(a[q][j]) * x[j];
+#pragma unroll
+    for (int q = 0; q < RR; ++q) {
+        double s = acc[q][0] + acc[q][1];
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+        if (lane == 0 && row0 + q < N) r[row0 + q] = beta[row0 + q] - s;
+    }
 }
 
-template <typename InT>
+// rs = the absolute row sums of A (the infinity norm's terms).
+template <typename InT, bool VEC>
 __global__ __launch_bounds__(256) void rowabs_kernel(int N, const InT *A, int64_t lda, double *rs)
 {
+    using R = RowVec<InT, VEC>;
+    constexpr int V = R::V;
     const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (row >= N) return;
     const InT *a = A + int64_t(row) * lda;
+    const int NV = N / V;
     double p4[4] = {0.0, 0.0, 0.0, 0.0};
-    int j = lane;
-    for (; j + 7 * 64 < N; j += 8 * 64) {
-        double av[8];
+    int i = lane;
+    for (; i + 7 * 64 < NV; i += 8 * 64) {
+        double av[8][V];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) av[u] = double(a[j + 64 * u]);
+        for (int u = 0; u < 8; ++u) R::load(a, i + 64 * u, av[u]);
 #pragma unroll
-        for (int u = 0; u < 8; ++u) p4[u & 3] += fabs(av[u]);
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int e = 0; e < V; ++e) p4[u & 3] += fabs(av[u][e]);
     }
-    for (; j < N; j += 64) p4[0] += fabs(double(a[j]));
+    for (; i < NV; i += 64) {
+        double av[V];
+        R::load(a, i, av);
+#pragma unroll
+        for (int e = 0; e < V; ++e) p4[e & 3] += fabs(av[e]);
+    }
+    for (int j = NV * V + lane; j < N; j += 64) p4[0] += fabs(double(a[j]));
     double s = (p4[0] + p4[1]) + (p4[2] + p4[3]);
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
     if (lane == 0) rs[row] = s;
+}
+
+// True when every row of A starts on a 16-byte boundary.
+template <typename InT>
+bool rows_aligned16(const void *A, int64_t lda)
+{
+    return reinterpret_cast<uintptr_t>(A) % 16 == 0 && (lda * int64_t(sizeof(InT))) % 16 == 0;
+}
+
+template <typename InT>
+void launch_rowabs(int N, const void *A, int64_t lda, double *rs, hipStream_t s)
+{
+    if (rows_aligned16<InT>(A, lda))
+        hipLaunchKernelGGL((rowabs_kernel<InT, true>), dim3((N + 3) / 4), dim3(256), 0, s, N, static_cast<const InT *>(A), lda, rs);
+    else
+        hipLaunchKernelGGL((rowabs_kernel<InT, false>), dim3((N + 3) / 4), dim3(256), 0, s, N, static_cast<const InT *>(A), lda, rs);
 }
 
 // Largest of two values that propagates NaN (fmax returns the other operand),
@@ -1669,8 +1781,12 @@ template <typename InT>
 void launch_residual(int N, const void *A, int64_t lda, const double *x, const double *beta, double *r, hipStream_t s,
                      const double *ctl = nullptr)
 {
-    hipLaunchKernelGGL(residual_kernel<InT>, dim3((N + 3) / 4), dim3(256), 0, s, N, static_cast<const InT *>(A), lda,
-                       x, beta, r, ctl);
+    if (rows_aligned16<InT>(A, lda))
+        hipLaunchKernelGGL((residual_kernel<InT, true>), dim3((N + 4 * kResRows - 1) / (4 * kResRows)), dim3(256), 0, s, N,
+                           static_cast<const InT *>(A), lda, x, beta, r, ctl);
+    else
+        hipLaunchKernelGGL((residual_kernel<InT, false>), dim3((N + 4 * kResRows - 1) / (4 * kResRows)), dim3(256), 0, s, N,
+                           static_cast<const InT *>(A), lda, x, beta, r, ctl);
 }
 
 // Exact symmetry test of A (row-major, leading dimension lda): each workgroup
@@ -1949,8 +2065,7 @@ hipError_t lu_factor_f32(int N, float *LU, int *piv, int *info, void *diag_inv, 
                 return e;
         }
         if (sym) {
-            const int nt = (N + 63) / 64;
-            hipLaunchKernelGGL(fill_upper_kernel, dim3(nt, nt), dim3(256), 0, s, N, LU);
+            hipLaunchKernelGGL(fill_upper_kernel, dim3((N + 127) / 128, (N + 63) / 64), dim3(256), 0, s, N, LU);
         }
         return hipGetLastError();
     }
@@ -2058,10 +2173,10 @@ int mixed_solve(int N, const void *d_A, int64_t lda, int a_prec, const double *d
     // ||A||_inf for the backward error (one read of A) and the exact symmetry test
     const int ngrid = std::min(N, 1024);
     if (a_prec == 0) {
-        hipLaunchKernelGGL(rowabs_kernel<double>, dim3((N + 3) / 4), dim3(256), 0, s, N, static_cast<const double *>(d_A), lda, w.red + 64);
+        launch_rowabs<double>(N, d_A, lda, w.red + 64, s);
         hipLaunchKernelGGL(asym_kernel<double>, dim3(ngrid), dim3(256), 0, s, N, static_cast<const double *>(d_A), lda, w.r);
     } else {
-        hipLaunchKernelGGL(rowabs_kernel<float>, dim3((N + 3) / 4), dim3(256), 0, s, N, static_cast<const float *>(d_A), lda, w.red + 64);
+        launch_rowabs<float>(N, d_A, lda, w.red + 64, s);
         hipLaunchKernelGGL(asym_kernel<float>, dim3(ngrid), dim3(256), 0, s, N, static_cast<const float *>(d_A), lda, w.r);
     }
     hipLaunchKernelGGL(max_kernel, dim3(1), dim3(1024), 0, s, N, w.red + 64, ctl + CTL_NORMA);
@@ -2154,11 +2269,20 @@ int mixed_solve(int N, const void *d_A, int64_t lda, int a_prec, const double *d
             na_known = true;
         }
         {
-            dim3 tg((N + 31) / 32, (N + 31) / 32);
-            if (a_prec == 0)
-                hipLaunchKernelGGL(to_colmajor_kernel<double>, tg, dim3(256), 0, s, N, static_cast<const double *>(d_A), lda, w.LU);
-            else
-                hipLaunchKernelGGL(to_colmajor_kernel<float>, tg, dim3(256), 0, s, N, static_cast<const float *>(d_A), lda, w.LU);
+            // without interchanges A is exactly symmetric: a plain copy of its rows
+            dim3 tg((N + 31) / 32, (N + 31) / 32), rg((N + 1023) / 1024, N);
+            const bool vec = N % 4 == 0 && (a_prec == 0 ? rows_aligned16<double>(d_A, lda) : rows_aligned16<float>(d_A, lda));
+            if (a_prec == 0) {
+                const double *A64 = static_cast<const double *>(d_A);
+                if (pivot) hipLaunchKernelGGL(to_colmajor_kernel<double>, tg, dim3(256), 0, s, N, A64, lda, w.LU);
+                else if (vec) hipLaunchKernelGGL((copy_rows_kernel<double, true>), rg, dim3(256), 0, s, N, A64, lda, w.LU);
+                else hipLaunchKernelGGL((copy_rows_kernel<double, false>), rg, dim3(256), 0, s, N, A64, lda, w.LU);
+            } else {
+                const float *A32 = static_cast<const float *>(d_A);
+                if (pivot) hipLaunchKernelGGL(to_colmajor_kernel<float>, tg, dim3(256), 0, s, N, A32, lda, w.LU);
+                else if (vec) hipLaunchKernelGGL((copy_rows_kernel<float, true>), rg, dim3(256), 0, s, N, A32, lda, w.LU);
+                else hipLaunchKernelGGL((copy_rows_kernel<float, false>), rg, dim3(256), 0, s, N, A32, lda, w.LU);
+            }
             if ((e = lu_factor_f32(N, w.LU, w.piv, w.info, w.DI, pivot, s)) != hipSuccess)
                 return fail(-5, "LU factorisation launch", e);
             if ((N + 63) / 64 >= 2)     // at least one pair of diagonal blocks
