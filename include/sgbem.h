@@ -135,7 +135,9 @@ sgbem_status sgbem_ctx_memory(sgbem_ctx ctx, int64_t *held_bytes, int64_t *budge
  *  SGBEM_MEM_RHS_DIRECT:   sgbem_rhs_direct with n_gauss points: node geometry and
  *                          the double-layer sweep's workspace;
  *  SGBEM_MEM_SOLVE:        sgbem_solve of order N: 4 N_p^2 + about 1.8 N_p KB,
- *                          N_p = N rounded up to a multiple of 64;
+ *                          N_p = N rounded up to a multiple of 64, plus, for
+ *                          N > 4096, 8 MiB per 1024 rows (the inverted
+ *                          1024-row diagonal blocks of the triangular factors);
  *  SGBEM_MEM_RULES_OPEN:   one sgbem_weights_open handle (N = n_el elements):
  *                          16 N Q_M + 8 n_q^2 + 8 n_q + 8 N bytes, Q_M = 2 n_ref (p + 1)
  *                          - 1 + 2p, n_q = 2p + 2 n_ref n_el - 1 nodes, plus alignment;

@@ -20,6 +20,12 @@ namespace sgbem {
 namespace {
 
 constexpr int NB = 64;            // widest panel (register panels); longer panels use 32 columns
+constexpr int kGJMaxN = 4096;     // up to this order: the explicit inverse (block Gauss-Jordan)
+// Beyond kGJMaxN the triangular solves go by super-blocks of kSB rows with the
+// inverses of L's and U's kSB x kSB diagonal super-blocks formed once per factor.
+constexpr int kSB = 1024;
+int superblocks(int N) { return (N + kSB - 1) / kSB; }
+size_t blkinv_floats(int N) { return N > kGJMaxN ? size_t(2) * superblocks(N) * kSB * kSB : 0; }
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
@@ -32,6 +38,7 @@ struct WS {
     float *DI;       // inverted diagonal blocks
     float *DI2;      // off-diagonal blocks of the inverses of pairs of diagonal blocks
     float *GR, *GC, *GP;   // Gauss-Jordan panels: row blocks [2][nt][64][64], column blocks [2][nt][64][64], pivot inverses [2][64][64]
+    float *INV;      // beyond kGJMaxN: [super-block][L, U][kSB x kSB] inverted diagonal super-blocks (column-major), else null
 };
 
 // Order padded to whole 64 x 64 tiles (the Gauss-Jordan inverse works on tiles).
@@ -81,6 +88,8 @@ WS carve(void *base, int N)
     w.GC = reinterpret_cast<float *>(p);
     p += align_up(2 * nt * 4096 * sizeof(float));
     w.GP = reinterpret_cast<float *>(p);
+    p += align_up(2 * 4096 * sizeof(float));
+    w.INV = N > kGJMaxN ? reinterpret_cast<float *>(p) : nullptr;
     return w;
 }
 
@@ -1209,6 +1218,222 @@ __global__ __launch_bounds__(256) void trsv_upper2_kernel(int N, const float *LU
     if (q == 0 && r < b0) y[r] -= (part[0][lr] + part[1][lr]) + (part[2][lr] + part[3][lr]);
 }
 
+// ---------------------------------------------------------------- inverted diagonal super-blocks
+// The inverses of L's (unit lower) and U's (upper) kSB x kSB diagonal blocks
+// (rows beyond N padded with the identity), built by recursive doubling from
+// the inverted 64 x 64 blocks: with a block split into halves P1, P2 of h rows,
+//   inv(L) = [[inv(P1), 0], [-inv(P2) L21 inv(P1), inv(P2)]],
+//   inv(U) = [[inv(P1), -inv(P1) U12 inv(P2)], [0, inv(P2)]],
+// for h = 64, 128, 256, 512, the products of one level batched in two launches
+// (T = L21 inv(P1) or inv(P1) U12, then the off-diagonal block from T; T sits in
+// the unused triangle of the same kSB x kSB block, which every later read of an
+// inverted block masks out).  Storage: INV + (sb * 2 + f)
+// kSB^2, f = 0 for L, 1 for U, column-major with leading dimension kSB.
+
+// The 64 x 64 diagonal blocks: DI's inverses (identity beyond N).
+__global__ __launch_bounds__(256) void blkinv_diag_kernel(int N, const float *DI, float *INV)
+{
+    const int t = blockIdx.x, sb = blockIdx.y >> 1, f = blockIdx.y & 1, g = sb * (kSB / 64) + t;
+    float *dst = INV + (int64_t(sb) * 2 + f) * kSB * kSB + int64_t(64 * t) * kSB + 64 * t;
+    const float *src = DI + (int64_t(g) * 2 + f) * 4096;
+    const bool in = 64 * g < N;
+#pragma unroll
+    for (int it = 0; it < 16; ++it) {
+        const int e = threadIdx.x + 256 * it, r = e & 63, c = e >> 6;
+        dst[int64_t(c) * kSB + r] = in ? src[e] : (r == c ? 1.0f : 0.0f);
+    }
+}
+
+// A view of a column-major matrix: entry (i, k) = base[(c0 + k) ld + r0 + i],
+// read as 0 outside [0, rmax) x [0, cmax) (addresses clamped) and, for a view
+// of an inverted block (tri 1: lower, 2: upper), outside its triangle: the
+// other triangle holds the scratch products of the doubling.
+struct MatView {
+    const float *base;
+    int64_t ld;
+    int r0, c0, rmax, cmax, tri;
+    __device__ float at(int i, int k) const
+    {
+        const int r = r0 + i, c = c0 + k;
+        const float v = base[int64_t(min(c, cmax - 1)) * ld + min(r, rmax - 1)];
+        const bool in = r < rmax && c < cmax && !(tri == 1 && r < c) && !(tri == 2 && r > c);
+        return in ? v : 0.0f;
+    }
+};
+
+// One level h of the doubling, stage 1 (T) or 2 (the off-diagonal block): the
+// workgroup forms the 64 x 64 block (ti, tj) of C = alpha A B (h x h x h) for
+// item z (factor f = z & 1, pair z >> 1 over super-blocks), on
+// v_mfma_f32_16x16x4_f32 with the layout of gemm_update_kernel (K in chunks of
+// 32 through LDS, a 32 x 32 quarter per wavefront).
+template <int STAGE>
+__global__ __launch_bounds__(256) void blkinv_gemm_kernel(int N, const float *LU, float *INV, int h)
+{
+    __shared__ float As[64][33];   // A chunk: [row][k]
+    __shared__ float Bs[64][33];   // B chunk transposed: [col][k]
+    const int npairs = kSB / (2 * h), z = blockIdx.z, f = z & 1, pl = z >> 1, sb = pl / npairs, a = 2 * h * (pl % npairs);
+    const int a0 = sb * kSB, big = 1 << 30;
+    float *IF = INV + (int64_t(sb) * 2 + f) * kSB * kSB;
+    MatView A, B;
+    int cr, cc;   // C block origin (local to IF)
+    float alpha;
+    if (STAGE == 1) {
+        if (f == 0) {   // T = L21 inv(P1) -> IF(a.., a+h..)
+            A = {LU, N, a0 + a + h, a0 + a, N, N, 0};
+            B = {IF, kSB, a, a, big, big, 1};
+            cr = a; cc = a + h;
+        } else {        // T = inv(P1) U12 -> IF(a+h.., a..)
+            A = {IF, kSB, a, a, big, big, 2};
+            B = {LU, N, a0 + a, a0 + a + h, N, N, 0};
+            cr = a + h; cc = a;
+        }
+        alpha = 1.0f;
+    } else {
+        if (f == 0) {   // inv(L)_21 = -inv(P2) T -> IF(a+h.., a..)
+            A = {IF, kSB, a + h, a + h, big, big, 1};
+            B = {IF, kSB, a, a + h, big, big, 0};
+            cr = a + h; cc = a;
+        } else {        // inv(U)_12 = -T inv(P2) -> IF(a.., a+h..)
+            A = {IF, kSB, a + h, a, big, big, 0};
+            B = {IF, kSB, a + h, a + h, big, big, 2};
+            cr = a; cc = a + h;
+        }
+        alpha = -1.0f;
+    }
+    const int m0 = 64 * blockIdx.x, n0 = 64 * blockIdx.y;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int wc = (wave >> 1) * 32, wr = (wave & 1) * 32;
+    floatx4 acc[2][2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) acc[x][y] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int kc = 0; kc < h; kc += 32) {
+        float va[8], vb[8];
+#pragma unroll
+        for (int it = 0; it < 8; ++it) {
+            const int e = tid + it * 256;
+            va[it] = A.at(m0 + (e & 63), kc + (e >> 6));
+            vb[it] = B.at(kc + (e & 31), n0 + (e >> 5));
+        }
+#pragma unroll
+        for (int it = 0; it < 8; ++it) {
+            const int e = tid + it * 256;
+            As[e & 63][e >> 6] = va[it];
+            Bs[e >> 5][e & 31] = vb[it];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 32; k += 4) {
+            const int kk = k + (lane >> 4);
+#pragma unroll
+            for (int x = 0; x < 2; ++x) {
+                const float av = Bs[wc + x * 16 + (lane & 15)][kk];   // MFMA A: [C column][k]
+#pragma unroll
+                for (int y = 0; y < 2; ++y) {
+                    const float bv = As[wr + y * 16 + (lane & 15)][kk];   // MFMA B: [k][C row]
+                    acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[x][y], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int c = n0 + wc + x * 16 + 4 * (lane >> 4) + i, r = m0 + wr + y * 16 + (lane & 15);
+                IF[int64_t(cc + c) * kSB + cr + r] = alpha * acc[x][y][i];
+            }
+}
+
+// Forms the inverted super-blocks of the factor (after its 64 x 64 inverses DI).
+void blkinv_build(int N, const float *LU, const float *DI, float *INV, hipStream_t s)
+{
+    const int nsb = superblocks(N);
+    hipLaunchKernelGGL(blkinv_diag_kernel, dim3(kSB / 64, 2 * nsb), dim3(256), 0, s, N, DI, INV);
+    for (int h = 64; 2 * h <= kSB; h *= 2) {
+        const dim3 g(h / 64, h / 64, 2 * nsb * (kSB / (2 * h)));
+        hipLaunchKernelGGL(blkinv_gemm_kernel<1>, g, dim3(256), 0, s, N, LU, INV, h);
+        hipLaunchKernelGGL(blkinv_gemm_kernel<2>, g, dim3(256), 0, s, N, LU, INV, h);
+    }
+}
+
+// out[r] = sum_c M(r, c) in[c] (or out[r] -= it) over the rows [r0, r1) and
+// columns [c0, c1) (c1 - c0 <= 1024), in and out indexed like the rows and
+// columns, M column-major with entry (r, c) at M[(c + mc0) ld + r + mr0] (the
+// offsets map them into M's own indices): 64 rows per workgroup, lane i holding
+// row i, the 16 wavefronts taking 64 columns each (32 loads of a column block
+// in flight before their products), partial sums meeting in LDS in a fixed
+// order.  TRI: 1 = only column blocks at or left of the row block (the
+// lower triangle of an inverted L super-block), 2 = at or right of it (U), 0 =
+// all.  ACC: out -= the sum (the updates), else out = the sum.
+template <int TRI, bool ACC>
+__global__ __launch_bounds__(1024) void blk_matvec_kernel(const float *M, int64_t ld, int r0, int r1, int c0, int c1,
+                                                          int mr0, int mc0, const float *in, float *out)
+{
+    __shared__ float xs[1024];
+    __shared__ float part[16][64];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int rb = blockIdx.x, r = r0 + 64 * rb + lane;
+    if (c0 + tid < c1) xs[tid] = in[c0 + tid];
+    __syncthreads();
+    const int cb0 = 64 * wave, ncol = min(64, c1 - c0 - cb0);
+    // the triangular kinds have r0 == c0: row block rb and column block wave, counted alike
+    const bool skip = ncol <= 0 || (TRI == 1 && wave > rb) || (TRI == 2 && wave < rb);
+    float p4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (!skip) {
+        const float *m = M + int64_t(mc0 + c0 + cb0) * ld + mr0 + r0 + 64 * rb + min(lane, r1 - r0 - 64 * rb - 1);
+#pragma unroll
+        for (int k0 = 0; k0 < 64; k0 += 32) {   // two halves of 32 loads in flight
+            float v[32];
+#pragma unroll
+            for (int k = 0; k < 32; ++k) v[k] = m[int64_t(min(k0 + k, ncol - 1)) * ld];
+#pragma unroll
+            for (int k = 0; k < 32; ++k) p4[k & 3] += (k0 + k < ncol ? v[k] : 0.0f) * xs[cb0 + min(k0 + k, ncol - 1)];
+        }
+    }
+    part[wave][lane] = (p4[0] + p4[1]) + (p4[2] + p4[3]);
+    __syncthreads();
+    if (wave == 0 && r < r1) {
+        float t = 0.0f;
+#pragma unroll
+        for (int w = 0; w < 16; ++w) t += part[w][lane];
+        if (ACC) out[r] -= t;
+        else out[r] = t;
+    }
+}
+
+// b := U^{-1} L^{-1} b for an already permuted b by super-blocks (tmp: N
+// floats of scratch), with the inverted super-blocks INV: per super-block one
+// product with its inverse and one update of the rows after (forward) or
+// before (backward) it.
+hipError_t lu_solve_blk(int N, const float *LU, const float *INV, float *b, float *tmp, hipStream_t s)
+{
+    const int nsb = superblocks(N);
+    for (int sb = 0; sb < nsb; ++sb) {
+        const int S0 = sb * kSB, bs = std::min(kSB, N - S0);
+        const float *IL = INV + (int64_t(sb) * 2) * kSB * kSB;
+        hipLaunchKernelGGL((blk_matvec_kernel<1, false>), dim3((bs + 63) / 64), dim3(1024), 0, s, IL, int64_t(kSB), S0,
+                           S0 + bs, S0, S0 + bs, -S0, -S0, b, tmp);
+        if (S0 + bs < N)
+            hipLaunchKernelGGL((blk_matvec_kernel<0, true>), dim3((N - S0 - bs + 63) / 64), dim3(1024), 0, s, LU, int64_t(N),
+                               S0 + bs, N, S0, S0 + bs, 0, 0, tmp, b);
+    }
+    for (int sb = nsb - 1; sb >= 0; --sb) {
+        const int S0 = sb * kSB, bs = std::min(kSB, N - S0);
+        const float *IU = INV + (int64_t(sb) * 2 + 1) * kSB * kSB;
+        hipLaunchKernelGGL((blk_matvec_kernel<2, false>), dim3((bs + 63) / 64), dim3(1024), 0, s, IU, int64_t(kSB), S0,
+                           S0 + bs, S0, S0 + bs, -S0, -S0, tmp, b);
+        if (S0 > 0)
+            hipLaunchKernelGGL((blk_matvec_kernel<0, true>), dim3((S0 + 63) / 64), dim3(1024), 0, s, LU, int64_t(N), 0, S0, S0,
+                               S0 + bs, 0, 0, b, tmp);
+    }
+    return hipGetLastError();
+}
+
 __global__ void permute_kernel(int N, const int *perm, const double *src, float *dst)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1228,7 +1453,6 @@ __global__ void permute_kernel(int N, const int *perm, const double *src, float 
 // launch), and the workgroup that updates the next pivot tile also inverts it.
 // Every product runs on v_mfma_f32_16x16x4_f32.  A refinement step then needs
 // one matrix-vector product with X instead of two triangular solves.
-constexpr int kGJMaxN = 4096;
 typedef float Tile64[64][65];
 
 // acc[a][b][v] = (X Y)[wr + 16 a + 4 (lane >> 4) + v][wc + 16 b + (lane & 15)]:
@@ -1865,7 +2089,8 @@ size_t solve_workspace_bytes(int N)
            align_up(size_t(N) * sizeof(double)) + 2 * align_up(size_t(N) * sizeof(float)) + align_up(64 * sizeof(double)) +
            align_up(size_t(N) * sizeof(double)) + align_up(nblk * 2 * 4096 * sizeof(float)) +
            align_up(std::max<size_t>(nblk / 2, 1) * 2 * 4096 * sizeof(float)) +
-           2 * align_up(2 * nblk * 4096 * sizeof(float)) + align_up(2 * 4096 * sizeof(float));
+           2 * align_up(2 * nblk * 4096 * sizeof(float)) + align_up(2 * 4096 * sizeof(float)) +
+           align_up(blkinv_floats(N) * sizeof(float));
 }
 
 bool lu_without_pivoting_supported(int N) { return N <= 16384; }
@@ -2285,13 +2510,18 @@ int mixed_solve(int N, const void *d_A, int64_t lda, int a_prec, const double *d
             }
             if ((e = lu_factor_f32(N, w.LU, w.piv, w.info, w.DI, pivot, s)) != hipSuccess)
                 return fail(-5, "LU factorisation launch", e);
-            if ((N + 63) / 64 >= 2)     // at least one pair of diagonal blocks
+            // the triangular solves' inverted blocks: 1024-row super-blocks beyond
+            // kGJMaxN, pairs of 64-row blocks below
+            if (w.INV)
+                blkinv_build(N, w.LU, w.DI, w.INV, s);
+            else if ((N + 63) / 64 >= 2)     // at least one pair of diagonal blocks
                 hipLaunchKernelGGL(pair_inverse_kernel, dim3(2 * ((N + 63) / 64 / 2)), dim3(256), 0, s, N, w.LU, w.DI, w.DI2);
         }
         // d = (LU)^-1 P rhs
         auto apply = [&](const double *rhs) {
             hipLaunchKernelGGL(permute_kernel, dim3((N + 255) / 256), dim3(256), 0, s, N, w.perm, rhs, w.v);
-            (void)lu_solve_f32(N, w.LU, w.DI, w.DI2, w.v, w.v2, s);
+            if (w.INV) (void)lu_solve_blk(N, w.LU, w.INV, w.v, w.v2, s);
+            else (void)lu_solve_f32(N, w.LU, w.DI, w.DI2, w.v, w.v2, s);
         };
         // the permutation from the interchange sequence (host, O(N)); none without
         // pivoting, and then no wait here either: the zero-pivot flag is read with

@@ -164,8 +164,9 @@ def _buf(b):
 
 def test_memory_need_formulas():
     """Device bytes per call kind, as the header states them: rule block
-    72 M (+ alignment), node geometry 48 M, solve workspace 4 N^2 + O(N), each
-    buffer rounded up to 4096 bytes, control nets beyond 64 points added."""
+    72 M (+ alignment), node geometry 48 M, solve workspace 4 N^2 + O(N) (plus
+    8 MiB per 1024 rows beyond N = 4096), each buffer rounded up to 4096 bytes,
+    control nets beyond 64 points added."""
     S = _lib()
     for p, N, R in [(3, 1024, 1), (2, 16384, 1), (4, 700, 2), (6, 14, 4)]:
         M = R * N
@@ -176,10 +177,12 @@ def test_memory_need_formulas():
         assert S.sgbem_memory_need(S.SGBEM_MEM_ASSEMBLE_WQ, p, N, R) == _buf(48 * M)
         assert S.sgbem_memory_need(S.SGBEM_MEM_ASSEMBLE_WQ, p, N, R, n_ctrl=64) == _buf(48 * M)
         assert S.sgbem_memory_need(S.SGBEM_MEM_ASSEMBLE_WQ, p, N, R, n_ctrl=100) == _buf(48 * M) + _buf(8 * 301)
-    for N in (16, 1000, 4099, 16384):
+    for N in (16, 1000, 4096, 4099, 16384):
         sv = S.sgbem_memory_need(S.SGBEM_MEM_SOLVE, 1, N)
         Np = (N + 63) // 64 * 64
-        assert 4 * N * N <= sv <= 4 * Np * Np + 1900 * Np + 65536 and sv % 4096 == 0
+        # beyond N = 4096: the inverted 1024-row diagonal blocks of L and U, 8 MiB per 1024 rows
+        inv = 8 * 1024 * 1024 * ((N + 1023) // 1024) if N > 4096 else 0
+        assert 4 * N * N + inv <= sv <= 4 * Np * Np + inv + 1900 * Np + 65536 and sv % 4096 == 0
     p, N, G = 3, 200, 5
     ebe = S.sgbem_memory_need(S.SGBEM_MEM_ASSEMBLE_EBE, p, N, 1, G)
     assert ebe == _buf(24 * N * G) + _buf(24 * N * 16) + _buf(16 * N * (p + 1) ** 2) + _buf(8 * (544 + 16 * (p + 1))) \
