@@ -292,6 +292,8 @@ def main():
                          "(the copy calibrates the byte counters of a profiler run)")
     ap.add_argument("--profile-n", type=int, default=0,
                     help="with --profile-run: assemble the star curve (p = 3) at this N instead of the workload")
+    ap.add_argument("--profile-solve", type=int, default=0,
+                    help="profiling only: assemble the star curve (p = 3) at this N in FP32 and solve it W + K times")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: there is no multi-GPU path (the matrix would be "
@@ -316,6 +318,18 @@ def main():
     t0 = time.perf_counter()
     ctx.rules(p, N, R)
     t_rules = time.perf_counter() - t0
+    if args.profile_solve:
+        Ns = args.profile_solve
+        star = synth.star(0)
+        A = torch.empty((Ns, Ns), dtype=torch.float32, device="cuda")
+        ctx.assemble(star, p, Ns, "wq", n_ref=R, precision="fp32", out=A)
+        bb = ctx.rhs(star, p, Ns, g, method="wq", n_ref=R)
+        for _ in range(W + K):
+            xb, sinfo = ctx.solve(A, bb, tol=1e-10, max_iter=30)
+        torch.cuda.synchronize()
+        log(f"[bench] profile run: {W + K} solves of the N={Ns} star (FP32 matrix), {sinfo.iters} refinement steps")
+        ctx.close()
+        return
     if args.profile_run:
         if args.profile_n:
             curve, N = synth.star(0), args.profile_n
