@@ -529,6 +529,7 @@ __global__ __launch_bounds__(1024) void trsm_block_kernel(int N, float *LU, int 
 // results are contiguous in the column-major factor.
 __global__ __launch_bounds__(256) void gemm_update_kernel(int N, float *LU, int r0, int c0, int cend, int kb, int klen)
 {
+    __builtin_amdgcn_s_setprio(3);   // panel work: ahead of the trailing update's MFMA waves on a shared SIMD
     __shared__ float As[64][33];   // L21 chunk: [row][k]
     __shared__ float Bs[64][33];   // U12 chunk transposed: [col][k]
     const int m0 = r0 + blockIdx.x * 64;    // first row of C
@@ -761,6 +762,7 @@ __global__ __launch_bounds__(256) void update128_kernel(int N, float *LU, int r0
     __shared__ __align__(16) float Bsm[kUpdBFloats];
     const int q = ntiles >> 3, rem = ntiles & 7;
     const int x = int(blockIdx.x & 7), cnt = q + (x < rem ? 1 : 0), base = x * q + min(x, rem);
+    if (SYM && !LOWER) __builtin_amdgcn_s_setprio(2);   // the next block's panel: ahead of the rest update
     for (int lt = int(blockIdx.x >> 3); lt < cnt; lt += per_xcd) {
         int tr, tc;
         if (LOWER) lower256_coords(base + lt, ntr, tr, tc);
@@ -816,6 +818,7 @@ __global__ __launch_bounds__(256) void fill_upper_kernel(int N, float *LU)
 // reported in info like a singular column.
 __global__ __launch_bounds__(128) void diag64_kernel(int N, float *LU, int K0, int bk, float *DI, int *info)
 {
+    __builtin_amdgcn_s_setprio(3);   // panel work: ahead of the trailing update's MFMA waves on a shared SIMD
     __shared__ float F[64][65];      // the factor: unit-lower L below the diagonal, U on and above
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if (wave == 0) {
@@ -885,6 +888,7 @@ __global__ __launch_bounds__(128) void diag64_kernel(int N, float *LU, int K0, i
 // place: every workgroup reads and writes only its own entries).
 __global__ __launch_bounds__(256) void panel_mul_kernel(int N, float *LU, int K0, int bk, int KE, const float *DI, int nrb)
 {
+    __builtin_amdgcn_s_setprio(3);   // panel work: ahead of the trailing update's MFMA waves on a shared SIMD
     __shared__ float X[64][65], V[64][65];
     const int tid = threadIdx.x;
     const bool rows = int(blockIdx.x) < nrb;
@@ -2223,6 +2227,10 @@ hipError_t lu_factor_f32(int N, float *LU, int *piv, int *info, void *diag_inv, 
         // written by one launch at a time: the cross of block b + 1 waits for the
         // rest of block b - 1, and the rest of block b for the panel work of
         // block b.
+        //
+        // The panel work on s (and the cross update) raise their wavefronts'
+        // issue priority: on a SIMD shared with the rest update's MFMA waves
+        // their short dependent chains would otherwise wait behind them.
         //
         // The matrices factored here are exactly symmetric (the caller's
         // symmetry test), so U = D L^T with D the pivots.  For N % 4 == 0 that
