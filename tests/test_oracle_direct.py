@@ -80,3 +80,65 @@ def test_direct_solution_converges_to_the_exact_flux():
         errs.append(np.abs(qh - q).max() / np.abs(q).max())
     assert errs[0] / errs[1] > 4 and errs[1] / errs[2] > 4, errs
     assert errs[2] < 1e-3, errs
+
+
+def test_exact_kbar_is_pi_on_the_circle_at_any_separation():
+    """The exact evaluation of the near terms keeps the circle's closed form
+    Kbar = pi down to separations where the FP64 formula has lost every digit."""
+    from fractions import Fraction
+    c = synth.circle(0.5)
+    s = Fraction(3, 7)
+    for h in (Fraction(1, 10 ** 12), Fraction(1, 3 * 10 ** 7), Fraction(-1, 10 ** 5), Fraction(1, 40)):
+        assert abs(direct.kbar_exact(c, s, s + h) - math.pi) < 1e-15
+    # across the period
+    assert abs(direct.kbar_exact(c, Fraction(0), Fraction(-1, 10 ** 9) + 1) - math.pi) < 1e-15
+
+
+@pytest.mark.parametrize("curve", [synth.star(3), synth.ellipse_bspline(), synth.ellipse_bspline_nonuniform(2)],
+                         ids=["star", "ellipse", "ellipse-nonuniform-knots"])
+def test_exact_kbar_limit_is_half_the_curvature_term(curve):
+    """As t -> s, f(t) - f(s) = f' h + f'' h^2 / 2 + O(h^3), so Kbar tends to
+    (f' x f'') / (2 |f'|^2) (the curvature times J / 2), with an O(h) remainder:
+    the exact evaluation at h = 1e-9 against f'' from scipy's B-spline
+    derivative or a central difference of the FP64 first derivative."""
+    from fractions import Fraction
+    rng = np.random.default_rng(11)
+    for s in rng.random(6):
+        sf = Fraction(float(s))
+        d = 1e-5
+        x, y, dx, dy, _ = curves.evaluate(curve, np.array([s]))
+        ddx = (curves.evaluate(curve, np.array([s + d]))[2] - curves.evaluate(curve, np.array([s - d]))[2]) / (2 * d)
+        ddy = (curves.evaluate(curve, np.array([s + d]))[3] - curves.evaluate(curve, np.array([s - d]))[3]) / (2 * d)
+        lim = float(((dx * ddy - dy * ddx) / (2 * (dx * dx + dy * dy)))[0])
+        ke = direct.kbar_exact(curve, sf, sf + Fraction(1, 10 ** 9))
+        assert abs(ke - lim) < 1e-6 * max(1.0, abs(lim)), (s, ke, lim)
+
+
+def test_exact_kbar_meets_fp64_away_from_the_node():
+    """Where FP64 does not cancel (separations of a few hundredths) the exact
+    evaluation and the FP64 formula agree to rounding."""
+    from fractions import Fraction
+    for curve in (synth.star(5), synth.ellipse_bspline()):
+        for s, h in ((Fraction(1, 3), Fraction(1, 40)), (Fraction(5, 9), Fraction(-3, 100)), (Fraction(0), Fraction(1, 25))):
+            t = s + h
+            kd = float(direct.kbar(curve, np.array(float(s)), np.array(float(t % 1))))
+            assert abs(direct.kbar_exact(curve, s, t) - kd) < 1e-13 * abs(kd)
+
+
+def test_near_window_holds_every_term_fp64_cannot_carry():
+    """Tiny case, every term exact (brute force): the inner sums with only the
+    window exact match it to rounding, i.e. the terms left in FP64 carry no
+    visible cancellation error."""
+    from fractions import Fraction
+    curve, N, R, G = synth.star(7), 12, 1, 4
+    g = synth.g_exp_cos
+    v = direct.inner_sums(curve, N, R, G, g)
+    t2, wt = direct.gauss_points(N, G)
+    x2, y2 = curves.evaluate(curve, t2)[:2]
+    coef = wt * g(x2, y2)
+    u = 0.5 * (np.polynomial.legendre.leggauss(G)[0] + 1.0)
+    for n in range(2 * R * N):
+        s = Fraction(n, 2 * R * N)
+        exact = sum(coef[e * G + q] * direct.kbar_exact(curve, s, (e + Fraction(float(u[q]))) / N)
+                    for e in range(N) for q in range(G))
+        assert abs(v[n] - exact) < 1e-14 * max(1.0, abs(exact)), (n, v[n], exact)
