@@ -101,12 +101,19 @@ def _exact_point(curve, t):
     return x, y, dx, dy
 
 
-def kbar_exact(curve, s, t) -> float:
+def kbar_exact(curve, s, t, cache=None) -> float:
     """Kbar(s, t) for exact rational parameters s != t (mod 1), evaluated exactly
-    (B-spline geometry) or with 50 digits (polar curves), then rounded."""
+    (B-spline geometry) or with 50 digits (polar curves), then rounded.  cache:
+    an optional dict of exact points by parameter."""
+    def point(u):
+        if cache is None:
+            return _exact_point(curve, u)
+        if u not in cache:
+            cache[u] = _exact_point(curve, u)
+        return cache[u]
     with mpmath.workdps(50):
-        x1, y1 = _exact_point(curve, s)[:2]
-        x2, y2, dx2, dy2 = _exact_point(curve, t)
+        x1, y1 = point(s)[:2]
+        x2, y2, dx2, dy2 = point(t)
         ax, ay = x2 - x1, y2 - y1
         return float((ax * dy2 - ay * dx2) / (ax * ax + ay * ay))
 
@@ -148,6 +155,7 @@ def inner_sums(curve, N: int, R: int, G: int, g, rows=None) -> np.ndarray:
         v[c0:c0 + 256] = K @ coef
     # the near terms, exactly: replace the FP64 value of each by the exact one
     u = 0.5 * (np.polynomial.legendre.leggauss(G)[0] + 1.0)
+    cache = {}
     for i, n in enumerate(rows):
         s = Fraction(int(n), 2 * R * N)
         for e in near_window(int(n), N, R):
@@ -157,7 +165,7 @@ def inner_sums(curve, N: int, R: int, G: int, g, rows=None) -> np.ndarray:
                 ax = x2[k] - x1[i]
                 ay = y2[k] - y1[i]
                 Kd = (ax * dy2[k] - ay * dx2[k]) / (ax * ax + ay * ay)
-                v[i] += coef[k] * (kbar_exact(curve, s, t) - Kd)
+                v[i] += coef[k] * (kbar_exact(curve, s, t, cache) - Kd)
     return v
 
 

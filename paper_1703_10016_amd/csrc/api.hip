@@ -1234,11 +1234,14 @@ sgbem_status sgbem_rhs_direct(sgbem_ctx c, const sgbem_curve *curve, sgbem_rules
     double *X1, *Y1, *J1;
     if ((st = geometry(c, cd, nodes, c->geo, X1, Y1, J1))) return st;
     const GridDesc gg = gauss_grid(N, G);
-    GaussW gw;
+    GaussW gw, gu;   // composite weights w_q / N, and the nodes u_q on [0, 1]
     {
         double gx[32], gwt[32];
         gauss_legendre01(G, gx, gwt);
-        for (int q = 0; q < 8; ++q) gw.w[q] = q < G ? gwt[q] / N : 0.0;
+        for (int q = 0; q < 8; ++q) {
+            gw.w[q] = q < G ? gwt[q] / N : 0.0;
+            gu.w[q] = q < G ? gx[q] : 0.0;
+        }
     }
     const int nn = nodes.npts, np = gg.npts;
     const int nchunk = dl_chunks(nn, np);
@@ -1251,6 +1254,7 @@ sgbem_status sgbem_rhs_direct(sgbem_ctx c, const sgbem_curve *curve, sgbem_rules
     const KernelEvents *kev;
     if ((st = timing_events(c, ke, kev))) return st;
     HIPCHK(launch_dl_sweep(nn, X1, Y1, np, X2, Y2, DX2, DY2, coef, nchunk, part, c->stream, kev));
+    HIPCHK(launch_dl_near(cd, N, 2 * r->R, G, gu, nn, X1, Y1, X2, Y2, DX2, DY2, coef, part, c->stream));
     HIPCHK(launch_dl_reduce(nn, nchunk, part, d_g_nodes, h, d_b2 ? v : nullptr, c->stream));
     HIPCHK(launch_rhs(N, nn, 2 * r->R, 1, r->Q, r->d_w0, 1.0, J1, h, d_F, c->stream));
     if (d_b2) HIPCHK(launch_rhs(N, nn, 2 * r->R, 1, r->Q, r->d_w0, 1.0, J1, v, d_b2, c->stream));

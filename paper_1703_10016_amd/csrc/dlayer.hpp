@@ -21,5 +21,10 @@ hipError_t launch_dl_sweep(int nn, const double *X1, const double *Y1, int np, c
                            hipStream_t s, const KernelEvents *ev);
 hipError_t launch_dl_reduce(int nn, int nchunk, const double *part, const double *g, double *h, double *vout,
                             hipStream_t s);
+// part[n] += the near Gauss points' terms evaluated without cancellation minus the
+// sweep's values of them (nodes n / P1 per element, gu.w[q] the Gauss nodes on [0, 1]).
+hipError_t launch_dl_near(const CurveDev &c, int N, int P1, int G, const GaussW &gu, int nn, const double *X1,
+                          const double *Y1, const double *X2, const double *Y2, const double *DX2, const double *DY2,
+                          const double *coef, double *part, hipStream_t s);
 
 }  // namespace sgbem
