@@ -626,6 +626,7 @@ sgbem_status sgbem_ctx_destroy(sgbem_ctx c)
     }
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     if (c->hbuf) (void)hipHostFree(c->hbuf);
+    lookahead_free(c->lookahead);
     delete c;
     return SGBEM_OK;
 }
@@ -1512,6 +1513,7 @@ sgbem_status sgbem_solve(sgbem_ctx c, int32_t N, const void *d_A, int64_t lda, i
     SolveResult res;
     std::string msg;
     const int rc = mixed_solve(N, d_A, lda, a_prec, d_beta, d_x, tol, max_iter, c->solve_ws.ptr, c->hbuf, c->stream,
+                               &c->lookahead,
                                res, msg);
     if (info) {
         info->iters = res.iters;

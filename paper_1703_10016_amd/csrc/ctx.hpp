@@ -97,6 +97,8 @@ struct sgbem_ctx_s {
     uint64_t held = 0, budget = 0;
     // pinned host buffer the solve's kernels write their results to (made on first use)
     double *hbuf = nullptr;
+    // the solve's second stream and events beyond N = 4096 (made on first use)
+    void *lookahead = nullptr;
     sgbem::DevBuf geo, geo16, nearL, params, solve_ws, dl;
     std::vector<sgbem_rules_s *> rules;
     std::vector<sgbem_batch_s *> batches;

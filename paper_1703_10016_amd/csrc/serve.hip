@@ -316,7 +316,7 @@ sgbem_completion run(sgbem_server s, Worker &w, Req *q)
         if (st == SGBEM_OK) {
             SolveResult res;
             st = sgbem_status(mixed_solve(N, dA, N, prec, dbeta, dx, s->cfg.tol, s->cfg.max_iter, dws, w.ctx->hbuf,
-                                          w.stream, res, msg));
+                                          w.stream, &w.ctx->lookahead, res, msg));
             c.iters = res.iters;
             c.backward_err = res.backward_err;
             if (st == SGBEM_OK || st == SGBEM_E_NOCONV) {

@@ -2152,36 +2152,51 @@ void update_sym_region(int N, float *LU, int r0, int c0, int cend, int kb, int k
                            ntc, ntiles, per);
 }
 
-// The second stream and events of the look-ahead, one set per host thread and
-// device (each serving thread keeps its own), made on first use and kept for
-// the life of the process.  nullptr if they cannot be made: the updates then
-// all go to the caller's stream, in the same order.
+}  // namespace
+
+// The second stream and events of the look-ahead (default priority), owned by
+// the caller's context: made on the first factorisation that uses them, kept
+// until lookahead_free.
 struct LookAhead {
     hipStream_t aux = nullptr;
     hipEvent_t ev_panel = nullptr, ev_rest[2] = {nullptr, nullptr};
-    bool ready = false;
 };
 
-LookAhead *look_ahead_resources()
+void lookahead_free(void *p)
 {
-    constexpr int kMaxDevices = 16;
-    static thread_local LookAhead la[kMaxDevices];
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
-    LookAhead &r = la[dev];
-    if (!r.ready) {
-        if (hipStreamCreateWithFlags(&r.aux, hipStreamNonBlocking) != hipSuccess) return nullptr;
-        if (hipEventCreateWithFlags(&r.ev_panel, hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&r.ev_rest[0], hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&r.ev_rest[1], hipEventDisableTiming) != hipSuccess)
-            return nullptr;
-        r.ready = true;
+    LookAhead *la = static_cast<LookAhead *>(p);
+    if (!la) return;
+    if (la->aux) (void)hipStreamSynchronize(la->aux);
+    for (hipEvent_t e : {la->ev_panel, la->ev_rest[0], la->ev_rest[1]})
+        if (e) (void)hipEventDestroy(e);
+    if (la->aux) (void)hipStreamDestroy(la->aux);
+    delete la;
+}
+
+namespace {
+// The caller's look-ahead resources (made in *slot on first use, on the
+// current device); nullptr if they cannot be made: the updates then all go to
+// the caller's stream, in the same order.
+LookAhead *lookahead_get(void **slot)
+{
+    if (!slot) return nullptr;
+    if (*slot) return static_cast<LookAhead *>(*slot);
+    LookAhead *la = new LookAhead;
+    if (hipStreamCreateWithFlags(&la->aux, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&la->ev_panel, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&la->ev_rest[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&la->ev_rest[1], hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        lookahead_free(la);
+        return nullptr;
     }
-    return &r;
+    *slot = la;
+    return la;
 }
 }  // namespace
 
-hipError_t lu_factor_f32(int N, float *LU, int *piv, int *info, void *diag_inv, bool pivot, hipStream_t s)
+hipError_t lu_factor_f32(int N, float *LU, int *piv, int *info, void *diag_inv, bool pivot, hipStream_t s,
+                         void **lookahead)
 {
     // Without pivoting (pivot false, N <= 16384, diag_inv required): blocked LU
     // in 64-column blocks up to N = 4096, 256-column blocks of four 64-column
@@ -2241,7 +2256,7 @@ hipError_t lu_factor_f32(int N, float *LU, int *piv, int *info, void *diag_inv, 
         // in as D L^T for the triangular solves.
         float *DI = static_cast<float *>(diag_inv);
         const bool sym = N % 4 == 0;
-        LookAhead *la = look_ahead_resources();
+        LookAhead *la = lookahead_get(lookahead);
         hipStream_t aux = la ? la->aux : s;
         bool aux_used = false;
         int b = 0;
@@ -2395,7 +2410,8 @@ hipError_t gj_inverse(int N, const void *A, int64_t lda, int a_prec, const WS &w
 }  // namespace
 
 int mixed_solve(int N, const void *d_A, int64_t lda, int a_prec, const double *d_beta, double *d_x, double tol,
-                int max_iter, void *ws_base, double *hbuf, hipStream_t s, SolveResult &res, std::string &msg)
+                int max_iter, void *ws_base, double *hbuf, hipStream_t s, void **lookahead, SolveResult &res,
+                std::string &msg)
 {
     WS w = carve(ws_base, N);
     double *ctl = w.red + 40;
@@ -2516,7 +2532,7 @@ int mixed_solve(int N, const void *d_A, int64_t lda, int a_prec, const double *d
                 else if (vec) hipLaunchKernelGGL((copy_rows_kernel<float, true>), rg, dim3(256), 0, s, N, A32, lda, w.LU);
                 else hipLaunchKernelGGL((copy_rows_kernel<float, false>), rg, dim3(256), 0, s, N, A32, lda, w.LU);
             }
-            if ((e = lu_factor_f32(N, w.LU, w.piv, w.info, w.DI, pivot, s)) != hipSuccess)
+            if ((e = lu_factor_f32(N, w.LU, w.piv, w.info, w.DI, pivot, s, lookahead)) != hipSuccess)
                 return fail(-5, "LU factorisation launch", e);
             // the triangular solves' inverted blocks: 1024-row super-blocks beyond
             // kGJMaxN, pairs of 64-row blocks below
