@@ -67,58 +67,17 @@ __device__ __forceinline__ double log_tab64(double x, const double2 *tab)
     return fma(ed, ln2_hi, cl.y + fma(ed, ln2_lo, fma(q, r * r, r)));
 }
 
-// FP64 natural logarithm without tables: x = 2^e m, m in [sqrt(1/2), sqrt(2)),
-// s = (m - 1)/(m + 1) (|s| <= 0.1716; reciprocal by v_rcp_f64 and one Newton
-// step, quotient corrected once by its residual, which leaves s exact to
-// rounding whenever the reciprocal carries more than ~27 bits),
-// log m = 2 atanh(s) = 2 sum_k s^(2k+1)/(2k+1) to k = 10 (first omitted term
-// 2 s^23/23 < 2.2e-19).
-__device__ __forceinline__ double log_atanh64(double x)
-{
-    constexpr double ln2_hi = 0.69314718036912381649017333984375;   // ln 2 truncated to 32 fraction bits
-    constexpr double ln2_lo = 1.9082149292705877000220e-10;         // ln 2 - ln2_hi
-    int e = __builtin_amdgcn_frexp_exp(x);
-    double m = __builtin_amdgcn_frexp_mant(x);               // [1/2, 1)
-    const bool lo = m < 0.70710678118654752440;
-    m = lo ? 2.0 * m : m;
-    e = lo ? e - 1 : e;
-    const double num = m - 1.0, den = m + 1.0;
-    double r = __builtin_amdgcn_rcp(den);
-    r = fma(r, fma(-den, r, 1.0), r);
-    double s = num * r;
-    s = fma(r, fma(-s, den, num), s);
-    const double s2 = s * s;
-    double p = 1.0 / 21.0;
-    p = fma(p, s2, 1.0 / 19.0);
-    p = fma(p, s2, 1.0 / 17.0);
-    p = fma(p, s2, 1.0 / 15.0);
-    p = fma(p, s2, 1.0 / 13.0);
-    p = fma(p, s2, 1.0 / 11.0);
-    p = fma(p, s2, 1.0 / 9.0);
-    p = fma(p, s2, 1.0 / 7.0);
-    p = fma(p, s2, 1.0 / 5.0);
-    p = fma(p, s2, 1.0 / 3.0);
-    const double t = 2.0 * s;
-    const double lm = fma(t * s2, p, t);
-    const double ed = double(e);
-    return fma(ed, ln2_hi, fma(ed, ln2_lo, lm));
-}
-
 // Logarithm of the kernel sweep (choices measured on MI355X): FP64 uses the
 // table-driven log above (a 64-entry version cost 23 FP64-operation
-// equivalents per log against 41 for the table-free series and 91 for the
+// equivalents per log against 41 for a table-free atanh series and 91 for the
 // device library's log, measured as throughput on independent chains; the
 // 256-entry table shortens the polynomial by three more FMAs); FP32: v_log_f32.
-template <typename Real, bool TableLog>
+template <typename Real>
 __device__ __forceinline__ Real k_log(Real x, const double2 *tab);
 template <>
-__device__ __forceinline__ double k_log<double, true>(double x, const double2 *tab) { return log_tab64(x, tab); }
+__device__ __forceinline__ double k_log<double>(double x, const double2 *tab) { return log_tab64(x, tab); }
 template <>
-__device__ __forceinline__ double k_log<double, false>(double x, const double2 *) { return log_atanh64(x); }
-template <>
-__device__ __forceinline__ float k_log<float, true>(float x, const double2 *) { return __logf(x); }
-template <>
-__device__ __forceinline__ float k_log<float, false>(float x, const double2 *) { return __logf(x); }
+__device__ __forceinline__ float k_log<float>(float x, const double2 *) { return __logf(x); }
 
 struct TileArgsF {          // FP32 copies of the per-support coefficients
     float coefA[64];
@@ -265,13 +224,13 @@ __device__ __forceinline__ void tile_body(const Args &a, const ArgsF &af, int bi
                 const int dl = c2 - r + (L - 1);
                 const Real2 iz = sinvz[dl];
                 const Real ratio = fma(J1sq, iz.y, r2 * iz.x);
-                U = k_log<Real, kTableLog>(ratio, ltab);
+                U = k_log<Real>(ratio, ltab);
                 V = swp[dl];
             } else {
                 int de = se2[c2] - e1;
                 if (de < 0) de += N;
                 const bool near = (de == 0) | (de == 1) | (de == N - 1);
-                U = near ? Real(0) : k_log<Real, kTableLog>(r2, ltab);
+                U = near ? Real(0) : k_log<Real>(r2, ltab);
             }
             const Real J2 = sJ2[c2];
             const Real JU = J2 * U, JV = J2 * V;
