@@ -18,6 +18,8 @@ Also measured in the same run (reported beside the headline value):
    over repeated requests;
  * the fused kernel's duration from HIP events on its stream -> roofline;
  * FP32 and FP64 throughput at N = 16384 (a star curve, one assembly each);
+ * a grid of star curves, 8 per point, p in {2, 3, 4} and N in {4096, 16384}:
+   FP32 assembly, then FP32 LU + FP64 refinement of that matrix to 1e-10;
  * the direct formulation's right-hand side (double-layer sweep, eq. final_b2)
    at the workload and at N = 16384;
  * collocation BEM with the same rules at the workload and at N = 16384;
@@ -279,6 +281,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-scale", action="store_true", help="skip the N = 16384 points")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-curve batch")
+    ap.add_argument("--no-stars", action="store_true",
+                    help="skip the star grid (8 curves per p in {2, 3, 4} and N in {4096, 16384}, FP32)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop sweep")
     ap.add_argument("--serve-requests", type=int, default=0,
                     help="requests per arrival rate (0: the rate times --serve-seconds, within [100, 2000])")
@@ -550,6 +554,52 @@ def main():
             del Ab, bb, xb
         torch.cuda.empty_cache()
 
+    # ---------------------------------------------------------------- star grid: 8 curves per (p, N)
+    # FP32 kernel values and contraction (FP64 rule tables), then FP32 LU + FP64
+    # refinement of the FP32 matrix to 1e-10; per point the median assembly
+    # kernel time and the median / max solve time over the curves
+    stars = {}
+    if not args.no_stars:
+        stars = {"curves_per_point": 8, "seeds": "star(idx), idx = 0..7", "precision": "fp32 matrix, fp64 refinement",
+                 "tol": 1e-10, "points": []}
+        for Ng in (4096, 16384):
+            Ag = torch.empty((Ng, Ng), dtype=torch.float32, device="cuda")
+            for pg in (2, 3, 4):
+                kt, st, its, piv, bwd = [], [], [], 0, 0.0
+                for idx in range(8):
+                    crv = synth.star(idx)
+                    ctx.assemble(crv, pg, Ng, "wq", precision="fp32", out=Ag)      # rules, code objects
+                    torch.cuda.synchronize()
+                    S.sgbem_ctx_set_timing(ctx.ctx, 1)
+                    ctx.assemble(crv, pg, Ng, "wq", precision="fp32", out=Ag)
+                    tms, c2 = S.sgbem_ctx_kernel_time(ctx.ctx)
+                    S.sgbem_ctx_set_timing(ctx.ctx, 0)
+                    kt.append(tms / c2)
+                    bg = ctx.rhs(crv, pg, Ng, g, method="wq")
+                    if idx == 0:
+                        ctx.solve(Ag, bg, tol=1e-10, max_iter=30)               # workspace, code objects
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    xg, sg = ctx.solve(Ag, bg, tol=1e-10, max_iter=30)
+                    torch.cuda.synchronize()
+                    st.append((time.perf_counter() - t0) * 1e3)
+                    its.append(int(sg.iters))
+                    piv += int(sg.pivoted)
+                    bwd = max(bwd, float(sg.backward_err))
+                    del xg, bg
+                km = float(np.median(kt))
+                pt = {"p": pg, "N": Ng, "assembly_kernel_ms_median": round(km, 4),
+                      "entries_per_s": Ng * Ng / (km * 1e-3),
+                      "tflops": Ng * (Ng + 1) / 2 * wq_flops_per_entry(pg, 1) / (km * 1e-3) / 1e12,
+                      "solve_ms_median": round(float(np.median(st)), 3), "solve_ms_max": round(max(st), 3),
+                      "refinement_steps": its, "pivoted": piv, "max_backward_err": bwd}
+                stars["points"].append(pt)
+                log(f"[bench] stars p={pg} N={Ng} (8 curves, FP32): assembly {km:.3f} ms median, solve "
+                    f"{pt['solve_ms_median']:.1f} ms median / {pt['solve_ms_max']:.1f} max, steps {its}, pivoted {piv}, "
+                    f"backward err <= {bwd:.1e}")
+            del Ag
+            torch.cuda.empty_cache()
+
     # ---------------------------------------------------------------- direct formulation: double-layer sweep
     direct_rhs = {}
     if not args.no_scale:
@@ -744,6 +794,7 @@ def main():
                      "kernel": "fused WQ sweep-and-contract (FP64)", "kernel_us": kern_ms * 1e3,
                      "flops_per_launch": flops},
         "scale_N16384": scale,
+        "stars_grid": stars,
         "fp32_fast_form": fp32,
         "direct_rhs": direct_rhs,
         "collocation": colloc,

@@ -439,15 +439,17 @@ sgbem_status sgbem_batch_free(sgbem_ctx ctx, sgbem_batch batch);
  * Solve A x = beta (eq. sistlin) for one N x N matrix on the device.
  * A is LU-factorised in FP32; x is then refined in FP64: r = beta - A x with
  * A as stored (FP64 or FP32 widened), d = LU \ r in FP32, x += d, until
- * ||d||_inf <= tol ||x||_inf or max_iter steps (or the corrections stop
- * shrinking with the backward error at the FP64 rounding level).
+ * ||d||_inf <= tol ||x||_inf or max_iter steps (or a correction does not
+ * halve with the backward error at the FP64 rounding level).
  * Factorisation: an exactly symmetric A with N <= 16384 (the Galerkin matrix,
  * positive definite in the paper's setting, eq. sistlin) is first factored
  * without row interchanges, which is stable for a positive definite matrix;
  * that attempt is kept only if the refinement converges.  A zero pivot or a
- * stalled refinement (possible when the curve's logarithmic capacity exceeds
- * 1 and A is indefinite) means a refactorisation with partial pivoting, which
- * every other matrix gets from the start.  info->pivoted says which was used.
+ * stalled refinement (above the FP64 level a correction that does not shrink,
+ * or two in a row that do not halve; possible when the curve's logarithmic
+ * capacity is near or above 1 and A is nearly singular or indefinite) means a
+ * refactorisation with partial pivoting, which every other matrix gets from
+ * the start.  info->pivoted says which was used.
  *  d_A:     device, row-major, lda, FP64 or FP32 per a_prec; not modified.
  *  d_beta:  device [N] FP64.    d_x: device [N] FP64 (output).
  *  info:    host, may be NULL; written before return (the call synchronises).

@@ -48,7 +48,9 @@ int padded64(int N) { return (N + 63) / 64 * 64; }
 //  [0] max |A_ij - A_ji|   [1] ||A||_inf   [2] previous ||d|| / ||x||   [3] stop reason
 //  (0 running, 1 converged, 2 stalled, 3 not finite, 4 zero pivot, 5 not symmetric)
 //  [4] steps taken   [5] last ||d|| / ||x||   [6] last backward error
-enum { CTL_ASYM = 0, CTL_NORMA = 1, CTL_PREV = 2, CTL_STOP = 3, CTL_ITERS = 4, CTL_REL = 5, CTL_BWD = 6, CTL_SIZE = 8 };
+//  [7] 1 when the last correction did not halve (the first slow step)
+enum { CTL_ASYM = 0, CTL_NORMA = 1, CTL_PREV = 2, CTL_STOP = 3, CTL_ITERS = 4, CTL_REL = 5, CTL_BWD = 6, CTL_SLOW = 7,
+       CTL_SIZE = 8 };
 
 // True when a batched refinement has stopped (or the matrix is not symmetric):
 // the remaining kernels of the batch return at once.
@@ -1899,10 +1901,11 @@ __device__ __forceinline__ double nan_max(double a, double b) { return (a > b ||
 // x += d (d FP32), and max-norms: red[0] = |d|_inf, red[1] = |x|_inf, red[2] = |r|_inf, red[3] = |beta|_inf.
 // With a control block (batched refinement): nothing once stopped; otherwise
 // the step's decision, taken as the host would: converged when
-// ||d|| <= tol ||x||, or when the corrections stop shrinking
+// ||d|| <= tol ||x||, or when a correction does not halve
 // (||d|| > ||d_prev|| / 2) with the backward error at the FP64 level; stalled
-// when they stop shrinking above it; not finite on NaN or overflow; a zero
-// pivot (info) or an asymmetric matrix ends the attempt before the first step.
+// above that level when a correction does not shrink at all or two in a row
+// do not halve; not finite on NaN or overflow; a zero pivot (info) or an
+// asymmetric matrix ends the attempt before the first step.
 __global__ __launch_bounds__(1024) void update_norms_kernel(int N, double *x, const float *d, const double *r,
                                                             const double *beta, int add, double *red, double *ctl,
                                                             const int *info, double tol)
@@ -1939,10 +1942,17 @@ __global__ __launch_bounds__(1024) void update_norms_kernel(int N, double *x, co
             const double dn = s[0][0], xn = s[1][0], rn = s[2][0], bn = s[3][0];
             const double rel = dn == 0.0 ? 0.0 : dn / xn;
             const double bwd = rn / (ctl[CTL_NORMA] * xn + bn);   // of the iterate before this step
-            double stop = 0.0;
-            if (rel <= tol) stop = 1.0;
-            else if (rel > 0.5 * ctl[CTL_PREV]) stop = bwd <= 64 * 1.1102230246251565e-16 ? 1.0 : 2.0;
-            else if (!(rel < 1e300)) stop = 3.0;
+            double stop = 0.0, slow = 0.0;
+            if (rel <= tol) {
+                stop = 1.0;
+            } else if (rel > 0.5 * ctl[CTL_PREV]) {
+                if (bwd <= 64 * 1.1102230246251565e-16) stop = 1.0;
+                else if (rel >= ctl[CTL_PREV] || ctl[CTL_SLOW] != 0.0) stop = 2.0;
+                else slow = 1.0;
+            } else if (!(rel < 1e300)) {
+                stop = 3.0;
+            }
+            ctl[CTL_SLOW] = slow;
             ctl[CTL_ITERS] += 1.0;
             ctl[CTL_REL] = rel;
             ctl[CTL_BWD] = bwd;
@@ -1987,6 +1997,7 @@ __global__ void ctl_init_kernel(double *ctl)
         ctl[CTL_ITERS] = 0.0;
         ctl[CTL_REL] = 1.0;
         ctl[CTL_BWD] = 1.0;
+        ctl[CTL_SLOW] = 0.0;
     }
 }
 
@@ -2582,12 +2593,13 @@ int mixed_solve(int N, const void *d_A, int64_t lda, int a_prec, const double *d
         res.pivoted = pivot;
         int status = -4;
         double prev = 1e300;
-        // Refinement: stop when ||d|| <= tol ||x||, or when the corrections stop
-        // shrinking (||d_k|| > ||d_{k-1}|| / 2: the FP64 residual has reached the
+        // Refinement: stop when ||d|| <= tol ||x||, or when a correction does
+        // not halve (||d_k|| > ||d_{k-1}|| / 2: the FP64 residual has reached the
         // cond(A) eps floor) with a backward error at the FP64 level.  Without
-        // pivoting, corrections that stop shrinking above that level end the
-        // attempt.
-        bool stalled = false, zero_pivot = false;
+        // pivoting, above that level a correction that does not shrink at all,
+        // or two in a row that do not halve, end the attempt (one slow step
+        // alone is the ordinary scatter of a slowly contracting refinement).
+        bool stalled = false, zero_pivot = false, slow = false;
         for (int it = 0; it < max_iter; ++it) {
             residual();
             apply(w.r);
@@ -2617,10 +2629,13 @@ int mixed_solve(int N, const void *d_A, int64_t lda, int a_prec, const double *d
                     status = 0;
                     break;
                 }
-                if (!pivot) {
+                if (!pivot && (res.rel_update >= prev || slow)) {
                     stalled = true;
                     break;
                 }
+                slow = true;
+            } else {
+                slow = false;
             }
             if (!(res.rel_update < 1e300)) {   // NaN or overflow: no convergence from here
                 if (!pivot) stalled = true;
