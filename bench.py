@@ -82,6 +82,40 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def write_traffic(fetch_csv: str, write_csv: str) -> None:
+    """HBM bytes per launch of the fused kernel from two counter runs of
+    `--profile-run`: each counter (KiB per dispatch) is scaled by the ratio of the
+    256 MiB that the run's copy kernel moves to what the counter reads for it."""
+    import csv
+    copy_kib = 32 * 1024 * 1024 * 8 / 1024.0
+
+    def per_dispatch(path, counter):
+        vals = {}
+        for r in csv.DictReader(open(path)):
+            if r.get("Counter_Name") != counter:
+                continue
+            key = (r["Dispatch_Id"], r["Kernel_Name"])
+            vals[key] = vals.get(key, 0.0) + float(r["Counter_Value"])
+        fused = [v for (d, n), v in vals.items() if "tile_kernel<2, 7, 1, true, double, double" in n]
+        # the copy is the run's last dispatch (the fill of its source, before it, writes as much)
+        big = sorted((int(d), v) for (d, n), v in vals.items() if "tile_kernel" not in n and v > 0.25 * copy_kib)
+        if not fused or not big:
+            raise SystemExit(f"{path}: {len(fused)} fused dispatches, no 256 MiB copy")
+        return sum(fused) / len(fused), big[-1][1]
+
+    f_kib, f_copy = per_dispatch(fetch_csv, "FETCH_SIZE")
+    w_kib, w_copy = per_dispatch(write_csv, "WRITE_SIZE")
+    fs, ws = copy_kib / f_copy, copy_kib / w_copy
+    out = {"bytes_per_launch": (f_kib * fs + w_kib * ws) * 1024.0, "fetch_kib_scaled": f_kib * fs,
+           "write_kib_scaled": w_kib * ws, "fetch_scale": fs, "write_scale": ws,
+           "fetch_kib_raw": f_kib, "write_kib_raw": w_kib, "copy_fetch_kib_raw": f_copy, "copy_write_kib_raw": w_copy,
+           "source_hash": kernel_source_hash()}
+    path = os.path.join(ROOT, "profiles", "wq_fp64_ellipse_N1024_traffic.json")
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out))
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -296,9 +330,16 @@ def main():
                          "(the copy calibrates the byte counters of a profiler run)")
     ap.add_argument("--profile-n", type=int, default=0,
                     help="with --profile-run: assemble the star curve (p = 3) at this N instead of the workload")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"), default=None,
+                    help="no GPU work: turn the counter CSVs of two profiler runs of --profile-run (FETCH_SIZE, "
+                         "then WRITE_SIZE) into profiles/wq_fp64_ellipse_N1024_traffic.json, scaling each "
+                         "counter by what it reads for the run's 256 MiB copy")
     ap.add_argument("--profile-solve", type=int, default=0,
                     help="profiling only: assemble the star curve (p = 3) at this N in FP32 and solve it W + K times")
     args = ap.parse_args()
+    if args.traffic_from:
+        write_traffic(*args.traffic_from)
+        return
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: there is no multi-GPU path (the matrix would be "
               "sharded by row blocks of tiles, each GPU assembling and factoring its own rows).",
