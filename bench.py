@@ -82,7 +82,7 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def write_traffic(fetch_csv: str, write_csv: str) -> None:
+def write_traffic(fetch_csv: str, write_csv: str, path: str | None = None) -> dict:
     """HBM bytes per launch of the fused kernel from two counter runs of
     `--profile-run`: each counter (KiB per dispatch) is scaled by the ratio of the
     256 MiB that the run's copy kernel moves to what the counter reads for it."""
@@ -110,10 +110,11 @@ def write_traffic(fetch_csv: str, write_csv: str) -> None:
            "write_kib_scaled": w_kib * ws, "fetch_scale": fs, "write_scale": ws,
            "fetch_kib_raw": f_kib, "write_kib_raw": w_kib, "copy_fetch_kib_raw": f_copy, "copy_write_kib_raw": w_copy,
            "source_hash": kernel_source_hash()}
-    path = os.path.join(ROOT, "profiles", "wq_fp64_ellipse_N1024_traffic.json")
+    path = path or os.path.join(ROOT, "profiles", "wq_fp64_ellipse_N1024_traffic.json")
     with open(path, "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps(out))
+    return out
 
 
 def log(msg):
