@@ -27,9 +27,21 @@ __global__ void batch_geometry_kernel(const CurveDev *curves, const int *npts, c
     eval_curve(curves[b], t, X[n], X[np + n], X[2 * np + n]);
 }
 
+// Dynamic LDS of the batch kernel: the largest of the tile variants it inlines,
+// which share it (static arrays would give each variant its own).
+template <typename Real, int T>
+constexpr size_t batch_lds_bytes()
+{
+    const size_t a = TileLds<2, 5, true, Real, T>::bytes(), b = TileLds<2, 7, true, Real, T>::bytes(),
+                 c = TileLds<2, 9, true, Real, T>::bytes();
+    return a > b ? (a > c ? a : c) : (b > c ? b : c);
+}
+
+// FP32: at least 6 waves per SIMD, as for the single-matrix FP32 instances (left
+// alone the compiler hoists the sweep's loads into many more registers).
 template <typename Real, int T, int S>
-__global__ __launch_bounds__(256) void batch_tile_kernel(const TileArgs *args, const TileArgsF *argsf, const int *deg,
-                                                         const int *prefix, int n, int total)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 ? 6 : 1, 8))) void
+batch_tile_kernel(const TileArgs *args, const TileArgsF *argsf, const int *deg, const int *prefix, int n, int total)
 {
     for (int t = blockIdx.x; t < total; t += gridDim.x) {
         int lo = 0, hi = n - 1;
@@ -45,9 +57,9 @@ __global__ __launch_bounds__(256) void batch_tile_kernel(const TileArgs *args, c
         int bi, bj;
         tile_coords(nb, t - prefix[b], bi, bj);
         switch (deg[b]) {   // n_ref = 1: P = 2 nodes per element, Q = 2p + 1 support nodes
-        case 2: tile_body<2, 5, 1, true, Real, Real, T, S>(a, af, bi, bj); break;
-        case 3: tile_body<2, 7, 1, true, Real, Real, T, S>(a, af, bi, bj); break;
-        default: tile_body<2, 9, 1, true, Real, Real, T, S>(a, af, bi, bj); break;
+        case 2: tile_body<2, 5, 1, true, Real, Real, T, S, true>(a, af, bi, bj); break;
+        case 3: tile_body<2, 7, 1, true, Real, Real, T, S, true>(a, af, bi, bj); break;
+        default: tile_body<2, 9, 1, true, Real, Real, T, S, true>(a, af, bi, bj); break;
         }
     }
 }
@@ -63,11 +75,12 @@ namespace {
 template <typename Real, int T, int S>
 hipError_t launch_one(const BatchDev &d, int cfg, int n, int total, int grid, hipStream_t s, const KernelEvents *ev)
 {
+    constexpr size_t lds = batch_lds_bytes<Real, T>();
     if (ev)
-        hipExtLaunchKernelGGL((batch_tile_kernel<Real, T, S>), dim3(grid), dim3(256), 0, s, ev->start, ev->stop, 0,
+        hipExtLaunchKernelGGL((batch_tile_kernel<Real, T, S>), dim3(grid), dim3(256), lds, s, ev->start, ev->stop, 0,
                               d.args, d.argsf, d.deg, d.prefix[cfg], n, total);
     else
-        hipLaunchKernelGGL((batch_tile_kernel<Real, T, S>), dim3(grid), dim3(256), 0, s, d.args, d.argsf, d.deg,
+        hipLaunchKernelGGL((batch_tile_kernel<Real, T, S>), dim3(grid), dim3(256), lds, s, d.args, d.argsf, d.deg,
                            d.prefix[cfg], n, total);
     return hipGetLastError();
 }
@@ -75,7 +88,9 @@ template <typename Real, int T, int S>
 int occupancy_one()
 {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_tile_kernel<Real, T, S>, 256, 0) != hipSuccess) nb = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_tile_kernel<Real, T, S>, 256, batch_lds_bytes<Real, T>()) !=
+        hipSuccess)
+        nb = 1;
     return nb < 1 ? 1 : nb;
 }
 }  // namespace

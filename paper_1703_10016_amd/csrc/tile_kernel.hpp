@@ -110,26 +110,94 @@ __device__ __forceinline__ void tile_coords(int nb, int b, int &bi, int &bj)
     bj = r + (b - (r * nb - (r * (r - 1)) / 2));
 }
 
+// The LDS of one tile: the two node windows, the table slices (WQ) or element
+// indices (plain form), the stage-1 sums and the output tile.
+template <int P, int Q, bool WQ, typename Real, int T>
+struct TileLds {
+    static constexpr int L = P * (T - 1) + Q;     // points in each window
+    static constexpr int LT = 2 * L - 1;          // table slice for n2 - n1
+    static constexpr int TW = (T % 2 == 0) ? T + 2 : T + 1;   // row pitch: even for paired columns
+    using Real2 = typename std::conditional<sizeof(Real) == 8, double2, float2>::type;
+    double *sx1, *sy1, *sx2, *sy2;
+    Real *sJ1, *sJ2;
+    int *se1, *se2;
+    // sinvz[dl] = ((pi / sin(pi d / npts))^2, 1 if d = 0 else 0) of the slice; sw[par * LT + dl]
+    Real2 *sinvz;
+    Real *sw;
+    Real (*C1)[TW];
+    Real (*tileo)[TW];
+    // bytes of the arrays carved one after another, each on 16 bytes
+    static constexpr size_t al(size_t b) { return (b + 15) & ~size_t(15); }
+    static constexpr size_t bytes()
+    {
+        return 4 * al(8 * L) + 2 * al(sizeof(Real) * L) + 2 * al(4 * (WQ ? 1 : L)) + al(sizeof(Real2) * (WQ ? LT : 1)) +
+               al(sizeof(Real) * (WQ ? 2 * LT : 1)) + al(sizeof(Real) * L * TW) + al(sizeof(Real) * T * TW);
+    }
+};
+
+// Where a tile's LDS lives: static arrays per instantiation (a kernel that
+// inlines one tile variant), or, with DYN, the kernel's dynamic LDS, which every
+// variant a kernel inlines then shares (the launch gives TileLds::bytes() of
+// the largest).
+template <int P, int Q, bool WQ, typename Real, int T, bool DYN>
+__device__ __forceinline__ TileLds<P, Q, WQ, Real, T> tile_lds()
+{
+    using M = TileLds<P, Q, WQ, Real, T>;
+    constexpr int L = M::L, LT = M::LT, TW = M::TW;
+    using Real2 = typename M::Real2;
+    M m;
+    if constexpr (DYN) {
+        extern __shared__ __align__(16) char tile_dyn_lds[];
+        char *p = tile_dyn_lds;
+        auto take = [&p](size_t b) { char *q = p; p += M::al(b); return q; };
+        m.sx1 = reinterpret_cast<double *>(take(8 * L));
+        m.sy1 = reinterpret_cast<double *>(take(8 * L));
+        m.sx2 = reinterpret_cast<double *>(take(8 * L));
+        m.sy2 = reinterpret_cast<double *>(take(8 * L));
+        m.sJ1 = reinterpret_cast<Real *>(take(sizeof(Real) * L));
+        m.sJ2 = reinterpret_cast<Real *>(take(sizeof(Real) * L));
+        m.se1 = reinterpret_cast<int *>(take(4 * (WQ ? 1 : L)));
+        m.se2 = reinterpret_cast<int *>(take(4 * (WQ ? 1 : L)));
+        m.sinvz = reinterpret_cast<Real2 *>(take(sizeof(Real2) * (WQ ? LT : 1)));
+        m.sw = reinterpret_cast<Real *>(take(sizeof(Real) * (WQ ? 2 * LT : 1)));
+        m.C1 = reinterpret_cast<Real(*)[TW]>(take(sizeof(Real) * L * TW));
+        m.tileo = reinterpret_cast<Real(*)[TW]>(take(sizeof(Real) * T * TW));
+    } else {
+        __shared__ double sx1[L], sy1[L], sx2[L], sy2[L];
+        __shared__ Real sJ1[L], sJ2[L];
+        __shared__ int se1[WQ ? 1 : L], se2[WQ ? 1 : L];
+        __shared__ Real2 sinvz[WQ ? LT : 1];
+        __shared__ Real sw[WQ ? 2 * LT : 1];
+        __shared__ __align__(16) Real C1[L][TW];
+        __shared__ __align__(16) Real tileo[T][TW];
+        m.sx1 = sx1; m.sy1 = sy1; m.sx2 = sx2; m.sy2 = sy2;
+        m.sJ1 = sJ1; m.sJ2 = sJ2; m.se1 = se1; m.se2 = se2;
+        m.sinvz = sinvz; m.sw = sw; m.C1 = C1; m.tileo = tileo;
+    }
+    return m;
+}
+
 // One T x T tile (bi <= bj) of one matrix: the whole sweep-and-contract.
-template <int P, int Q, int S0, bool WQ, typename Real, typename OutT, int T, int S, typename Args, typename ArgsF>
+template <int P, int Q, int S0, bool WQ, typename Real, typename OutT, int T, int S, bool DYN = false, typename Args,
+          typename ArgsF>
 __device__ __forceinline__ void tile_body(const Args &a, const ArgsF &af, int bi, int bj)
 {
-    constexpr int L = P * (T - 1) + Q;     // points in each window
-    constexpr int LT = 2 * L - 1;          // table slice for n2 - n1
+    using M = TileLds<P, Q, WQ, Real, T>;
+    constexpr int L = M::L;
+    constexpr int LT = M::LT;
     constexpr int NSTRIP = T / S;
     constexpr int W2 = P * (S - 1) + Q;    // n2 points swept by one strip
     static_assert(T % S == 0, "strip must divide tile");
 
-    __shared__ double sx1[L], sy1[L], sx2[L], sy2[L];
-    __shared__ Real sJ1[L], sJ2[L];
-    __shared__ int se1[WQ ? 1 : L], se2[WQ ? 1 : L];
-    // sinvz[dl] = ((pi / sin(pi d / npts))^2, 1 if d = 0 else 0) of the slice; sw[par * LT + dl]
-    using Real2 = typename std::conditional<sizeof(Real) == 8, double2, float2>::type;
-    __shared__ Real2 sinvz[WQ ? LT : 1];
-    __shared__ Real sw[WQ ? 2 * LT : 1];
-    constexpr int TW = (T % 2 == 0) ? T + 2 : T + 1;      // row pitch: even for paired columns
-    __shared__ __align__(16) Real C1[L][TW];
-    __shared__ __align__(16) Real tileo[T][TW];
+    const M m = tile_lds<P, Q, WQ, Real, T, DYN>();
+    double *const sx1 = m.sx1, *const sy1 = m.sy1, *const sx2 = m.sx2, *const sy2 = m.sy2;
+    Real *const sJ1 = m.sJ1, *const sJ2 = m.sJ2;
+    int *const se1 = m.se1, *const se2 = m.se2;
+    using Real2 = typename M::Real2;
+    Real2 *const sinvz = m.sinvz;
+    Real *const sw = m.sw;
+    Real(*const C1)[M::TW] = m.C1;
+    Real(*const tileo)[M::TW] = m.tileo;
     constexpr bool kTableLog = sizeof(Real) == 8;
     double2 *ltab = nullptr;
     if constexpr (kTableLog) {
