@@ -258,39 +258,61 @@ __device__ double kbar_near(const CurveDev &c, double t, double h)
 // and operations.  h from the integer indices: h = (P1 e' - n + P1 u_q) / (P1 N)
 // with e' the element index taken periodically nearest to the node.
 // gu.w[q]: the Gauss nodes u_q on [0, 1] (not the weights).
+// One thread per (node, near Gauss point): a workgroup takes blockDim / (3G)
+// nodes (3G <= 24); the differences meet in LDS and one thread per node adds
+// them in the order (element -1, 0, +1; Gauss point 0 .. G-1).
+__device__ __forceinline__ bool dl_near_skip(int N, int en, int de)
+{
+    if (N < 3 && de == 1 && ((en + 1) % N) == ((en - 1 + N) % N)) return true;   // N = 2: one neighbour
+    return N < 2 && de != 0;
+}
+
 __global__ __launch_bounds__(256) void dl_near_kernel(CurveDev c, int N, int P1, int G, GaussW gu, int nn,
                                                       const double *X1, const double *Y1, const double *X2,
                                                       const double *Y2, const double *DX2, const double *DY2,
                                                       const double *coef, double *part)
 {
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= nn) return;
-    const double x1 = X1[n], y1 = Y1[n];
-    const int en = n / P1;
-    double corr = 0.0;
-    for (int de = -1; de <= 1; ++de) {
-        if (N < 3 && de == 1 && ((en + 1) % N) == ((en - 1 + N) % N)) continue;   // N = 2: one neighbour
-        if (N < 2 && de != 0) continue;
-        const int e = ((en + de) % N + N) % N, ee = en + de;   // periodic index, and its unwrapped position
-        for (int q = 0; q < G; ++q) {
+    __shared__ double diff[256];
+    const int per = 3 * G, npw = int(blockDim.x) / per;
+    const int tid = threadIdx.x, ln = tid / per, it = tid - ln * per;
+    const int n = int(blockIdx.x) * npw + ln;
+    const bool node = ln < npw && n < nn;
+    const int en = node ? n / P1 : 0;
+    if (node) {
+        const int de = it / G - 1, q = it - (it / G) * G;
+        double v = 0.0;
+        if (!dl_near_skip(N, en, de)) {
+            const int e = ((en + de) % N + N) % N, ee = en + de;   // periodic index, and its unwrapped position
             const int k = e * G + q;
-            const double ax = X2[k] - x1, ay = Y2[k] - y1;
+            const double ax = X2[k] - X1[n], ay = Y2[k] - Y1[n];
             const double num = fma(ax, DY2[k], -ay * DX2[k]);
             const double den = fma(ax, ax, ay * ay);
             const double kd = quot(num, den);
             const double t = (double(e) + gu.w[q]) / double(N);
             const double h = (double(P1 * ee - n) + P1 * gu.w[q]) / double(P1 * N);
-            corr += coef[k] * (kbar_near(c, t, h) - kd);
+            v = kbar_near(c, t, h) - kd;
         }
+        diff[tid] = v;
     }
-    part[n] += corr;
+    __syncthreads();
+    if (node && it == 0) {
+        double corr = 0.0;
+        for (int de = -1; de <= 1; ++de) {
+            if (dl_near_skip(N, en, de)) continue;
+            const int e = ((en + de) % N + N) % N;
+            for (int q = 0; q < G; ++q) corr = fma(coef[e * G + q], diff[tid + (de + 1) * G + q], corr);
+        }
+        part[n] += corr;
+    }
 }
 
 hipError_t launch_dl_near(const CurveDev &c, int N, int P1, int G, const GaussW &gu, int nn, const double *X1,
                           const double *Y1, const double *X2, const double *Y2, const double *DX2, const double *DY2,
                           const double *coef, double *part, hipStream_t s)
 {
-    hipLaunchKernelGGL(dl_near_kernel, dim3((nn + 255) / 256), dim3(256), 0, s, c, N, P1, G, gu, nn, X1, Y1, X2, Y2,
+    if (G < 1 || 3 * G > 256) return hipErrorInvalidValue;
+    const int npw = 256 / (3 * G);
+    hipLaunchKernelGGL(dl_near_kernel, dim3((nn + npw - 1) / npw), dim3(256), 0, s, c, N, P1, G, gu, nn, X1, Y1, X2, Y2,
                        DX2, DY2, coef, part);
     return hipGetLastError();
 }
