@@ -72,7 +72,9 @@ __global__ __launch_bounds__(256) void knot_tile_kernel(KnotArgs a)
         double acc[S];
 #pragma unroll
         for (int s = 0; s < S; ++s) acc[s] = 0.0;
-#pragma unroll
+        // not unrolled: each kernel value carries a sine and a division, and the
+        // unrolled sweep held one wavefront per SIMD (380 registers)
+#pragma unroll 1
         for (int k2 = 0; k2 < W2; ++k2) {
             const int c2 = st * S * P + k2;
             const int g2 = sg2[c2];
@@ -84,7 +86,8 @@ __global__ __launch_bounds__(256) void knot_tile_kernel(KnotArgs a)
             // product stays finite (no branch per kernel value around the node loads)
             const bool diag = g2 == g1;
             const double sp = diag ? 1.0 : sinpi(d);
-            const double ratio = fma(r2, (kPiK / sp) * (kPiK / sp), diag ? J1 * J1 : 0.0);
+            const double isp = kPiK / sp;
+            const double ratio = fma(r2, isp * isp, diag ? J1 * J1 : 0.0);
             const double U = 0.5 * log_tab64(ratio, ltab);
             const double V = wsrow[g2];
             const double J2 = sJ2[c2];
