@@ -11,7 +11,11 @@ items with L = P (T - 1) + Q rows; the shape is chosen so that the items fill th
 256 threads in one pass.  Fast form with n_ref = 1, p <= 4: 28 x 28 tiles with
 7-column strips (236..252 items), and in FP64 from N = 4096 an instance compiled
 for at least 4 waves per SIMD (FP32 reaches that occupancy anyway); p = 5, 6: 24 x 24 tiles, 6-column strips (228, 236
-items).  Otherwise the shape that function `shape` scores best.
+items).  FP64 fast form with n_ref = 3, 4: 16 x 16 tiles with 8-column
+strips for p = 2..4 (measured at N = 1024: 1.1-1.5x faster than the scored shapes,
+whose larger tiles held one or two workgroups per CU by LDS and registers; FP32
+and n_ref = 2 gain nothing from it).  Otherwise the shape that function `shape`
+scores best.
 Run from this directory: python gen_instances.py
 """
 import os
@@ -74,6 +78,8 @@ def main():
             fname = f"launch_{tag}_{suf}"
             s = HDR.format(what=what, prec=prec, fname=fname)
             for (p, P, Q, S0, wq, T, S, big) in cases():
+                if tag == "wq" and real == "double" and P >= 6 and 2 <= p <= 4:
+                    T, S = 16, 8
                 k = f"launch_tile<{P}, {Q}, {S0}, {wq}, {real}, {T}, {S}"
                 if big and real == "double":
                     s += f"    case {p * 16 + P}: return a.N >= 4096 ? {k}, 4>(a, s, ev) : {k}>(a, s, ev);\n"
