@@ -43,6 +43,59 @@ __host__ __device__ inline void sin_cos(double x, double *s, double *c)
 #endif
 }
 
+// Periodic B-spline on uniform knots at a compile-time degree D: the same
+// arithmetic as the general branch below, with the de Boor arrays in registers
+// (with a run-time degree they live in scratch).
+template <int D>
+__host__ __device__ __forceinline__ void eval_uniform_periodic(const CurveDev &c, const double *cq, double t, double &x,
+                                                              double &y, double &dx, double &dy)
+{
+    const int nc = c.n_ctrl;
+    const double u = t * nc;
+    int l = int(std::floor(u));
+    if (l >= nc) l = nc - 1;
+    if (l < 0) l = 0;
+    double px[D + 1], py[D + 1];
+#pragma unroll
+    for (int i = 0; i <= D; ++i) {
+        int j = l - D + i;
+        j = ((j % nc) + nc) % nc;
+        px[i] = cq[2 * j];
+        py[i] = cq[2 * j + 1];
+    }
+    double qx[D], qy[D];
+#pragma unroll
+    for (int i = 1; i <= D; ++i) {
+        qx[i - 1] = nc * (px[i] - px[i - 1]);
+        qy[i - 1] = nc * (py[i] - py[i - 1]);
+    }
+#pragma unroll
+    for (int r = 1; r <= D; ++r) {
+#pragma unroll
+        for (int i = D; i >= r; --i) {
+            const int j = l - D + i;
+            const double al = (u - j) / double(D + 1 - r);
+            px[i] = (1.0 - al) * px[i - 1] + al * px[i];
+            py[i] = (1.0 - al) * py[i - 1] + al * py[i];
+        }
+    }
+    x = px[D];
+    y = py[D];
+    constexpr int dd = D - 1;
+#pragma unroll
+    for (int r = 1; r <= dd; ++r) {
+#pragma unroll
+        for (int i = dd; i >= r; --i) {
+            const int j = l - dd + i;
+            const double al = (u - j) / double(dd + 1 - r);
+            qx[i] = (1.0 - al) * qx[i - 1] + al * qx[i];
+            qy[i] = (1.0 - al) * qy[i - 1] + al * qy[i];
+        }
+    }
+    dx = qx[dd];
+    dy = qy[dd];
+}
+
 // f(t) and f'(t)
 __host__ __device__ __forceinline__ void eval_curve_d(const CurveDev &c, double t, double &x, double &y, double &dx,
                                                       double &dy)
@@ -135,6 +188,8 @@ __host__ __device__ __forceinline__ void eval_curve_d(const CurveDev &c, double 
         }
         dx = qx[dd];
         dy = qy[dd];
+    } else if (c.degree == 3) {   // the cubic curves of the workloads
+        eval_uniform_periodic<3>(c, cq, t, x, y, dx, dy);
     } else {
         const int d = c.degree, nc = c.n_ctrl;
         const double u = t * nc;
