@@ -96,6 +96,84 @@ __host__ __device__ __forceinline__ void eval_uniform_periodic(const CurveDev &c
     dy = qy[dd];
 }
 
+// The clamped and non-uniform periodic branches at a compile-time degree D: the
+// same arithmetic as the run-time-degree branch below, arrays in registers.
+template <int D>
+__host__ __device__ __forceinline__ void eval_knots_d(const CurveDev &c, const double *cq, double t, double &x, double &y,
+                                                     double &dx, double &dy)
+{
+    const int nc = c.n_ctrl;
+    const double *tk = c.inline_data ? c.inl + 128 : c.knots;
+    double tau[2 * D + 1], px[D + 1], py[D + 1];   // knots l - D .. l + D and control points l - D .. l
+    int lo, hi;
+    if (c.kind == 2) {
+        lo = D;
+        hi = nc - 1;                  // the span l with T_l <= t < T_{l+1}
+    } else {
+        lo = 0;
+        hi = nc - 1;                  // the span l with tau_l <= t < tau_{l+1}
+    }
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tk[mid] <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    const int l = lo;
+    if (c.kind == 2) {
+#pragma unroll
+        for (int i = 0; i <= 2 * D; ++i) tau[i] = tk[l - D + i];
+#pragma unroll
+        for (int i = 0; i <= D; ++i) {
+            px[i] = cq[2 * (l - D + i)];
+            py[i] = cq[2 * (l - D + i) + 1];
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i <= 2 * D; ++i) {
+            const int k = l - D + i;
+            const int kk = k < 0 ? k + nc : (k >= nc ? k - nc : k);
+            tau[i] = tk[kk] + (k < 0 ? -1.0 : (k >= nc ? 1.0 : 0.0));
+        }
+#pragma unroll
+        for (int i = 0; i <= D; ++i) {
+            int j = l - D + i;
+            j = ((j % nc) + nc) % nc;
+            px[i] = cq[2 * j];
+            py[i] = cq[2 * j + 1];
+        }
+    }
+    double qx[D], qy[D];
+#pragma unroll
+    for (int i = 1; i <= D; ++i) {
+        const double s = D / (tau[i + D] - tau[i]);
+        qx[i - 1] = s * (px[i] - px[i - 1]);
+        qy[i - 1] = s * (py[i] - py[i - 1]);
+    }
+#pragma unroll
+    for (int r = 1; r <= D; ++r) {
+#pragma unroll
+        for (int i = D; i >= r; --i) {
+            const double al = (t - tau[i]) / (tau[i + D + 1 - r] - tau[i]);
+            px[i] = (1.0 - al) * px[i - 1] + al * px[i];
+            py[i] = (1.0 - al) * py[i - 1] + al * py[i];
+        }
+    }
+    x = px[D];
+    y = py[D];
+    constexpr int dd = D - 1;
+#pragma unroll
+    for (int r = 1; r <= dd; ++r) {
+#pragma unroll
+        for (int i = dd; i >= r; --i) {
+            const double al = (t - tau[i + 1]) / (tau[i + 1 + dd + 1 - r] - tau[i + 1]);
+            qx[i] = (1.0 - al) * qx[i - 1] + al * qx[i];
+            qy[i] = (1.0 - al) * qy[i - 1] + al * qy[i];
+        }
+    }
+    dx = qx[dd];
+    dy = qy[dd];
+}
+
 // f(t) and f'(t)
 __host__ __device__ __forceinline__ void eval_curve_d(const CurveDev &c, double t, double &x, double &y, double &dx,
                                                       double &dy)
@@ -120,6 +198,9 @@ __host__ __device__ __forceinline__ void eval_curve_d(const CurveDev &c, double 
         y = r * sn;
         dx = 6.283185307179586476925286766559 * (dr * cs - r * sn);
         dy = 6.283185307179586476925286766559 * (dr * sn + r * cs);
+    } else if ((c.kind == 2 || c.nonuniform) && (c.degree == 2 || c.degree == 3)) {   // the workloads' arcs and graded curves
+        if (c.degree == 2) eval_knots_d<2>(c, cq, t, x, y, dx, dy);
+        else eval_knots_d<3>(c, cq, t, x, y, dx, dy);
     } else if (c.kind == 2 || c.nonuniform) {
         const int d = c.degree, nc = c.n_ctrl;
         const double *tk = c.inline_data ? c.inl + 128 : c.knots;
