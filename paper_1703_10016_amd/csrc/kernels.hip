@@ -31,7 +31,7 @@ __global__ void geometry_kernel(CurveDev c, GridDesc g, double *X, double *Y, do
 
 hipError_t launch_geometry(const CurveDev &c, const GridDesc &g, double *X, double *Y, double *J, hipStream_t s)
 {
-    const int bs = 256;
+    const int bs = 64;   // small launches (2048 points at N = 1024): more workgroups, faster ramp (1 % of the step)
     hipLaunchKernelGGL(geometry_kernel, dim3((g.npts + bs - 1) / bs), dim3(bs), 0, s, c, g, X, Y, J);
     return hipGetLastError();
 }
